@@ -1,0 +1,307 @@
+"""Checks that tie the FP64 oracle to facts fixed by the paper and by
+mathematics (not to the oracle itself).  Each check raises AssertionError.
+The planted-mistake test runs them against deliberately broken copies of
+the oracle and expects at least one to fail."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import scipy.sparse as sp
+
+import oracle
+from synth.partition import molecule_partition, uneven_spatial_partition
+from synth.water import make_water
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+_cache: dict = {}
+
+
+def water(n_mol, seed=0, **kw):
+    key = (n_mol, seed, tuple(sorted(kw.items())))
+    if key not in _cache:
+        _cache[key] = make_water(n_mol, seed, **kw)
+    return _cache[key]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+# -- Gershgorin (Methods, SP2: bounds from the circle theorem) ---------------
+
+def check_gershgorin_textbook():
+    # discrete 1-D Laplacian tridiag(-1, 2, -1): discs centred at 2 with
+    # radius 2 inside and 1 at the two ends, so the bounds are [0, 4]; its
+    # eigenvalues 2 - 2 cos(k pi / (n + 1)) lie strictly inside.
+    n = 12
+    L = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    lo, hi = oracle.gershgorin_bounds(L)
+    assert (lo, hi) == (0.0, 4.0), (lo, hi)
+    lam = 2 - 2 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    assert lo < lam.min() and lam.max() < hi
+    # a diagonal matrix has zero radii: the bounds are its extreme entries
+    d = np.array([3.5, -7.25, 0.0, 11.0])
+    assert oracle.gershgorin_bounds(np.diag(d)) == (-7.25, 11.0)
+    # sparse and dense inputs agree, signs of off-diagonals do not matter
+    A = np.array([[1.0, -2.0, 0.5], [-2.0, -3.0, 1.0], [0.5, 1.0, 4.0]])
+    assert oracle.gershgorin_bounds(A) == (-6.0, 5.5)
+    assert oracle.gershgorin_bounds(sp.csr_matrix(A)) == (-6.0, 5.5)
+
+
+def check_gershgorin_contains(H):
+    lo, hi = oracle.gershgorin_bounds(H)
+    w = np.linalg.eigvalsh(H.toarray() if sp.issparse(H) else H)
+    assert lo <= w[0] + 1e-12 and w[-1] <= hi + 1e-12, (lo, hi, w[0], w[-1])
+
+
+# -- eq. (1): X0 maps the spectrum into [0, 1] in reverse order ---------------
+
+def check_initial_guess(H):
+    Hd = H.toarray()
+    lo, hi = oracle.gershgorin_bounds(Hd)
+    X0 = oracle.initial_guess(Hd, lo, hi)
+    w, V = np.linalg.eigh(Hd)
+    x = np.diag(V.T @ X0 @ V)
+    assert np.all(x >= -1e-12) and np.all(x <= 1 + 1e-12)
+    # the lowest eigenvalue of H becomes the largest of X0, and vice versa
+    assert np.allclose(x, (hi - w) / (hi - lo), atol=1e-12)
+    assert np.all(np.diff(x) <= 1e-12)
+
+
+# -- the limit of eq. (3) is the projector on the occupied states ------------
+
+def check_dense_projector(sys_, tol=1e-12):
+    P, res = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    assert res.converged, res.status
+    Ps = oracle.eig_projector(sys_.H, sys_.n_occ)
+    Hd = sys_.H.toarray()
+    assert rel(P, Ps) <= tol, rel(P, Ps)
+    assert np.linalg.norm(P @ P - P) / np.linalg.norm(P) <= tol
+    assert abs(np.trace(P) - sys_.n_occ) <= 1e-9 * sys_.n
+    assert np.linalg.norm(Hd @ P - P @ Hd) / np.linalg.norm(Hd) <= tol
+    # a few dozen products, as the paper reports
+    assert 15 <= res.n_products <= 60
+    return P, res
+
+
+def check_iterates_are_polynomials(sys_):
+    """Every iterate X_t equals the branch maps applied to the eigenvalues of
+    X0 (functional calculus); checks every step, not only the limit."""
+    Hd = sys_.H.toarray()
+    lo, hi = oracle.gershgorin_bounds(Hd)
+    X0 = oracle.initial_guess(Hd, lo, hi)
+    w, V = np.linalg.eigh(Hd)
+    _, res = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    for t in range(len(res.alphas) + 1):
+        x = (hi - w) / (hi - lo)
+        for a in res.alphas[:t]:
+            x = (2 * x - x * x) if a > 0 else (x * x)
+        Xt = oracle.sp2_blocks([X0], [Hd.shape[0]], sys_.n_occ, alpha_seq=res.alphas[:t]).blocks[0]
+        D = V.T @ Xt @ V
+        assert np.linalg.norm(D - np.diag(np.diag(D))) <= 1e-10 * max(1.0, np.linalg.norm(D)), t
+        assert np.allclose(np.diag(D), x, atol=1e-9), t
+
+
+def check_branch_direction(sys_):
+    """The trace rule picks 2X - X^2 while the trace is at or below N_occ."""
+    _, res = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    for tr, a in zip(res.traces, res.alphas):
+        assert a == (1 if tr <= sys_.n_occ else -1)
+    # x -> 2x - x^2 raises and x -> x^2 lowers every eigenvalue in [0, 1], so
+    # the chosen branch moves the trace toward N_occ
+    for t, a in enumerate(res.alphas):
+        step = res.traces[t + 1] - res.traces[t]
+        assert (step >= -1e-9) if a > 0 else (step <= 1e-9), (t, a, step)
+
+
+def check_diagonal_step():
+    d = np.array([-3.0, 1.5, -8.0, 0.25, 4.0, -1.0, 2.0])
+    P, res = oracle.dense_sp2(np.diag(d), 3)
+    expect = np.zeros(7)
+    expect[np.argsort(d)[:3]] = 1.0
+    assert np.allclose(P, np.diag(expect), atol=1e-12)
+
+
+# -- A = 0 monomer: closed form ------------------------------------------------
+
+def monomer_eigenvalues():
+    """Monomer spectrum from the model, worked by hand: the two O p
+    combinations orthogonal to (1,1,1)/sqrt(3) stay at -10 eV and the
+    antisymmetric H combination stays at -5 eV; s, the symmetric p
+    combination and the symmetric H combination couple through -4 sqrt(2)
+    and -4 sqrt(6), giving the cubic
+        (l+20)(l+10)(l+5) - 96 (l+20) - 32 (l+10) = 0
+      = l^3 + 35 l^2 + 222 l - 1240 = 0 ."""
+    cubic = np.sort(np.roots([1.0, 35.0, 222.0, -1240.0]).real)
+    return np.sort(np.concatenate([cubic, [-10.0, -10.0, -5.0]]))
+
+
+def check_monomer():
+    s = water(8, seed=3, hop_a=0.0)
+    w = np.linalg.eigvalsh(s.H.toarray())
+    mono = monomer_eigenvalues()
+    assert np.allclose(w, np.repeat(mono, 8), atol=1e-10)
+    assert np.allclose(mono[[0, 1, 5]], [-23.010, -15.473, 3.483], atol=1e-3)
+    # one part per molecule: the halo is empty and G-SP2 is exact
+    Pprev = s.H  # block diagonal pattern, no intermolecular entries
+    part = molecule_partition(s)
+    g = oracle.gsp2(s.H, Pprev, 1e-5, part, s.n_mol, s.n_occ)
+    assert all(len(h) == 0 for h in g.halos)
+    assert rel(g.dense(), oracle.eig_projector(s.H, s.n_occ)) <= 1e-12
+
+
+# -- graph: Fig. 2 worked example, threshold rule, halo definition ------------
+
+def check_fig2():
+    with open(os.path.join(GOLDEN, "fig2_corehalo.json")) as f:
+        fx = json.load(f)
+    names = fx["vertices"]
+    ix = {v: i for i, v in enumerate(names)}
+    n = len(names)
+    Pp = np.eye(n)
+    for a, b in fx["edges"]:
+        Pp[ix[a], ix[b]] = Pp[ix[b], ix[a]] = 0.5
+    A = oracle.threshold_graph(sp.csr_matrix(Pp), 0.1)
+    for key in ("a", "b"):
+        case = fx["partitions"][key]
+        part = np.empty(n, dtype=np.int32)
+        for k, members in enumerate(case["parts"]):
+            part[[ix[v] for v in members]] = k
+        cores, halos = oracle.core_halo(A, part, len(case["parts"]))
+        for k in range(len(case["parts"])):
+            assert sorted(names[i] for i in halos[k]) == sorted(case["halos"][k])
+        sizes = [len(c) + len(h) for c, h in zip(cores, halos)]
+        assert sizes == case["sizes"]
+        assert oracle.ch_cost(sizes) == case["cost"]
+        cut = sum(1 for a, b in fx["edges"] if part[ix[a]] != part[ix[b]])
+        assert cut == case["edge_cut"]
+
+
+def check_threshold_rule():
+    tau = 0.25
+    P = np.array([[9.0, 0.25, 0.0, -0.3],
+                  [0.25, 9.0, 0.2500001, 0.0],
+                  [0.0, 0.1, 9.0, 0.0],
+                  [-0.3, 0.0, 0.0, 9.0]])
+    A = oracle.threshold_graph(sp.csr_matrix(P), tau).toarray()
+    expect = np.zeros((4, 4), dtype=np.int8)
+    # |0.25| is not > 0.25; |-0.3| is; 0.2500001 above (1,2) only, union makes it symmetric
+    for u, v in ((0, 3), (1, 2)):
+        expect[u, v] = expect[v, u] = 1
+    assert (A == expect).all(), A
+
+
+def check_halo_brute_force(seed=0):
+    rng = np.random.default_rng(seed)
+    n, k = 40, 5
+    M = (rng.random((n, n)) < 0.08).astype(float)
+    M = np.maximum(M, M.T)
+    np.fill_diagonal(M, 1.0)
+    part = rng.integers(0, k, n).astype(np.int32)
+    part[:k] = np.arange(k)
+    A = oracle.threshold_graph(sp.csr_matrix(M), 0.5)
+    cores, halos = oracle.core_halo(A, part, k)
+    for p in range(k):
+        core = [v for v in range(n) if part[v] == p]
+        halo = sorted({u for v in core for u in range(n) if u != v and M[v, u] > 0.5 and part[u] != p})
+        assert list(cores[p]) == core
+        assert list(halos[p]) == halo
+
+
+# -- G-SP2 special cases -------------------------------------------------------
+
+def check_gsp2_one_part_is_dense(sys_):
+    P, res = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    part = np.zeros(sys_.n, dtype=np.int32)
+    g = oracle.gsp2(sys_.H, P, 1e-5, part, 1, sys_.n_occ)
+    assert g.sp2.alphas == res.alphas
+    # equal up to the summation order of the sparse vs dense Gershgorin row sums
+    assert rel(g.dense(), P) <= 1e-13
+
+
+def check_gsp2_full_halo_is_dense(sys_):
+    P, res = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    part = uneven_spatial_partition(sys_, 4, seed=1)
+    full = np.ones((sys_.n, sys_.n))
+    g = oracle.gsp2(sys_.H, sp.csr_matrix(full), 0.5, part, 4, sys_.n_occ)
+    assert all(s == sys_.n for s in g.sizes)
+    assert rel(g.dense(), P) <= 1e-12
+
+
+def check_gsp2_truncation(sys_, n_parts=8):
+    P, _ = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    Ps = oracle.eig_projector(sys_.H, sys_.n_occ)
+    part = uneven_spatial_partition(sys_, n_parts, seed=0)
+    out = {}
+    for tau in (1e-5, 1e-2):
+        g = oracle.gsp2(sys_.H, P, tau, part, n_parts, sys_.n_occ)
+        assert g.sp2.converged
+        err = rel(g.dense(), Ps)
+        assert err <= 10 * tau, (tau, err)
+        out[tau] = (err, g)
+    # a real truncation at 1e-2: smaller blocks, non-zero error
+    g2 = out[1e-2][1]
+    assert max(g2.sizes) < sys_.n and out[1e-2][0] > 1e-4
+    return out
+
+
+def check_gsp2_blocks_share_sequence(sys_, tau=1e-2, n_parts=8):
+    """With truncated halos, each part's final block is still the common
+    branch polynomial of its own X0 (one global sequence for every part)."""
+    P, _ = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    part = uneven_spatial_partition(sys_, n_parts, seed=0)
+    g = oracle.gsp2(sys_.H, P, tau, part, n_parts, sys_.n_occ)
+    lo, hi = g.eps
+    kept = g.sp2.alphas
+    for k in (0, n_parts - 1):
+        idx = g.index[k]
+        X0 = oracle.initial_guess(sys_.H[idx][:, idx].toarray(), lo, hi)
+        w, V = np.linalg.eigh(X0)
+        x = w.copy()
+        for a in kept:
+            x = (2 * x - x * x) if a > 0 else (x * x)
+        Xk = (V * x) @ V.T
+        c = len(g.cores[k])
+        assert np.allclose(Xk[:, :c], g.core_columns[k], atol=1e-9)
+
+
+def check_core_column_layout(sys_, tau=1e-2, n_parts=8):
+    """Part k writes P's core columns: column j of part k is non-zero only in
+    part k's rows (core + halo)."""
+    P, _ = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    part = uneven_spatial_partition(sys_, n_parts, seed=0)
+    g = oracle.gsp2(sys_.H, P, tau, part, n_parts, sys_.n_occ)
+    D = g.dense()
+    for k in range(n_parts):
+        outside = np.setdiff1d(np.arange(sys_.n), g.index[k])
+        assert np.abs(D[np.ix_(outside, g.cores[k])]).max(initial=0.0) == 0.0
+        assert np.array_equal(D[np.ix_(g.index[k], g.cores[k])], g.core_columns[k])
+
+
+def battery():
+    """Every pin, on small systems; raises on the first failure."""
+    check_gershgorin_textbook()
+    for seed in (0, 1):
+        check_gershgorin_contains(water(64, seed).H)
+    check_initial_guess(water(16, 0).H)
+    check_dense_projector(water(64, 0))
+    check_iterates_are_polynomials(water(16, 1))
+    check_branch_direction(water(64, 0))
+    check_diagonal_step()
+    check_monomer()
+    check_fig2()
+    check_threshold_rule()
+    for seed in range(4):
+        check_halo_brute_force(seed)
+    check_gsp2_one_part_is_dense(water(32, 0))
+    check_gsp2_full_halo_is_dense(water(24, 2))
+    check_gsp2_truncation(water(64, 0))
+    check_gsp2_blocks_share_sequence(water(64, 0))
+    check_core_column_layout(water(64, 0))
+
+
+if __name__ == "__main__":
+    battery()
