@@ -16,9 +16,11 @@ notes):
   of each part's *core* rows (every vertex is core in exactly one part).
   Dense SP2 is the single-part case, where it is the ordinary trace.
 * Stopping.  e_t = Tr[X_t] - Tr[X_t^2] measures idempotency of the iterate
-  that is being squared.  Stop at the first product t >= 2 with
-  e_t >= e_{t-2} and e_{t-2} < 1 (the error has stopped falling), and
-  return X_t (the square just formed is discarded).  At most ``max_iter``
+  that is being squared; the error bound applies to its magnitude, since in
+  finite precision e_t turns negative once X_t is idempotent to rounding.
+  Stop at the first product t >= 2 with |e_t| >= |e_{t-2}| and
+  |e_{t-2}| < 1 (the error has stopped falling), and return X_t (the square
+  just formed is discarded).  At most ``max_iter``
   products; if the rule never fires the result is the last iterate and the
   run is "not converged".
 * Replay.  With a stored branch sequence, exactly that many products are
@@ -99,7 +101,8 @@ def sp2_blocks(X0: list, cores: list, n_occ: float, max_iter: int = 60,
         Y = [x @ x for x in X]                 # the product of eq. (2)
         trY = _core_trace(Y, cores)
         errors.append(tr - trY)
-        if not replay and stop_rule and t >= 2 and errors[t] >= errors[t - 2] and errors[t - 2] < 1.0:
+        if (not replay and stop_rule and t >= 2 and abs(errors[t]) >= abs(errors[t - 2])
+                and abs(errors[t - 2]) < 1.0):
             return SP2Result(X, t + 1, alphas, traces, errors, True)
         if replay:
             alpha = int(alpha_seq[t])
