@@ -1,0 +1,218 @@
+/*
+ * gsp2.h - graph-partitioned SP2 (G-SP2) density matrices on AMD Instinct
+ * MI355X (gfx950).  C ABI of libgsp2.so.
+ *
+ * Method: Ghale et al., "Task-based Parallel Computation of the Density
+ * Matrix in Quantum-based Molecular Dynamics using Graph Partitioning",
+ * arXiv:1801.10016.  A previous density matrix P_prev is thresholded into an
+ * undirected graph G_tau (Methods, "Graph Theory"); a given partition of its
+ * vertices defines, for every part, a core (the part's vertices) and a halo
+ * (vertices outside the part adjacent to a core vertex); each part's dense
+ * core+halo sub-block of H is purified by SP2 (Methods, eqs. (1)-(3)) with a
+ * branch sequence common to all parts, chosen from the summed core trace;
+ * each part's core columns are reassembled into the sparse P (Fig. 1
+ * description in the Introduction).
+ *
+ * Conventions for every call:
+ *  - Every function returns gsp2_status; nothing throws or aborts across
+ *    the ABI.  On failure gsp2_last_error() gives a thread-local message.
+ *  - "device" pointers are HIP device memory on the current device; "host"
+ *    pointers are ordinary host memory.  The caller owns every buffer it
+ *    passes; the library owns the plan and its device workspace.
+ *  - Indices are 0-based.  CSR arrays: row_ptr has n+1 int64 entries,
+ *    col has nnz int32 entries, val has nnz entries of type `dtype`.
+ *    Column indices of a row need not be sorted; duplicates are not allowed.
+ *  - Work is enqueued on the plan's HIP stream (set at creation, changed
+ *    with gsp2_plan_set_stream) in stream order.
+ */
+#ifndef GSP2_H
+#define GSP2_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GSP2_OK = 0,
+    GSP2_E_INVALID = 1,        /* bad argument, size mismatch, empty part, non-finite H */
+    GSP2_E_HIP = 2,            /* a HIP runtime call failed */
+    GSP2_E_OOM = 3,            /* device or host allocation failed */
+    GSP2_E_NOT_CONVERGED = 4,  /* the stop rule did not fire within max_iter products,
+                                  or the iteration left the finite range */
+    GSP2_E_WRONG_TRACE = 5,    /* a replayed branch sequence ended with the wrong trace */
+    GSP2_E_UNSUPPORTED = 6     /* option not available in this build */
+} gsp2_status;
+
+typedef enum { GSP2_F32 = 0, GSP2_F64 = 1 } gsp2_dtype;
+
+typedef enum {
+    GSP2_ALPHA_TRACE = 0,      /* branch from the summed core trace each product */
+    GSP2_ALPHA_REPLAY = 1      /* branch sequence supplied by the caller */
+} gsp2_alpha_mode;
+
+/* Sparse matrix in CSR form.  All four arrays are device pointers. */
+typedef struct {
+    int32_t n;                 /* rows = columns */
+    int64_t nnz;
+    const int64_t *row_ptr;    /* device, n+1 */
+    const int32_t *col;        /* device, nnz */
+    const void *val;           /* device, nnz, gsp2_dtype `dtype` */
+    int32_t dtype;             /* GSP2_F32 or GSP2_F64 */
+} gsp2_csr;
+
+typedef struct gsp2_plan_s *gsp2_plan;   /* opaque, library-owned */
+
+/* Plan options.  Zero-initialised means defaults. */
+typedef struct {
+    int32_t tile;              /* macro-tile edge of the SP2 product: 0 = automatic, or 128 */
+    int32_t reserved[7];
+} gsp2_plan_options;
+
+/* Summary of a plan, filled by gsp2_plan_query. */
+typedef struct {
+    int32_t n;                 /* vertices (rows of H and P) */
+    int32_t n_parts;
+    int32_t max_s;             /* largest sub-problem s_k = c_k + h_k */
+    int32_t min_s;
+    int64_t nnz_graph;         /* off-diagonal entries of P_prev with |value| > tau */
+    int64_t nnz_P;             /* stored entries of P: sum_k c_k s_k */
+    int64_t sum_s;             /* sum_k s_k */
+    double sum_s3;             /* eq. (4): C = sum_k s_k^3 */
+    int32_t tile;              /* macro-tile edge in use */
+    int32_t n_tiles;           /* product tiles per SP2 iteration (upper triangles) */
+    int64_t workspace_bytes;   /* device memory held by the plan */
+    double plan_ms;            /* host wall time of gsp2_plan_create */
+} gsp2_plan_info;
+
+/* Options of one density-matrix computation.  Fill with
+ * gsp2_run_options_default() and change what is needed. */
+typedef struct {
+    int32_t max_iter;          /* most matrix products per P (1..GSP2_MAX_ITER), default 60 */
+    int32_t alpha_mode;        /* gsp2_alpha_mode, default GSP2_ALPHA_TRACE */
+    const int8_t *alpha_seq;   /* host, replay mode only: n_alpha entries, each +1 or -1 */
+    int32_t n_alpha;           /* replay mode: number of products to apply (<= GSP2_MAX_ITER) */
+    int32_t stop_rule;         /* trace mode: 1 = stop when idempotency stops improving
+                                  (default); 0 = always form max_iter products */
+    double trace_tol;          /* replay mode: allowed |Tr P - n_occ|, default 0.5 */
+} gsp2_run_options;
+
+#define GSP2_MAX_ITER 100
+
+/* Outcome of one density-matrix computation (filled when info != NULL). */
+typedef struct {
+    int32_t status;            /* gsp2_status of the run */
+    int32_t n_products;        /* products formed, including a discarded last one */
+    int32_t n_alpha;           /* branches applied to reach the returned P */
+    int32_t result_iterate;    /* index t of the returned iterate X_t */
+    double eps_min, eps_max;   /* Gershgorin bounds of H */
+    double trace;              /* summed core trace of the returned P */
+    double idempotency;        /* e_t = Tr[X_t] - Tr[X_t^2] of the returned iterate (NaN if not formed) */
+    int8_t alpha[GSP2_MAX_ITER];           /* applied branches, +1 = 2X - X^2, -1 = X^2 */
+    double traces[GSP2_MAX_ITER + 1];      /* Tr[X_t], t = 0 .. n_alpha */
+    double errors[GSP2_MAX_ITER];          /* e_t for each product t */
+} gsp2_run_info;
+
+/* Human-readable name of a status code (static string). */
+const char *gsp2_status_string(gsp2_status s);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *gsp2_last_error(void);
+
+/* Fill *opt with the defaults listed in gsp2_run_options. */
+gsp2_status gsp2_run_options_default(gsp2_run_options *opt);
+
+/*
+ * Build a plan: threshold P_prev into G_tau on the GPU (an edge u-v, u != v,
+ * when |P_prev[u,v]| > tau or |P_prev[v,u]| > tau, compared in double
+ * precision; Methods, "Graph Theory"), derive every part's core and
+ * one-hop halo (core vertices ascending, then halo vertices ascending),
+ * allocate the device workspace and upload the index lists.
+ *
+ *  P_prev  device CSR, n x n (a previous density matrix, or any matrix whose
+ *          pattern and magnitudes define the graph).
+ *  tau     threshold, >= 0.
+ *  part    host, n int32 part ids in [0, n_parts); every part non-empty.
+ *  n_parts >= 1.
+ *  opt     nullable.
+ *  stream  hipStream_t to use (NULL = default stream).
+ *  out     receives the plan; NULL on failure.
+ * Blocks the calling thread until the graph has been built.
+ * Errors: GSP2_E_INVALID (sizes, ids, empty part), GSP2_E_OOM, GSP2_E_HIP.
+ */
+gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *part,
+                             int32_t n_parts, const gsp2_plan_options *opt, void *stream,
+                             gsp2_plan *out);
+
+/* Plan summary; sub_sizes and core_sizes (host, n_parts int32 each) are
+ * nullable and receive s_k and c_k.  Errors: GSP2_E_INVALID. */
+gsp2_status gsp2_plan_query(gsp2_plan plan, gsp2_plan_info *info, int32_t *core_sizes,
+                            int32_t *sub_sizes);
+
+/* CSC pattern of P: column j (in part k) holds the rows of part k's core and
+ * halo, in ascending order.  col_ptr: host, n+1 int64; row_idx: host,
+ * nnz_P int32.  Errors: GSP2_E_INVALID. */
+gsp2_status gsp2_plan_pattern(gsp2_plan plan, int64_t *col_ptr, int32_t *row_idx);
+
+/* Global vertex ids of part k's sub-problem in local order (core ascending,
+ * then halo ascending).  idx: host, s_k int32.  Errors: GSP2_E_INVALID. */
+gsp2_status gsp2_plan_part_index(gsp2_plan plan, int32_t k, int32_t *idx);
+
+/* Use another HIP stream for later calls on this plan. */
+gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
+
+/*
+ * One density matrix P from H:
+ *   eps_min, eps_max from the Gershgorin discs of the whole H (Methods, SP2);
+ *   X0_k = (eps_max I - H[idx_k, idx_k]) / (eps_max - eps_min)    (eq. (1));
+ *   then, for t = 0, 1, ...: Y_k = X_k X_k on every part (eq. (2)),
+ *   e_t = Tr[X_t] - Tr[Y_t]; stop (trace mode, stop_rule = 1) at the first
+ *   t >= 2 with |e_t| >= |e_{t-2}| and |e_{t-2}| < 1, returning X_t; otherwise
+ *   X_k <- 2 X_k - Y_k when Tr[X_t] <= n_occ, else X_k <- Y_k (replay mode:
+ *   the supplied branches, then the trace check).  Tr is the sum over parts
+ *   of the diagonal of each part's core rows.  P[idx_k, j] = X_k[:, j]
+ *   for each core column j of part k; other entries are not stored.
+ * Arithmetic: FP32 products on the matrix cores with FP32 accumulation,
+ * Gershgorin bounds, X0 and all traces in FP64.
+ *
+ *  H       device CSR, n x n, symmetric; its pattern may change between calls.
+ *  n_occ   number of occupied states N_el / 2, 0 <= n_occ <= n.
+ *  run     nullable (defaults).
+ *  P_val   device, nnz_P floats in the order of gsp2_plan_pattern; caller-owned.
+ *  info    nullable.  When given, the call waits for the result and returns
+ *          the run's status; otherwise it returns after enqueueing.
+ * Errors: GSP2_E_INVALID (arguments, non-finite H, eps_max <= eps_min),
+ * GSP2_E_NOT_CONVERGED, GSP2_E_WRONG_TRACE, GSP2_E_HIP.  On error the
+ * contents of P_val are unspecified.
+ */
+gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ,
+                         const gsp2_run_options *run, float *P_val, gsp2_run_info *info);
+
+/* Wait for the last gsp2_density on this plan and report it. */
+gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info);
+
+/* Release the plan and its device memory (waits for its stream).  NULL is a no-op. */
+void gsp2_plan_destroy(gsp2_plan plan);
+
+/*
+ * Host-only planning step (no GPU needed): core and one-hop halo of every
+ * part of an undirected graph given by a directed adjacency (the union of
+ * both orientations is used; self loops are ignored).
+ *  adj_ptr, adj_col  host CSR of the adjacency, n+1 / adj_ptr[n] entries.
+ *  part              host, n int32 ids in [0, n_parts).
+ *  sub_ptr           host, n_parts+1 int64 (out): offsets into sub_idx.
+ *  sub_idx           host, sub_ptr[n_parts] int32 (out), nullable: pass NULL
+ *                    first to size it, then call again.
+ *  core_count        host, n_parts int32 (out), nullable.
+ * Errors: GSP2_E_INVALID.
+ */
+gsp2_status gsp2_core_halo_host(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col,
+                                const int32_t *part, int32_t n_parts, int64_t *sub_ptr,
+                                int32_t *sub_idx, int32_t *core_count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSP2_H */

@@ -1,0 +1,609 @@
+// C ABI of libgsp2.so: plan construction (graph threshold on the GPU, host
+// core/halo planning, device workspace) and density-matrix runs captured
+// once into a HIP graph and replayed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "gsp2.h"
+#include "gsp2_internal.hpp"
+
+using namespace gsp2;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct Failure {
+    gsp2_status status;
+    std::string msg;
+};
+
+[[noreturn]] void fail(gsp2_status s, const std::string &m) { throw Failure{s, m}; }
+
+void check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(GSP2_E_OOM, std::string(what) + ": out of device memory");
+    fail(GSP2_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename F>
+gsp2_status guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        f();
+        return GSP2_OK;
+    } catch (const Failure &x) {
+        g_last_error = x.msg;
+        return x.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return GSP2_E_OOM;
+    } catch (const std::exception &x) {
+        g_last_error = x.what();
+        return GSP2_E_INVALID;
+    } catch (...) {
+        g_last_error = "unknown failure";
+        return GSP2_E_INVALID;
+    }
+}
+
+template <typename T>
+T *dev_alloc(size_t count, const char *what, int64_t &total) {
+    if (count == 0) count = 1;
+    void *p = nullptr;
+    check_hip(hipMalloc(&p, count * sizeof(T)), what);
+    total += (int64_t)(count * sizeof(T));
+    return static_cast<T *>(p);
+}
+
+template <typename T>
+void upload(T *dst, const std::vector<T> &src, hipStream_t s, const char *what) {
+    if (src.empty()) return;
+    check_hip(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s), what);
+}
+
+// Core and one-hop halo of every part (host).  adj: directed CSR; the union
+// of both orientations is the undirected graph; self loops ignored.
+void plan_core_halo(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, const int32_t *part,
+                    int32_t n_parts, std::vector<int64_t> &sub_ptr, std::vector<int32_t> &sub_idx,
+                    std::vector<int32_t> &core_count) {
+    if (n < 1) fail(GSP2_E_INVALID, "n must be >= 1");
+    if (n_parts < 1) fail(GSP2_E_INVALID, "n_parts must be >= 1");
+    if (!adj_ptr || !part) fail(GSP2_E_INVALID, "null pointer");
+    const int64_t nnz = adj_ptr[n];
+    if (adj_ptr[0] != 0 || nnz < 0) fail(GSP2_E_INVALID, "bad adjacency row pointer");
+    if (nnz > 0 && !adj_col) fail(GSP2_E_INVALID, "null adjacency columns");
+    for (int32_t v = 0; v < n; ++v)
+        if (adj_ptr[v + 1] < adj_ptr[v]) fail(GSP2_E_INVALID, "adjacency row pointer not monotone");
+    for (int64_t e = 0; e < nnz; ++e)
+        if (adj_col[e] < 0 || adj_col[e] >= n) fail(GSP2_E_INVALID, "adjacency column out of range");
+    core_count.assign(n_parts, 0);
+    for (int32_t v = 0; v < n; ++v) {
+        if (part[v] < 0 || part[v] >= n_parts)
+            fail(GSP2_E_INVALID, "part id out of range at vertex " + std::to_string(v));
+        core_count[part[v]]++;
+    }
+    for (int32_t k = 0; k < n_parts; ++k)
+        if (core_count[k] == 0) fail(GSP2_E_INVALID, "part " + std::to_string(k) + " is empty");
+    // cores, ascending
+    std::vector<int64_t> core_ptr(n_parts + 1, 0);
+    for (int32_t k = 0; k < n_parts; ++k) core_ptr[k + 1] = core_ptr[k] + core_count[k];
+    std::vector<int32_t> core_list(n);
+    {
+        std::vector<int64_t> fill(core_ptr.begin(), core_ptr.end() - 1);
+        for (int32_t v = 0; v < n; ++v) core_list[fill[part[v]]++] = v;
+    }
+    // transpose, for in-neighbours
+    std::vector<int64_t> tr_ptr(n + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) tr_ptr[adj_col[e] + 1]++;
+    for (int32_t v = 0; v < n; ++v) tr_ptr[v + 1] += tr_ptr[v];
+    std::vector<int32_t> tr_col(nnz);
+    {
+        std::vector<int64_t> fill(tr_ptr.begin(), tr_ptr.end() - 1);
+        for (int32_t u = 0; u < n; ++u)
+            for (int64_t e = adj_ptr[u]; e < adj_ptr[u + 1]; ++e) tr_col[fill[adj_col[e]]++] = u;
+    }
+    std::vector<int32_t> stamp(n, -1);
+    std::vector<int32_t> halo;
+    sub_ptr.assign(n_parts + 1, 0);
+    sub_idx.clear();
+    sub_idx.reserve(n);
+    for (int32_t k = 0; k < n_parts; ++k) {
+        const int32_t *core = core_list.data() + core_ptr[k];
+        const int32_t c = core_count[k];
+        for (int32_t i = 0; i < c; ++i) stamp[core[i]] = k;
+        halo.clear();
+        for (int32_t i = 0; i < c; ++i) {
+            const int32_t u = core[i];
+            for (int64_t e = adj_ptr[u]; e < adj_ptr[u + 1]; ++e) {
+                const int32_t w = adj_col[e];
+                if (stamp[w] != k) { stamp[w] = k; halo.push_back(w); }
+            }
+            for (int64_t e = tr_ptr[u]; e < tr_ptr[u + 1]; ++e) {
+                const int32_t w = tr_col[e];
+                if (stamp[w] != k) { stamp[w] = k; halo.push_back(w); }
+            }
+        }
+        std::sort(halo.begin(), halo.end());
+        sub_idx.insert(sub_idx.end(), core, core + c);
+        sub_idx.insert(sub_idx.end(), halo.begin(), halo.end());
+        sub_ptr[k + 1] = (int64_t)sub_idx.size();
+    }
+}
+
+struct GraphKey {
+    const void *h_ptr = nullptr, *h_col = nullptr, *h_val = nullptr;
+    int64_t h_nnz = -1;
+    int32_t h_dtype = -1;
+    float *p_val = nullptr;
+    RunParams rp{};
+    bool operator==(const GraphKey &o) const {
+        return h_ptr == o.h_ptr && h_col == o.h_col && h_val == o.h_val && h_nnz == o.h_nnz &&
+               h_dtype == o.h_dtype && p_val == o.p_val && std::memcmp(&rp, &o.rp, sizeof(rp)) == 0;
+    }
+};
+
+}  // namespace
+
+struct gsp2_plan_s {
+    int32_t n = 0, n_parts = 0, tile = kTile;
+    hipStream_t stream = nullptr;
+    int64_t nnz_graph = 0;
+    double plan_ms = 0.0;
+    std::vector<int32_t> part;
+    std::vector<int64_t> sub_ptr;
+    std::vector<int32_t> sub_idx, core_count;
+    std::vector<PartDesc> desc;
+    std::vector<TileDesc> tiles;
+    std::vector<RowChunk> chunks;
+    std::vector<int32_t> perm;
+    std::vector<int64_t> col_ptr;
+    std::vector<int32_t> col_part, col_local;
+    int32_t n_diag = 0;
+    int64_t arena_floats = 0;
+    int64_t workspace_bytes = 0;
+    DevicePlan dp{};
+    std::vector<void *> dev_ptrs;
+    RunState *h_state = nullptr;      // pinned copy for run_info
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    GraphKey key;
+    bool have_graph = false;
+    RunParams last_rp{};
+    bool ran = false;
+
+    ~gsp2_plan_s() {
+        if (stream) (void)hipStreamSynchronize(stream); else (void)hipDeviceSynchronize();
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (void *p : dev_ptrs) (void)hipFree(p);
+        if (h_state) (void)hipHostFree(h_state);
+    }
+    template <typename T>
+    T *alloc(size_t count, const char *what) {
+        T *p = dev_alloc<T>(count, what, workspace_bytes);
+        dev_ptrs.push_back(p);
+        return p;
+    }
+};
+
+extern "C" {
+
+const char *gsp2_status_string(gsp2_status s) {
+    switch (s) {
+        case GSP2_OK: return "GSP2_OK";
+        case GSP2_E_INVALID: return "GSP2_E_INVALID";
+        case GSP2_E_HIP: return "GSP2_E_HIP";
+        case GSP2_E_OOM: return "GSP2_E_OOM";
+        case GSP2_E_NOT_CONVERGED: return "GSP2_E_NOT_CONVERGED";
+        case GSP2_E_WRONG_TRACE: return "GSP2_E_WRONG_TRACE";
+        case GSP2_E_UNSUPPORTED: return "GSP2_E_UNSUPPORTED";
+    }
+    return "GSP2_UNKNOWN";
+}
+
+const char *gsp2_last_error(void) { return g_last_error.c_str(); }
+
+gsp2_status gsp2_run_options_default(gsp2_run_options *opt) {
+    return guarded([&] {
+        if (!opt) fail(GSP2_E_INVALID, "null options");
+        opt->max_iter = 60;
+        opt->alpha_mode = GSP2_ALPHA_TRACE;
+        opt->alpha_seq = nullptr;
+        opt->n_alpha = 0;
+        opt->stop_rule = 1;
+        opt->trace_tol = 0.5;
+    });
+}
+
+gsp2_status gsp2_core_halo_host(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, const int32_t *part,
+                                int32_t n_parts, int64_t *sub_ptr, int32_t *sub_idx, int32_t *core_count) {
+    return guarded([&] {
+        if (!sub_ptr) fail(GSP2_E_INVALID, "null sub_ptr");
+        std::vector<int64_t> sp;
+        std::vector<int32_t> si, cc;
+        plan_core_halo(n, adj_ptr, adj_col, part, n_parts, sp, si, cc);
+        std::copy(sp.begin(), sp.end(), sub_ptr);
+        if (sub_idx) std::copy(si.begin(), si.end(), sub_idx);
+        if (core_count) std::copy(cc.begin(), cc.end(), core_count);
+    });
+}
+
+gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *part, int32_t n_parts,
+                             const gsp2_plan_options *opt, void *stream, gsp2_plan *out) {
+    if (out) *out = nullptr;
+    gsp2_plan_s *plan = nullptr;
+    const gsp2_status st = guarded([&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!out) fail(GSP2_E_INVALID, "null output handle");
+        if (!P_prev) fail(GSP2_E_INVALID, "null P_prev");
+        if (!part) fail(GSP2_E_INVALID, "null part");
+        if (P_prev->n < 1) fail(GSP2_E_INVALID, "P_prev.n must be >= 1");
+        if (P_prev->nnz < 0) fail(GSP2_E_INVALID, "P_prev.nnz must be >= 0");
+        if (!P_prev->row_ptr || (P_prev->nnz > 0 && (!P_prev->col || !P_prev->val)))
+            fail(GSP2_E_INVALID, "null P_prev array");
+        if (P_prev->dtype != GSP2_F32 && P_prev->dtype != GSP2_F64) fail(GSP2_E_INVALID, "bad P_prev.dtype");
+        if (!(tau >= 0.0) || !std::isfinite(tau)) fail(GSP2_E_INVALID, "tau must be finite and >= 0");
+        if (n_parts < 1 || n_parts > P_prev->n) fail(GSP2_E_INVALID, "need 1 <= n_parts <= n");
+        if (opt && opt->tile != 0 && opt->tile != kTile) fail(GSP2_E_UNSUPPORTED, "tile must be 0 or 128");
+        plan = new gsp2_plan_s();
+        plan->n = P_prev->n;
+        plan->n_parts = n_parts;
+        plan->stream = static_cast<hipStream_t>(stream);
+        hipStream_t s = plan->stream;
+        const int32_t n = plan->n;
+        plan->part.assign(part, part + n);
+
+        // a1: threshold on the GPU, then bring the directed adjacency home
+        int64_t tmp_bytes = 0;
+        int32_t *d_counts = dev_alloc<int32_t>(n, "threshold counts", tmp_bytes);
+        std::vector<int32_t> counts(n);
+        std::vector<int64_t> adj_ptr(n + 1, 0);
+        std::vector<int32_t> adj_col;
+        int64_t *d_adj_ptr = nullptr;
+        int32_t *d_adj_col = nullptr;
+        try {
+            if (P_prev->nnz > 0) {
+                check_hip(launch_threshold_count(*P_prev, tau, d_counts, s), "threshold count");
+                check_hip(hipMemcpyAsync(counts.data(), d_counts, n * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                          "copy counts");
+                check_hip(hipStreamSynchronize(s), "threshold count");
+            } else {
+                std::fill(counts.begin(), counts.end(), 0);
+            }
+            for (int32_t v = 0; v < n; ++v) adj_ptr[v + 1] = adj_ptr[v] + counts[v];
+            const int64_t nnz_adj = adj_ptr[n];
+            adj_col.resize(nnz_adj);
+            if (nnz_adj > 0) {
+                d_adj_ptr = dev_alloc<int64_t>(n + 1, "adjacency", tmp_bytes);
+                d_adj_col = dev_alloc<int32_t>(nnz_adj, "adjacency", tmp_bytes);
+                check_hip(hipMemcpyAsync(d_adj_ptr, adj_ptr.data(), (n + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s),
+                          "upload adjacency pointer");
+                check_hip(launch_threshold_fill(*P_prev, tau, d_adj_ptr, d_adj_col, s), "threshold fill");
+                check_hip(hipMemcpyAsync(adj_col.data(), d_adj_col, nnz_adj * sizeof(int32_t), hipMemcpyDeviceToHost, s),
+                          "copy adjacency");
+                check_hip(hipStreamSynchronize(s), "threshold fill");
+            }
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(d_counts); (void)hipFree(d_adj_ptr); (void)hipFree(d_adj_col);
+            throw;
+        }
+        (void)hipFree(d_counts); (void)hipFree(d_adj_ptr); (void)hipFree(d_adj_col);
+
+        // a3: cores and halos (host)
+        plan_core_halo(n, adj_ptr.data(), adj_col.data(), part, n_parts, plan->sub_ptr, plan->sub_idx,
+                       plan->core_count);
+        plan->nnz_graph = (int64_t)adj_col.size();
+        std::vector<int64_t>().swap(adj_ptr);
+        std::vector<int32_t>().swap(adj_col);
+
+        // descriptors, LPT tile list, gather chunks, P pattern
+        const int T = kTile;
+        plan->desc.resize(n_parts);
+        int64_t xoff = 0;
+        int32_t max_s_pad = 0;
+        for (int32_t k = 0; k < n_parts; ++k) {
+            PartDesc d{};
+            d.s = (int32_t)(plan->sub_ptr[k + 1] - plan->sub_ptr[k]);
+            d.c = plan->core_count[k];
+            d.s_pad = ((d.s + T - 1) / T) * T;
+            d.idx_off = (int32_t)plan->sub_ptr[k];
+            d.perm_off = (int32_t)plan->sub_ptr[k];
+            d.x_off = xoff;
+            xoff += (int64_t)d.s_pad * d.s_pad;
+            max_s_pad = std::max(max_s_pad, d.s_pad);
+            plan->desc[k] = d;
+        }
+        plan->arena_floats = xoff;
+        std::vector<int32_t> order(n_parts);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return plan->desc[a].s_pad > plan->desc[b].s_pad; });
+        int32_t slot = 0;
+        for (int32_t k : order) {
+            const int nt = plan->desc[k].s_pad / T;
+            for (int ti = 0; ti < nt; ++ti)
+                for (int tj = ti; tj < nt; ++tj)
+                    plan->tiles.push_back(TileDesc{k, ti, tj, ti == tj ? slot++ : -1});
+        }
+        plan->n_diag = slot;
+        constexpr int kRowsPerChunk = 16;
+        for (int32_t k = 0; k < n_parts; ++k)
+            for (int r0 = 0; r0 < plan->desc[k].s_pad; r0 += kRowsPerChunk)
+                plan->chunks.push_back(RowChunk{k, r0, std::min(r0 + kRowsPerChunk, plan->desc[k].s_pad), 0});
+        plan->perm.resize(plan->sub_idx.size());
+        for (int32_t k = 0; k < n_parts; ++k) {
+            const int64_t b = plan->sub_ptr[k];
+            const int32_t s = plan->desc[k].s, c = plan->desc[k].c;
+            const int32_t *ix = plan->sub_idx.data() + b;
+            // merge the two ascending runs (core, halo) by global id
+            int32_t i = 0, j = c, t = 0;
+            while (i < c || j < s) {
+                if (j >= s || (i < c && ix[i] < ix[j])) plan->perm[b + t++] = i++;
+                else plan->perm[b + t++] = j++;
+            }
+        }
+        plan->col_ptr.assign(n + 1, 0);
+        plan->col_part.resize(n);
+        plan->col_local.resize(n);
+        {
+            std::vector<int32_t> seen(n_parts, 0);
+            for (int32_t j = 0; j < n; ++j) {
+                const int32_t k = part[j];
+                plan->col_part[j] = k;
+                plan->col_local[j] = seen[k]++;    // cores are ascending, so this is j's local index
+                plan->col_ptr[j + 1] = plan->col_ptr[j] + plan->desc[k].s;
+            }
+        }
+
+        // device workspace
+        DevicePlan &dp = plan->dp;
+        dp.n = n;
+        dp.n_parts = n_parts;
+        dp.n_tiles = (int32_t)plan->tiles.size();
+        dp.n_diag = plan->n_diag;
+        dp.n_chunks = (int32_t)plan->chunks.size();
+        dp.max_s_pad = max_s_pad;
+        dp.gersh_blocks = std::max(1, std::min(1024, (n + 3) / 4));
+        dp.buf[0] = plan->alloc<float>(plan->arena_floats, "X buffer 0");
+        dp.buf[1] = plan->alloc<float>(plan->arena_floats, "X buffer 1");
+        auto *d_parts = plan->alloc<PartDesc>(n_parts, "part descriptors");
+        auto *d_tiles = plan->alloc<TileDesc>(plan->tiles.size(), "tiles");
+        auto *d_chunks = plan->alloc<RowChunk>(plan->chunks.size(), "row chunks");
+        auto *d_idx = plan->alloc<int32_t>(plan->sub_idx.size(), "index arena");
+        auto *d_perm = plan->alloc<int32_t>(plan->perm.size(), "perm arena");
+        auto *d_colptr = plan->alloc<int64_t>(n + 1, "col_ptr");
+        auto *d_colpart = plan->alloc<int32_t>(n, "col_part");
+        auto *d_collocal = plan->alloc<int32_t>(n, "col_local");
+        dp.diag_partials = plan->alloc<double>(2 * (size_t)std::max(1, plan->n_diag), "diag partials");
+        dp.x0_partials = plan->alloc<double>(plan->chunks.size(), "x0 partials");
+        dp.gersh_partials = plan->alloc<double>(3 * (size_t)dp.gersh_blocks, "gershgorin partials");
+        dp.state = plan->alloc<RunState>(1, "run state");
+        upload(d_parts, plan->desc, s, "upload parts");
+        upload(d_tiles, plan->tiles, s, "upload tiles");
+        upload(d_chunks, plan->chunks, s, "upload chunks");
+        upload(d_idx, plan->sub_idx, s, "upload index");
+        upload(d_perm, plan->perm, s, "upload perm");
+        upload(d_colptr, plan->col_ptr, s, "upload col_ptr");
+        upload(d_colpart, plan->col_part, s, "upload col_part");
+        upload(d_collocal, plan->col_local, s, "upload col_local");
+        check_hip(hipMemsetAsync(dp.state, 0, sizeof(RunState), s), "clear state");
+        dp.parts = d_parts;
+        dp.tiles = d_tiles;
+        dp.chunks = d_chunks;
+        dp.idx = d_idx;
+        dp.perm = d_perm;
+        dp.col_ptr = d_colptr;
+        dp.col_part = d_colpart;
+        dp.col_local = d_collocal;
+        check_hip(hipHostMalloc((void **)&plan->h_state, sizeof(RunState), hipHostMallocDefault), "pinned state");
+        check_hip(hipStreamSynchronize(s), "plan upload");
+        plan->plan_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        *out = plan;
+    });
+    if (st != GSP2_OK) delete plan;
+    return st;
+}
+
+gsp2_status gsp2_plan_query(gsp2_plan plan, gsp2_plan_info *info, int32_t *core_sizes, int32_t *sub_sizes) {
+    return guarded([&] {
+        if (!plan) fail(GSP2_E_INVALID, "null plan");
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->n = plan->n;
+            info->n_parts = plan->n_parts;
+            int32_t mx = 0, mn = INT32_MAX;
+            double s3 = 0.0;
+            int64_t nnzp = 0;
+            for (const auto &d : plan->desc) {
+                mx = std::max(mx, d.s);
+                mn = std::min(mn, d.s);
+                s3 += (double)d.s * d.s * d.s;
+                nnzp += (int64_t)d.c * d.s;
+            }
+            info->max_s = mx;
+            info->min_s = mn;
+            info->nnz_graph = plan->nnz_graph;
+            info->nnz_P = nnzp;
+            info->sum_s = (int64_t)plan->sub_idx.size();
+            info->sum_s3 = s3;
+            info->tile = plan->tile;
+            info->n_tiles = (int32_t)plan->tiles.size();
+            info->workspace_bytes = plan->workspace_bytes;
+            info->plan_ms = plan->plan_ms;
+        }
+        for (int32_t k = 0; k < plan->n_parts; ++k) {
+            if (core_sizes) core_sizes[k] = plan->desc[k].c;
+            if (sub_sizes) sub_sizes[k] = plan->desc[k].s;
+        }
+    });
+}
+
+gsp2_status gsp2_plan_pattern(gsp2_plan plan, int64_t *col_ptr, int32_t *row_idx) {
+    return guarded([&] {
+        if (!plan) fail(GSP2_E_INVALID, "null plan");
+        if (col_ptr) std::copy(plan->col_ptr.begin(), plan->col_ptr.end(), col_ptr);
+        if (row_idx) {
+            for (int32_t j = 0; j < plan->n; ++j) {
+                const PartDesc &d = plan->desc[plan->col_part[j]];
+                const int32_t *ix = plan->sub_idx.data() + d.idx_off;
+                const int32_t *pm = plan->perm.data() + d.perm_off;
+                int32_t *dst = row_idx + plan->col_ptr[j];
+                for (int32_t t = 0; t < d.s; ++t) dst[t] = ix[pm[t]];
+            }
+        }
+    });
+}
+
+gsp2_status gsp2_plan_part_index(gsp2_plan plan, int32_t k, int32_t *idx) {
+    return guarded([&] {
+        if (!plan) fail(GSP2_E_INVALID, "null plan");
+        if (k < 0 || k >= plan->n_parts) fail(GSP2_E_INVALID, "part out of range");
+        if (!idx) fail(GSP2_E_INVALID, "null idx");
+        std::copy(plan->sub_idx.begin() + plan->sub_ptr[k], plan->sub_idx.begin() + plan->sub_ptr[k + 1], idx);
+    });
+}
+
+gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream) {
+    return guarded([&] {
+        if (!plan) fail(GSP2_E_INVALID, "null plan");
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (s != plan->stream) {
+            check_hip(plan->stream ? hipStreamSynchronize(plan->stream) : hipDeviceSynchronize(), "set stream");
+            plan->stream = s;
+        }
+    });
+}
+
+static void fill_info(const gsp2_plan_s *plan, gsp2_run_info *info) {
+    const RunState &r = *plan->h_state;
+    std::memset(info, 0, sizeof(*info));
+    info->status = r.status;
+    info->n_products = r.n_products;
+    info->n_alpha = r.t;
+    info->result_iterate = r.result_t;
+    info->eps_min = r.eps_min;
+    info->eps_max = r.eps_max;
+    info->trace = (r.result_t >= 0 && r.result_t <= GSP2_MAX_ITER) ? r.traces[r.result_t] : NAN;
+    info->idempotency = r.idem;
+    for (int i = 0; i < GSP2_MAX_ITER; ++i) {
+        info->alpha[i] = r.alpha_hist[i];
+        info->errors[i] = r.errors[i];
+        info->traces[i] = r.traces[i];
+    }
+    info->traces[GSP2_MAX_ITER] = r.traces[GSP2_MAX_ITER];
+}
+
+static gsp2_status collect(gsp2_plan_s *plan, gsp2_run_info *info) {
+    gsp2_status run_status = GSP2_OK;
+    const gsp2_status st = guarded([&] {
+        check_hip(hipMemcpyAsync(plan->h_state, plan->dp.state, sizeof(RunState), hipMemcpyDeviceToHost,
+                                 plan->stream), "copy run state");
+        check_hip(hipStreamSynchronize(plan->stream), "run");
+        if (info) fill_info(plan, info);
+        run_status = (gsp2_status)plan->h_state->status;
+        if (run_status != GSP2_OK) {
+            const RunState &r = *plan->h_state;
+            char buf[256];
+            if (run_status == GSP2_E_INVALID)
+                std::snprintf(buf, sizeof buf, "H rejected: Gershgorin bounds [%g, %g] not finite or empty",
+                              r.eps_min, r.eps_max);
+            else if (run_status == GSP2_E_NOT_CONVERGED)
+                std::snprintf(buf, sizeof buf, "no convergence after %d products", r.n_products);
+            else
+                std::snprintf(buf, sizeof buf, "trace %.6f differs from n_occ %.6f by more than %g",
+                              r.traces[r.result_t], r.n_occ, r.trace_tol);
+            g_last_error = buf;
+        }
+    });
+    if (st != GSP2_OK) return st;
+    return run_status;
+}
+
+gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const gsp2_run_options *run,
+                         float *P_val, gsp2_run_info *info) {
+    gsp2_status st = guarded([&] {
+        if (!plan) fail(GSP2_E_INVALID, "null plan");
+        if (!H) fail(GSP2_E_INVALID, "null H");
+        if (H->n != plan->n) fail(GSP2_E_INVALID, "H.n differs from the plan");
+        if (H->nnz < 0 || !H->row_ptr || (H->nnz > 0 && (!H->col || !H->val)))
+            fail(GSP2_E_INVALID, "bad H arrays");
+        if (H->dtype != GSP2_F32 && H->dtype != GSP2_F64) fail(GSP2_E_INVALID, "bad H.dtype");
+        if (!P_val) fail(GSP2_E_INVALID, "null P_val");
+        if (!(n_occ >= 0.0) || !(n_occ <= (double)plan->n)) fail(GSP2_E_INVALID, "need 0 <= n_occ <= n");
+        gsp2_run_options def;
+        gsp2_run_options_default(&def);
+        const gsp2_run_options &o = run ? *run : def;
+        RunParams rp{};
+        rp.n_occ = n_occ;
+        rp.trace_tol = o.trace_tol;
+        rp.mode = o.alpha_mode;
+        rp.stop_rule = o.stop_rule ? 1 : 0;
+        if (o.alpha_mode == GSP2_ALPHA_TRACE) {
+            if (o.max_iter < 1 || o.max_iter > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter out of range");
+            rp.n_steps = o.max_iter;
+        } else if (o.alpha_mode == GSP2_ALPHA_REPLAY) {
+            if (o.n_alpha < 0 || o.n_alpha > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_alpha out of range");
+            if (o.n_alpha > 0 && !o.alpha_seq) fail(GSP2_E_INVALID, "null alpha_seq");
+            if (!(o.trace_tol >= 0.0)) fail(GSP2_E_INVALID, "trace_tol must be >= 0");
+            for (int i = 0; i < o.n_alpha; ++i) {
+                if (o.alpha_seq[i] != 1 && o.alpha_seq[i] != -1) fail(GSP2_E_INVALID, "alpha must be +1 or -1");
+                rp.alpha_seq[i] = o.alpha_seq[i];
+            }
+            rp.n_steps = o.n_alpha;
+        } else {
+            fail(GSP2_E_INVALID, "bad alpha_mode");
+        }
+        GraphKey k;
+        k.h_ptr = H->row_ptr; k.h_col = H->col; k.h_val = H->val; k.h_nnz = H->nnz; k.h_dtype = H->dtype;
+        k.p_val = P_val; k.rp = rp;
+        const bool eager = plan->stream == nullptr || std::getenv("GSP2_EAGER") != nullptr;
+        if (eager) {
+            check_hip(launch_density(plan->dp, *H, rp, P_val, plan->stream), "launch density");
+        } else {
+            if (!plan->have_graph || !(plan->key == k)) {
+                if (plan->exec) { check_hip(hipGraphExecDestroy(plan->exec), "graph destroy"); plan->exec = nullptr; }
+                if (plan->graph) { check_hip(hipGraphDestroy(plan->graph), "graph destroy"); plan->graph = nullptr; }
+                plan->have_graph = false;
+                check_hip(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+                const hipError_t le = launch_density(plan->dp, *H, rp, P_val, plan->stream);
+                hipGraph_t g = nullptr;
+                const hipError_t ce = hipStreamEndCapture(plan->stream, &g);
+                check_hip(le, "launch density (capture)");
+                check_hip(ce, "end capture");
+                plan->graph = g;
+                check_hip(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0), "graph instantiate");
+                plan->key = k;
+                plan->have_graph = true;
+            }
+            check_hip(hipGraphLaunch(plan->exec, plan->stream), "graph launch");
+        }
+        plan->last_rp = rp;
+        plan->ran = true;
+    });
+    if (st != GSP2_OK || !info) return st;
+    return collect(plan, info);
+}
+
+gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info) {
+    if (!plan) { g_last_error = "null plan"; return GSP2_E_INVALID; }
+    if (!plan->ran) { g_last_error = "no run on this plan"; return GSP2_E_INVALID; }
+    return collect(plan, info);
+}
+
+void gsp2_plan_destroy(gsp2_plan plan) { delete plan; }
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Layouts shared by the host planner, the ABI layer and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsp2.h"
+
+namespace gsp2 {
+
+// Macro tile of the SP2 product (rows x columns of Y computed by one
+// workgroup) and the K depth staged through LDS per pipeline step.
+constexpr int kTile = 128;
+constexpr int kKChunk = 32;
+
+// One part of the partition, as the device sees it.
+struct PartDesc {
+    int64_t x_off;      // float offset of the part's s_pad x s_pad block in each X buffer
+    int32_t idx_off;    // offset of its vertex list (local order) in the index arena
+    int32_t s;          // sub-problem size c + h
+    int32_t c;          // core size
+    int32_t s_pad;      // s rounded up to a multiple of kTile (padding is zero)
+    int32_t perm_off;   // offset of its sorted-position -> local-index map
+    int32_t pad_;
+};
+static_assert(sizeof(PartDesc) == 32, "PartDesc layout");
+
+// One upper-triangle macro tile (ti <= tj) of one part's product.
+struct TileDesc {
+    int32_t part, ti, tj, diag_slot;   // diag_slot >= 0 only when ti == tj
+};
+
+// A run of consecutive local rows of one part, built by one gather workgroup.
+struct RowChunk {
+    int32_t part, r0, r1, pad_;
+};
+
+// Run-time state of one density-matrix computation, in device memory.
+// Written only by the single-workgroup control kernels.
+struct RunState {
+    double n_occ;
+    double trace_tol;
+    double eps_min, eps_max;
+    double trX;                 // Tr[X_t] of the current iterate
+    double idem;                // e_t of the returned iterate
+    int32_t n_steps;            // product budget (trace mode) or replay length
+    int32_t mode;               // gsp2_alpha_mode
+    int32_t stop_rule;
+    int32_t t;                  // products formed and kept so far (= index of X_t)
+    int32_t cur;                // buffer holding X_t
+    int32_t alpha;              // branch for the next product
+    int32_t done;
+    int32_t status;             // gsp2_status
+    int32_t result_buf;
+    int32_t result_t;
+    int32_t n_products;
+    int32_t pad_;
+    int8_t alpha_seq[GSP2_MAX_ITER];
+    int8_t alpha_hist[GSP2_MAX_ITER];
+    double traces[GSP2_MAX_ITER + 1];
+    double errors[GSP2_MAX_ITER];
+};
+
+// Per-call parameters baked into the run's kernels.
+struct RunParams {
+    double n_occ;
+    double trace_tol;
+    int32_t n_steps;
+    int32_t mode;
+    int32_t stop_rule;
+    int32_t pad_;
+    int8_t alpha_seq[GSP2_MAX_ITER];
+};
+
+// Device buffers of a plan, passed to the launchers.
+struct DevicePlan {
+    int32_t n;
+    int32_t n_parts;
+    int32_t n_tiles;
+    int32_t n_diag;
+    int32_t n_chunks;
+    int32_t max_s_pad;
+    int32_t gersh_blocks;
+    int32_t pad_;
+    float *buf[2];
+    const PartDesc *parts;
+    const TileDesc *tiles;
+    const RowChunk *chunks;
+    const int32_t *idx;         // index arena (local order)
+    const int32_t *perm;        // per part: sorted position -> local index
+    const int64_t *col_ptr;     // CSC column pointers of P, n+1
+    const int32_t *col_part;    // part of every column
+    const int32_t *col_local;   // local index of every column in its part
+    double *diag_partials;      // n_diag x 2
+    double *x0_partials;        // n_chunks
+    double *gersh_partials;     // gersh_blocks x 3
+    RunState *state;
+};
+
+// Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.
+hipError_t launch_threshold_count(const gsp2_csr &P, double tau, int32_t *counts, hipStream_t s);
+hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *out_ptr,
+                                 int32_t *out_col, hipStream_t s);
+hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp,
+                          float *P_val, hipStream_t s);
+
+}  // namespace gsp2

@@ -1,0 +1,557 @@
+// HIP kernels of the G-SP2 hot path for CDNA4 (gfx950), wave64.
+//
+//  threshold   G_tau from a previous P                (Methods, "Graph Theory")
+//  gershgorin  spectral bounds of the whole H          (Methods, SP2: Gershgorin discs)
+//  gather_x0   dense core+halo blocks of eq. (1)       (Fig. 1 description: sub-matrices of H)
+//  sp2_step    X^2 on the matrix cores + eq. (2) update + core-trace partials
+//  control     FP64 trace reductions, branch and stop decisions (eq. (2) branch rule, idempotency)
+//  scatter     core columns into the sparse P          (Fig. 1 description: reassembly)
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "gsp2_internal.hpp"
+
+namespace gsp2 {
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+template <typename T>
+__device__ __forceinline__ double as_double(T v) { return static_cast<double>(v); }
+
+// Deterministic wave sum (fixed butterfly).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Deterministic block sum of two doubles; result valid in thread 0.
+__device__ __forceinline__ void block_sum2(double &a, double &b) {
+    __shared__ double red[2][kBlock / kWave];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) { red[0][w] = a; red[1][w] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        a = 0.0; b = 0.0;
+        for (int i = 0; i < kBlock / kWave; ++i) { a += red[0][i]; b += red[1][i]; }
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// a1: threshold.  One wave per row; entries kept in their stored order.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_threshold_count(const int64_t *__restrict__ row_ptr,
+                                                            const int32_t *__restrict__ col,
+                                                            const T *__restrict__ val, int32_t n,
+                                                            double tau, int32_t *__restrict__ counts) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (row >= n) return;
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    int cnt = 0;
+    for (int64_t i = b + lane; i < e; i += kWave)
+        cnt += (col[i] != row && fabs(as_double(val[i])) > tau) ? 1 : 0;
+    cnt = wave_sum_int(cnt);
+    if (lane == 0) counts[row] = cnt;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_threshold_fill(const int64_t *__restrict__ row_ptr,
+                                                           const int32_t *__restrict__ col,
+                                                           const T *__restrict__ val, int32_t n,
+                                                           double tau, const int64_t *__restrict__ out_ptr,
+                                                           int32_t *__restrict__ out_col) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (row >= n) return;
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    int64_t o = out_ptr[row];
+    const int64_t o_end = out_ptr[row + 1];
+    for (int64_t base = b; base < e; base += kWave) {
+        const int64_t i = base + lane;
+        const bool keep = i < e && col[i] != row && fabs(as_double(val[i])) > tau;
+        const uint64_t m = __ballot(keep);
+        const int before = __popcll(m & ((1ull << lane) - 1ull));
+        if (keep && o + before < o_end) out_col[o + before] = col[i];
+        o += __popcll(m);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a4: Gershgorin bounds.  One wave per row, FP64; per-block min/max partials.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gershgorin(const int64_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ col,
+                                                       const T *__restrict__ val, int32_t n,
+                                                       double *__restrict__ partials) {
+    __shared__ double lo_s[kBlock / kWave], hi_s[kBlock / kWave], bad_s[kBlock / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + w; row < n; row += stride) {
+        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+        double rad = 0.0, d = 0.0, nf = 0.0;
+        for (int64_t i = b + lane; i < e; i += kWave) {
+            const double v = as_double(val[i]);
+            if (!isfinite(v)) nf = 1.0;
+            if (col[i] == row) d += v; else rad += fabs(v);
+        }
+        rad = wave_sum(rad);
+        d = wave_sum(d);
+        nf = wave_sum(nf);
+        lo = fmin(lo, d - rad);
+        hi = fmax(hi, d + rad);
+        if (nf > 0.0) bad = 1.0;
+    }
+    if (lane == 0) { lo_s[w] = lo; hi_s[w] = hi; bad_s[w] = bad; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / kWave; ++i) {
+            lo = fmin(lo, lo_s[i]); hi = fmax(hi, hi_s[i]); bad = fmax(bad, bad_s[i]);
+        }
+        lo = fmin(lo, lo_s[0]); hi = fmax(hi, hi_s[0]); bad = fmax(bad, bad_s[0]);
+        partials[3 * blockIdx.x + 0] = lo;
+        partials[3 * blockIdx.x + 1] = hi;
+        partials[3 * blockIdx.x + 2] = bad;
+    }
+}
+
+// Reduce the Gershgorin partials and initialise the run state.
+__global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ partials, int nblk,
+                                                     RunParams rp, RunState *__restrict__ st) {
+    if (threadIdx.x != 0) return;
+    double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+    for (int i = 0; i < nblk; ++i) {
+        lo = fmin(lo, partials[3 * i]);
+        hi = fmax(hi, partials[3 * i + 1]);
+        bad = fmax(bad, partials[3 * i + 2]);
+    }
+    st->n_occ = rp.n_occ;
+    st->trace_tol = rp.trace_tol;
+    st->eps_min = lo;
+    st->eps_max = hi;
+    st->trX = 0.0;
+    st->idem = NAN;
+    st->n_steps = rp.n_steps;
+    st->mode = rp.mode;
+    st->stop_rule = rp.stop_rule;
+    st->t = 0;
+    st->cur = 0;
+    st->alpha = 0;
+    st->result_buf = 0;
+    st->result_t = 0;
+    st->n_products = 0;
+    for (int i = 0; i < GSP2_MAX_ITER; ++i) {
+        st->alpha_seq[i] = rp.alpha_seq[i];
+        st->alpha_hist[i] = 0;
+        st->errors[i] = NAN;
+        st->traces[i] = NAN;
+    }
+    st->traces[GSP2_MAX_ITER] = NAN;
+    const bool ok = bad == 0.0 && isfinite(lo) && isfinite(hi) && hi > lo;
+    st->status = ok ? GSP2_OK : GSP2_E_INVALID;
+    st->done = ok ? 0 : 1;
+}
+
+// ---------------------------------------------------------------------------
+// a5: gather + X0 (eq. (1)).  One workgroup per chunk of rows of one part;
+// every row of the padded block (s_pad wide) is written exactly once, built
+// in LDS so the HBM writes are whole coalesced rows.
+// ---------------------------------------------------------------------------
+constexpr int kGatherLdsIdx = 8192;    // vertex list held in LDS up to this size
+constexpr int kGatherChunk = 8192;     // row segment built in LDS per pass
+
+__device__ __forceinline__ int find_sorted(const int32_t *a, int n, int32_t key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < n && a[lo] == key) ? lo : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict__ row_ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const T *__restrict__ val,
+                                                      const PartDesc *__restrict__ parts,
+                                                      const RowChunk *__restrict__ chunks,
+                                                      const int32_t *__restrict__ idx_arena,
+                                                      float *__restrict__ X, const RunState *__restrict__ st,
+                                                      double *__restrict__ x0_partials) {
+    __shared__ int32_t idx_s[kGatherLdsIdx];
+    __shared__ float row_s[kGatherChunk];
+    if (st->done) return;
+    const RowChunk ch = chunks[blockIdx.x];
+    const PartDesc pd = parts[ch.part];
+    const int32_t *idx_g = idx_arena + pd.idx_off;
+    const bool in_lds = pd.s <= kGatherLdsIdx;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < pd.s; i += kBlock) idx_s[i] = idx_g[i];
+        __syncthreads();
+    }
+    const int32_t *idx = in_lds ? idx_s : idx_g;
+    const double emin = st->eps_min, emax = st->eps_max;
+    const double inv = 1.0 / (emax - emin);
+    const int ld = pd.s_pad;
+    float *Xp = X + pd.x_off;
+    double tr = 0.0;
+    for (int r = ch.r0; r < ch.r1; ++r) {
+        const bool real = r < pd.s;
+        const int64_t g = real ? idx[r] : -1;
+        const int64_t hb = real ? row_ptr[g] : 0, he = real ? row_ptr[g + 1] : 0;
+        for (int c0 = 0; c0 < ld; c0 += kGatherChunk) {
+            const int cw = min(kGatherChunk, ld - c0);
+            for (int i = threadIdx.x; i < cw; i += kBlock) row_s[i] = 0.0f;
+            __syncthreads();
+            if (real && threadIdx.x == 0 && r >= c0 && r < c0 + cw)
+                row_s[r - c0] = static_cast<float>(emax * inv);       // H_gg = 0 if not stored
+            __syncthreads();
+            for (int64_t e = hb + threadIdx.x; e < he; e += kBlock) {
+                const int32_t cg = col[e];
+                int q = find_sorted(idx, pd.c, cg);
+                if (q < 0) {
+                    q = find_sorted(idx + pd.c, pd.s - pd.c, cg);
+                    if (q >= 0) q += pd.c;
+                }
+                if (q >= c0 && q < c0 + cw) {
+                    const double h = as_double(val[e]);
+                    const double x = (cg == g) ? (emax - h) * inv : -h * inv;
+                    row_s[q - c0] = static_cast<float>(x);
+                }
+            }
+            __syncthreads();
+            if (real && r < pd.c && threadIdx.x == 0 && r >= c0 && r < c0 + cw)
+                tr += static_cast<double>(row_s[r - c0]);
+            float4 *dst = reinterpret_cast<float4 *>(Xp + (int64_t)r * ld + c0);
+            const float4 *src = reinterpret_cast<const float4 *>(row_s);
+            for (int i = threadIdx.x; i < cw / 4; i += kBlock) dst[i] = src[i];
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) x0_partials[blockIdx.x] = tr;
+}
+
+// Reduce the X0 core-trace partials; pick the first branch.
+__global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__ x0_partials, int n,
+                                                      RunState *__restrict__ st) {
+    if (st->done) return;
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) a += x0_partials[i];
+    block_sum2(a, b);
+    if (threadIdx.x == 0) {
+        st->trX = a;
+        st->traces[0] = a;
+        if (st->n_steps <= 0) {
+            st->done = 1;
+            st->result_buf = 0;
+            st->result_t = 0;
+            st->status = (st->mode == GSP2_ALPHA_REPLAY && fabs(a - st->n_occ) > st->trace_tol)
+                             ? GSP2_E_WRONG_TRACE : GSP2_OK;
+            return;
+        }
+        st->alpha = (st->mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[0] : (a <= st->n_occ ? 1 : -1);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a6: one SP2 product on the matrix cores.
+//
+// Each workgroup computes one 128x128 tile Y[I,J] = sum_k X[I,k] X[J,k] of
+// one part (X is symmetric, so both operands are row panels with k
+// contiguous), for ti <= tj only; the eq. (2) update X' = Y or 2X - Y is
+// fused into the epilogue and written to the other buffer at (I,J) and,
+// mirrored, at (J,I), so every iterate stays exactly symmetric.  Diagonal
+// tiles also emit FP64 partial sums of Y and X' over the part's core
+// diagonal.
+//
+// 256 threads = 4 waves in a 2x2 grid, each wave a 64x64 sub-tile as 2x2
+// blocks of v_mfma_f32_32x32x2f32.  Operands are staged through LDS in K
+// chunks of 32 with a register prefetch of the next chunk and two LDS
+// buffers.  Within a chunk, lane half h of the MFMA operand feeds k = 16h+s
+// at step s, for A and B alike, so each lane reads 16 contiguous floats.
+// ---------------------------------------------------------------------------
+constexpr int kLdsStride = kKChunk + 4;      // padded LDS row (floats)
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restrict__ tiles,
+                                                        const PartDesc *__restrict__ parts,
+                                                        float *__restrict__ buf0, float *__restrict__ buf1,
+                                                        const RunState *__restrict__ st,
+                                                        double *__restrict__ diag_partials) {
+    __shared__ float As[2][kTile * kLdsStride];
+    __shared__ float Bs[2][kTile * kLdsStride];
+    if (st->done) return;
+    const TileDesc td = tiles[blockIdx.x];
+    const PartDesc pd = parts[td.part];
+    const int cur = st->cur;
+    const float alpha = static_cast<float>(st->alpha);
+    const float *__restrict__ X = (cur ? buf1 : buf0) + pd.x_off;
+    float *__restrict__ Xn = (cur ? buf0 : buf1) + pd.x_off;
+    const int ld = pd.s_pad;
+    const int I0 = td.ti * kTile, J0 = td.tj * kTile;
+    const bool diag = td.ti == td.tj;
+
+    const int tid = threadIdx.x;
+    // global -> LDS mapping: 8 threads per 32-float row segment, 32 rows per pass
+    const int lr = tid >> 3, lc = (tid & 7) * 4;
+    const float *Ag = X + (int64_t)(I0 + lr) * ld + lc;
+    const float *Bg = X + (int64_t)(J0 + lr) * ld + lc;
+    const int64_t pass_stride = (int64_t)32 * ld;
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int l32 = lane & 31, kh = lane >> 5;
+
+    v16f acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+
+    float4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
+#define GSP2_LOAD_CHUNK(k0)                                                            \
+    do {                                                                               \
+        pa0 = *reinterpret_cast<const float4 *>(Ag + (k0));                            \
+        pa1 = *reinterpret_cast<const float4 *>(Ag + pass_stride + (k0));              \
+        pa2 = *reinterpret_cast<const float4 *>(Ag + 2 * pass_stride + (k0));          \
+        pa3 = *reinterpret_cast<const float4 *>(Ag + 3 * pass_stride + (k0));          \
+        if (!diag) {                                                                   \
+            pb0 = *reinterpret_cast<const float4 *>(Bg + (k0));                        \
+            pb1 = *reinterpret_cast<const float4 *>(Bg + pass_stride + (k0));          \
+            pb2 = *reinterpret_cast<const float4 *>(Bg + 2 * pass_stride + (k0));      \
+            pb3 = *reinterpret_cast<const float4 *>(Bg + 3 * pass_stride + (k0));      \
+        }                                                                              \
+    } while (0)
+#define GSP2_STORE_CHUNK(b)                                                            \
+    do {                                                                               \
+        float *As_ = As[b] + lr * kLdsStride + lc;                                     \
+        *reinterpret_cast<float4 *>(As_) = pa0;                                        \
+        *reinterpret_cast<float4 *>(As_ + 32 * kLdsStride) = pa1;                      \
+        *reinterpret_cast<float4 *>(As_ + 64 * kLdsStride) = pa2;                      \
+        *reinterpret_cast<float4 *>(As_ + 96 * kLdsStride) = pa3;                      \
+        if (!diag) {                                                                   \
+            float *Bs_ = Bs[b] + lr * kLdsStride + lc;                                 \
+            *reinterpret_cast<float4 *>(Bs_) = pb0;                                    \
+            *reinterpret_cast<float4 *>(Bs_ + 32 * kLdsStride) = pb1;                  \
+            *reinterpret_cast<float4 *>(Bs_ + 64 * kLdsStride) = pb2;                  \
+            *reinterpret_cast<float4 *>(Bs_ + 96 * kLdsStride) = pb3;                  \
+        }                                                                              \
+    } while (0)
+
+    const int nk = ld / kKChunk;
+    GSP2_LOAD_CHUNK(0);
+    GSP2_STORE_CHUNK(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nk) GSP2_LOAD_CHUNK((kc + 1) * kKChunk);
+        const float *Asb = As[buf];
+        const float *Bsb = diag ? As[buf] : Bs[buf];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            float4 fa[2], fb[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                fa[m] = *reinterpret_cast<const float4 *>(Asb + (wr * 64 + m * 32 + l32) * kLdsStride + kh * 16 + 4 * q);
+                fb[m] = *reinterpret_cast<const float4 *>(Bsb + (wc * 64 + m * 32 + l32) * kLdsStride + kh * 16 + 4 * q);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn)
+                        acc[m][nn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][e], fb[nn][e], acc[m][nn], 0, 0, 0);
+            }
+        }
+        if (kc + 1 < nk) GSP2_STORE_CHUNK(buf ^ 1);
+        __syncthreads();
+    }
+#undef GSP2_LOAD_CHUNK
+#undef GSP2_STORE_CHUNK
+
+    // Epilogue.  Accumulator element i of lane (l32, kh) in a 32x32 block is
+    // row 8*(i/4) + 4*kh + (i%4), column l32.
+    double tY = 0.0, tX = 0.0;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+#pragma unroll
+        for (int nn = 0; nn < 2; ++nn) {
+            const int cg = J0 + wc * 64 + nn * 32 + l32;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int rg0 = I0 + wr * 64 + m * 32 + g * 8 + kh * 4;
+                float xn[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rg = rg0 + e;
+                    const float y = acc[m][nn][4 * g + e];
+                    const float xo = X[(int64_t)rg * ld + cg];
+                    const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
+                    xn[e] = v;
+                    Xn[(int64_t)rg * ld + cg] = v;
+                    if (diag && rg == cg && rg < pd.c) {
+                        tY += static_cast<double>(y);
+                        tX += static_cast<double>(v);
+                    }
+                }
+                if (!diag)
+                    *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+            }
+        }
+    }
+    if (diag) {
+        block_sum2(tY, tX);
+        if (tid == 0) {
+            diag_partials[2 * td.diag_slot + 0] = tY;
+            diag_partials[2 * td.diag_slot + 1] = tX;
+        }
+    }
+}
+
+// a7: reduce the product's trace partials, apply the stop rule, choose the
+// next branch.  One workgroup; fixed summation order.
+__global__ __launch_bounds__(kBlock) void k_sp2_decide(const double *__restrict__ diag_partials, int n_diag,
+                                                       RunState *__restrict__ st) {
+    if (st->done) return;
+    double ty = 0.0, tx = 0.0;
+    for (int i = threadIdx.x; i < n_diag; i += kBlock) {
+        ty += diag_partials[2 * i];
+        tx += diag_partials[2 * i + 1];
+    }
+    block_sum2(ty, tx);
+    if (threadIdx.x != 0) return;
+    const int t = st->t;
+    const double e = st->trX - ty;              // e_t = Tr[X_t] - Tr[X_t^2]
+    st->errors[t] = e;
+    st->n_products = t + 1;
+    if (!isfinite(ty) || !isfinite(tx)) {       // left the finite range: keep X_t
+        st->done = 1;
+        st->result_buf = st->cur;
+        st->result_t = t;
+        st->status = GSP2_E_NOT_CONVERGED;
+        return;
+    }
+    // the bound applies to |e|: in FP32 e turns negative once X_t is idempotent to rounding
+    if (st->mode == GSP2_ALPHA_TRACE && st->stop_rule && t >= 2 && fabs(e) >= fabs(st->errors[t - 2]) &&
+        fabs(st->errors[t - 2]) < 1.0) {
+        st->done = 1;                           // X_t is the result; X_t^2 is discarded
+        st->result_buf = st->cur;
+        st->result_t = t;
+        st->idem = e;
+        st->status = GSP2_OK;
+        return;
+    }
+    st->alpha_hist[t] = (int8_t)st->alpha;
+    st->cur ^= 1;
+    st->trX = tx;
+    st->traces[t + 1] = tx;
+    st->t = t + 1;
+    if (t + 1 >= st->n_steps) {
+        st->done = 1;
+        st->result_buf = st->cur;
+        st->result_t = t + 1;
+        if (st->mode == GSP2_ALPHA_REPLAY)
+            st->status = fabs(tx - st->n_occ) <= st->trace_tol ? GSP2_OK : GSP2_E_WRONG_TRACE;
+        else
+            st->status = st->stop_rule ? GSP2_E_NOT_CONVERGED : GSP2_OK;
+        return;
+    }
+    st->alpha = (st->mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[t + 1] : (tx <= st->n_occ ? 1 : -1);
+}
+
+// ---------------------------------------------------------------------------
+// a8: scatter.  One wave per column of P; the column's rows are the part's
+// vertices in ascending global order, read from the (symmetric) row of the
+// final iterate through the sorted-position map.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_scatter(const PartDesc *__restrict__ parts,
+                                                    const int32_t *__restrict__ perm_arena,
+                                                    const int64_t *__restrict__ col_ptr,
+                                                    const int32_t *__restrict__ col_part,
+                                                    const int32_t *__restrict__ col_local, int32_t n,
+                                                    const float *__restrict__ buf0, const float *__restrict__ buf1,
+                                                    const RunState *__restrict__ st, float *__restrict__ P_val) {
+    if (st->status == GSP2_E_INVALID) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t j = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (j >= n) return;
+    const PartDesc pd = parts[col_part[j]];
+    const float *Xr = (st->result_buf ? buf1 : buf0) + pd.x_off + (int64_t)col_local[j] * pd.s_pad;
+    const int32_t *perm = perm_arena + pd.perm_off;
+    float *out = P_val + col_ptr[j];
+    for (int t = lane; t < pd.s; t += kWave) out[t] = Xr[perm[t]];
+}
+
+template <typename T>
+hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, float *P_val,
+                         hipStream_t s) {
+    const T *hv = static_cast<const T *>(H.val);
+    hipLaunchKernelGGL(k_gershgorin<T>, dim3(dp.gersh_blocks), dim3(kBlock), 0, s, H.row_ptr, H.col, hv, dp.n,
+                       dp.gersh_partials);
+    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(kBlock), 0, s, dp.gersh_partials, dp.gersh_blocks, rp, dp.state);
+    hipLaunchKernelGGL(k_gather_x0<T>, dim3(dp.n_chunks), dim3(kBlock), 0, s, H.row_ptr, H.col, hv, dp.parts,
+                       dp.chunks, dp.idx, dp.buf[0], dp.state, dp.x0_partials);
+    hipLaunchKernelGGL(k_run_start, dim3(1), dim3(kBlock), 0, s, dp.x0_partials, dp.n_chunks, dp.state);
+    for (int it = 0; it < rp.n_steps; ++it) {
+        hipLaunchKernelGGL(k_sp2_step, dim3(dp.n_tiles), dim3(kBlock), 0, s, dp.tiles, dp.parts, dp.buf[0],
+                           dp.buf[1], dp.state, dp.diag_partials);
+        hipLaunchKernelGGL(k_sp2_decide, dim3(1), dim3(kBlock), 0, s, dp.diag_partials, dp.n_diag, dp.state);
+    }
+    const int wpb = kBlock / kWave;
+    hipLaunchKernelGGL(k_scatter, dim3((dp.n + wpb - 1) / wpb), dim3(kBlock), 0, s, dp.parts, dp.perm, dp.col_ptr,
+                       dp.col_part, dp.col_local, dp.n, dp.buf[0], dp.buf[1], dp.state, P_val);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_threshold_count(const gsp2_csr &P, double tau, int32_t *counts, hipStream_t s) {
+    const int wpb = kBlock / kWave;
+    const dim3 grid((P.n + wpb - 1) / wpb);
+    if (P.dtype == GSP2_F64)
+        hipLaunchKernelGGL(k_threshold_count<double>, grid, dim3(kBlock), 0, s, P.row_ptr, P.col,
+                           static_cast<const double *>(P.val), P.n, tau, counts);
+    else
+        hipLaunchKernelGGL(k_threshold_count<float>, grid, dim3(kBlock), 0, s, P.row_ptr, P.col,
+                           static_cast<const float *>(P.val), P.n, tau, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *out_ptr, int32_t *out_col,
+                                 hipStream_t s) {
+    const int wpb = kBlock / kWave;
+    const dim3 grid((P.n + wpb - 1) / wpb);
+    if (P.dtype == GSP2_F64)
+        hipLaunchKernelGGL(k_threshold_fill<double>, grid, dim3(kBlock), 0, s, P.row_ptr, P.col,
+                           static_cast<const double *>(P.val), P.n, tau, out_ptr, out_col);
+    else
+        hipLaunchKernelGGL(k_threshold_fill<float>, grid, dim3(kBlock), 0, s, P.row_ptr, P.col,
+                           static_cast<const float *>(P.val), P.n, tau, out_ptr, out_col);
+    return hipGetLastError();
+}
+
+hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, float *P_val,
+                          hipStream_t s) {
+    if (H.dtype == GSP2_F64) return density_typed<double>(dp, H, rp, P_val, s);
+    return density_typed<float>(dp, H, rp, P_val, s);
+}
+
+}  // namespace gsp2

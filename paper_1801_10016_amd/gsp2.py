@@ -1,0 +1,310 @@
+"""ctypes binding of libgsp2.so (the C ABI declared in include/gsp2.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch supplies device memory and the HIP stream.  Importing
+this module fails loudly if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsp2.so")
+
+GSP2_OK, GSP2_E_INVALID, GSP2_E_HIP, GSP2_E_OOM, GSP2_E_NOT_CONVERGED, GSP2_E_WRONG_TRACE, GSP2_E_UNSUPPORTED = range(7)
+GSP2_F32, GSP2_F64 = 0, 1
+GSP2_ALPHA_TRACE, GSP2_ALPHA_REPLAY = 0, 1
+GSP2_MAX_ITER = 100
+
+STATUS_NAMES = {0: "GSP2_OK", 1: "GSP2_E_INVALID", 2: "GSP2_E_HIP", 3: "GSP2_E_OOM",
+                4: "GSP2_E_NOT_CONVERGED", 5: "GSP2_E_WRONG_TRACE", 6: "GSP2_E_UNSUPPORTED"}
+
+
+class gsp2_csr(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("row_ptr", C.c_void_p), ("col", C.c_void_p),
+                ("val", C.c_void_p), ("dtype", C.c_int32)]
+
+
+class gsp2_plan_options(C.Structure):
+    _fields_ = [("tile", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
+class gsp2_plan_info(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_parts", C.c_int32), ("max_s", C.c_int32), ("min_s", C.c_int32),
+                ("nnz_graph", C.c_int64), ("nnz_P", C.c_int64), ("sum_s", C.c_int64), ("sum_s3", C.c_double),
+                ("tile", C.c_int32), ("n_tiles", C.c_int32), ("workspace_bytes", C.c_int64),
+                ("plan_ms", C.c_double)]
+
+
+class gsp2_run_options(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("alpha_mode", C.c_int32), ("alpha_seq", C.POINTER(C.c_int8)),
+                ("n_alpha", C.c_int32), ("stop_rule", C.c_int32), ("trace_tol", C.c_double)]
+
+
+class gsp2_run_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_products", C.c_int32), ("n_alpha", C.c_int32),
+                ("result_iterate", C.c_int32), ("eps_min", C.c_double), ("eps_max", C.c_double),
+                ("trace", C.c_double), ("idempotency", C.c_double),
+                ("alpha", C.c_int8 * GSP2_MAX_ITER), ("traces", C.c_double * (GSP2_MAX_ITER + 1)),
+                ("errors", C.c_double * GSP2_MAX_ITER)]
+
+
+_PLAN = C.c_void_p
+
+# name -> (restype, argtypes), exactly the functions declared in gsp2.h
+SIGNATURES = {
+    "gsp2_status_string": (C.c_char_p, [C.c_int]),
+    "gsp2_last_error": (C.c_char_p, []),
+    "gsp2_run_options_default": (C.c_int, [C.POINTER(gsp2_run_options)]),
+    "gsp2_plan_create": (C.c_int, [C.POINTER(gsp2_csr), C.c_double, C.POINTER(C.c_int32), C.c_int32,
+                                   C.POINTER(gsp2_plan_options), C.c_void_p, C.POINTER(_PLAN)]),
+    "gsp2_plan_query": (C.c_int, [_PLAN, C.POINTER(gsp2_plan_info), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "gsp2_plan_pattern": (C.c_int, [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "gsp2_plan_part_index": (C.c_int, [_PLAN, C.c_int32, C.POINTER(C.c_int32)]),
+    "gsp2_plan_set_stream": (C.c_int, [_PLAN, C.c_void_p]),
+    "gsp2_density": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.c_double, C.POINTER(gsp2_run_options),
+                               C.c_void_p, C.POINTER(gsp2_run_info)]),
+    "gsp2_run_status": (C.c_int, [_PLAN, C.POINTER(gsp2_run_info)]),
+    "gsp2_plan_destroy": (None, [_PLAN]),
+    "gsp2_core_halo_host": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libgsp2.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -m paper_1801_10016_amd.build)")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class Gsp2Error(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status: int):
+    if status != GSP2_OK:
+        raise Gsp2Error(status, load().gsp2_last_error().decode())
+
+
+def _i32(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _i64(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int64))
+
+
+@dataclass
+class DeviceCSR:
+    """A CSR matrix whose arrays are torch tensors on the GPU."""
+    n: int
+    row_ptr: "object"     # torch.int64, n+1
+    col: "object"         # torch.int32, nnz
+    val: "object"         # torch.float32 or torch.float64, nnz
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    def as_c(self) -> gsp2_csr:
+        import torch
+        dt = GSP2_F64 if self.val.dtype == torch.float64 else GSP2_F32
+        return gsp2_csr(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                        self.val.data_ptr(), dt)
+
+
+def csr_to_device(M, dtype=None, device="cuda") -> DeviceCSR:
+    """scipy.sparse matrix -> DeviceCSR (values float64 unless dtype given)."""
+    import scipy.sparse as sp
+    import torch
+    M = sp.csr_matrix(M)
+    dtype = dtype or torch.float64
+    return DeviceCSR(M.shape[0],
+                     torch.as_tensor(M.indptr.astype(np.int64)).to(device),
+                     torch.as_tensor(M.indices.astype(np.int32)).to(device),
+                     torch.as_tensor(M.data).to(device=device, dtype=dtype))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def gsp2_run_options_default() -> gsp2_run_options:
+    o = gsp2_run_options()
+    _check(load().gsp2_run_options_default(C.byref(o)))
+    return o
+
+
+class Plan:
+    """Owns a gsp2_plan handle."""
+
+    def __init__(self, handle: int):
+        self.handle = C.c_void_p(handle)
+        self.nnz_P = None
+
+    def close(self):
+        if self.handle and self.handle.value:
+            load().gsp2_plan_destroy(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def gsp2_plan_create(P_prev: DeviceCSR, tau: float, part, n_parts: int, tile: int = 0, stream=None) -> Plan:
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    if part.shape != (P_prev.n,):
+        raise ValueError("part must have one entry per vertex")
+    c = P_prev.as_c()
+    opt = gsp2_plan_options(tile)
+    out = _PLAN()
+    _check(load().gsp2_plan_create(C.byref(c), float(tau), _i32(part), int(n_parts), C.byref(opt),
+                                   C.c_void_p(_stream_handle(stream)), C.byref(out)))
+    plan = Plan(out.value)
+    plan.nnz_P = gsp2_plan_query(plan)[0]["nnz_P"]
+    return plan
+
+
+def gsp2_plan_query(plan: Plan):
+    lib = load()
+    info = gsp2_plan_info()
+    _check(lib.gsp2_plan_query(plan.handle, C.byref(info), None, None))
+    cs = np.empty(info.n_parts, dtype=np.int32)
+    ss = np.empty(info.n_parts, dtype=np.int32)
+    _check(lib.gsp2_plan_query(plan.handle, None, _i32(cs), _i32(ss)))
+    d = {f: getattr(info, f) for f, _ in gsp2_plan_info._fields_}
+    return d, cs, ss
+
+
+def gsp2_plan_pattern(plan: Plan):
+    info, _, _ = gsp2_plan_query(plan)
+    col_ptr = np.empty(info["n"] + 1, dtype=np.int64)
+    row_idx = np.empty(info["nnz_P"], dtype=np.int32)
+    _check(load().gsp2_plan_pattern(plan.handle, _i64(col_ptr), _i32(row_idx)))
+    return col_ptr, row_idx
+
+
+def gsp2_plan_part_index(plan: Plan, k: int) -> np.ndarray:
+    _, _, ss = gsp2_plan_query(plan)
+    idx = np.empty(int(ss[k]), dtype=np.int32)
+    _check(load().gsp2_plan_part_index(plan.handle, int(k), _i32(idx)))
+    return idx
+
+
+def gsp2_plan_set_stream(plan: Plan, stream=None):
+    _check(load().gsp2_plan_set_stream(plan.handle, C.c_void_p(_stream_handle(stream))))
+
+
+def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5):
+    o = gsp2_run_options_default()
+    o.max_iter = int(max_iter)
+    o.stop_rule = 1 if stop_rule else 0
+    o.trace_tol = float(trace_tol)
+    keep = None
+    if alpha_seq is not None:
+        keep = np.ascontiguousarray(alpha_seq, dtype=np.int8)
+        o.alpha_mode = GSP2_ALPHA_REPLAY
+        o.n_alpha = int(keep.size)
+        o.alpha_seq = keep.ctypes.data_as(C.POINTER(C.c_int8))
+    return o, keep
+
+
+def run_info_dict(info: gsp2_run_info) -> dict:
+    n = info.n_alpha
+    return {
+        "status": info.status, "status_name": STATUS_NAMES.get(info.status, str(info.status)),
+        "n_products": info.n_products, "n_alpha": n, "result_iterate": info.result_iterate,
+        "eps_min": info.eps_min, "eps_max": info.eps_max, "trace": info.trace,
+        "idempotency": info.idempotency, "alpha": [int(a) for a in info.alpha[:n]],
+        "traces": [float(t) for t in info.traces[:n + 1]],
+        "errors": [float(e) for e in info.errors[:info.n_products]],
+    }
+
+
+def gsp2_density(plan: Plan, H: DeviceCSR, n_occ: float, P_val, max_iter=60, alpha_seq=None,
+                 stop_rule=True, trace_tol=0.5, want_info=True, check=True):
+    """Enqueue one density matrix into P_val (torch float32 on the GPU, nnz_P
+    entries).  With want_info the call waits and returns the run's info dict;
+    with check a failing status raises Gsp2Error."""
+    import torch
+    if P_val.dtype != torch.float32 or not P_val.is_cuda or not P_val.is_contiguous():
+        raise ValueError("P_val must be a contiguous float32 GPU tensor")
+    if P_val.numel() < plan.nnz_P:
+        raise ValueError(f"P_val holds {P_val.numel()} values, the plan needs {plan.nnz_P}")
+    c = H.as_c()
+    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol)
+    info = gsp2_run_info() if want_info else None
+    st = load().gsp2_density(plan.handle, C.byref(c), float(n_occ), C.byref(o), C.c_void_p(P_val.data_ptr()),
+                             C.byref(info) if info is not None else None)
+    del keep
+    msg = load().gsp2_last_error().decode()
+    if check and st != GSP2_OK:
+        raise Gsp2Error(st, msg)
+    if info is None:
+        return {"status": st}
+    d = run_info_dict(info)
+    d["call_status"] = st
+    d["message"] = msg
+    return d
+
+
+def gsp2_run_status(plan: Plan) -> dict:
+    info = gsp2_run_info()
+    st = load().gsp2_run_status(plan.handle, C.byref(info))
+    d = run_info_dict(info)
+    d["call_status"] = st
+    return d
+
+
+def gsp2_plan_destroy(plan: Plan):
+    plan.close()
+
+
+def gsp2_core_halo_host(adj_ptr, adj_col, part, n_parts: int):
+    """Host planning step: (sub_ptr, sub_idx, core_count) for a directed adjacency."""
+    adj_ptr = np.ascontiguousarray(adj_ptr, dtype=np.int64)
+    adj_col = np.ascontiguousarray(adj_col, dtype=np.int32)
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    n = part.size
+    if adj_ptr.size != n + 1:
+        raise ValueError("adj_ptr must have n+1 entries")
+    lib = load()
+    sub_ptr = np.empty(n_parts + 1, dtype=np.int64)
+    _check(lib.gsp2_core_halo_host(n, _i64(adj_ptr), _i32(adj_col), _i32(part), int(n_parts),
+                                   _i64(sub_ptr), None, None))
+    sub_idx = np.empty(int(sub_ptr[-1]), dtype=np.int32)
+    core = np.empty(n_parts, dtype=np.int32)
+    _check(lib.gsp2_core_halo_host(n, _i64(adj_ptr), _i32(adj_col), _i32(part), int(n_parts),
+                                   _i64(sub_ptr), _i32(sub_idx), _i32(core)))
+    return sub_ptr, sub_idx, core

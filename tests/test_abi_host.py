@@ -1,0 +1,116 @@
+"""The C-ABI library without a GPU: it loads, exports every declared symbol,
+and its host planning step matches the oracle's core/halo sets."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import paper_1801_10016_amd as g
+from paper_1801_10016_amd import gsp2 as binding
+from synth.partition import uneven_spatial_partition
+from tests import _pins as pins
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "gsp2.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gsp2_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = g.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(binding.SIGNATURES) == names
+
+
+def test_status_strings_and_defaults():
+    lib = g.load()
+    for code, name in g.STATUS_NAMES.items():
+        assert lib.gsp2_status_string(code).decode() == name
+    o = g.gsp2_run_options_default()
+    assert (o.max_iter, o.alpha_mode, o.n_alpha, o.stop_rule, o.trace_tol) == (60, 0, 0, 1, 0.5)
+
+
+def _as_csr(adj):
+    adj = sp.csr_matrix(adj)
+    return adj.indptr.astype(np.int64), adj.indices.astype(np.int32)
+
+
+def _compare(adj, part, n_parts):
+    ptr, col = _as_csr(adj)
+    sub_ptr, sub_idx, core = g.gsp2_core_halo_host(ptr, col, part, n_parts)
+    cores, halos = oracle.core_halo(oracle.threshold_graph(adj, 0.5), part, n_parts)
+    for k in range(n_parts):
+        got = sub_idx[sub_ptr[k]:sub_ptr[k + 1]]
+        want = np.concatenate([cores[k], halos[k]])
+        assert np.array_equal(got, want), k
+        assert core[k] == len(cores[k])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_core_halo_host_matches_oracle_random(seed):
+    rng = np.random.default_rng(seed)
+    n, k = 200, 7
+    A = (rng.random((n, n)) < 0.03).astype(float)   # directed: the union must be taken
+    part = rng.integers(0, k, n).astype(np.int32)
+    part[:k] = np.arange(k)
+    _compare(sp.csr_matrix(A), part, k)
+
+
+def test_core_halo_host_matches_oracle_water():
+    s = pins.water(64, 0)
+    P, _ = oracle.dense_sp2(s.H, s.n_occ)
+    part = uneven_spatial_partition(s, 8, seed=0)
+    for tau in (1e-5, 1e-3, 1e-2):
+        A = oracle.threshold_graph(P, tau)
+        _compare(A, part, 8)
+
+
+def test_core_halo_host_fig2():
+    # the worked example of Fig. 2 through the library's planner
+    import json
+    fx = json.load(open(os.path.join(ROOT, "tests", "golden", "fig2_corehalo.json")))
+    ix = {v: i for i, v in enumerate(fx["vertices"])}
+    A = np.zeros((6, 6))
+    for a, b in fx["edges"]:
+        A[ix[a], ix[b]] = 1.0          # one orientation only
+    for key in ("a", "b"):
+        case = fx["partitions"][key]
+        part = np.empty(6, dtype=np.int32)
+        for k, members in enumerate(case["parts"]):
+            part[[ix[v] for v in members]] = k
+        ptr, col = _as_csr(A)
+        sub_ptr, _, _ = g.gsp2_core_halo_host(ptr, col, part, 2)
+        sizes = np.diff(sub_ptr)
+        assert sizes.tolist() == case["sizes"]
+        assert int((sizes.astype(np.int64) ** 3).sum()) == case["cost"]
+
+
+def test_core_halo_host_rejects_bad_partitions():
+    ptr = np.array([0, 1, 2, 2], dtype=np.int64)
+    col = np.array([1, 0], dtype=np.int32)
+    with pytest.raises(g.Gsp2Error) as e:
+        g.gsp2_core_halo_host(ptr, col, np.array([0, 0, 2], dtype=np.int32), 3)    # part 1 empty
+    assert e.value.status == binding.GSP2_E_INVALID
+    with pytest.raises(g.Gsp2Error):
+        g.gsp2_core_halo_host(ptr, col, np.array([0, 1, 5], dtype=np.int32), 3)    # id out of range
+    with pytest.raises(g.Gsp2Error):
+        g.gsp2_core_halo_host(ptr, np.array([1, 7], dtype=np.int32), np.array([0, 1, 2], dtype=np.int32), 3)
+
+
+def test_core_halo_host_isolated_vertices_and_self_loops():
+    # self loops and isolated vertices: halos stay empty
+    A = sp.identity(5, format="csr")
+    part = np.array([0, 0, 1, 1, 2], dtype=np.int32)
+    ptr, col = _as_csr(A)
+    sub_ptr, sub_idx, core = g.gsp2_core_halo_host(ptr, col, part, 3)
+    assert np.diff(sub_ptr).tolist() == [2, 2, 1]
+    assert sub_idx.tolist() == [0, 1, 2, 3, 4]

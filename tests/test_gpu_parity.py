@@ -1,0 +1,112 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle on the same inputs.
+
+Bar: ||P_gpu - P_oracle||_F / ||P_oracle||_F <= 1e-5 (FP32 products), index
+sets bit-exact, run-to-run bitwise determinism."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from synth.partition import molecule_partition, uneven_spatial_partition
+from tests import _pins as pins
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1801_10016_amd as g
+    g.load()
+
+
+def _dense_prev(s):
+    return pins.cached(("dense", s.n_mol, s.seed, s.hop_a), lambda: oracle.dense_sp2(s.H, s.n_occ)[0])
+
+
+def _check_parity(s, tau, n_parts, part=None, **kw):
+    from tests._gpu import rel_fro, run_gsp2
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, n_parts, seed=0) if part is None else part
+    ref = oracle.gsp2(s.H, Pp, tau, part, n_parts, s.n_occ)
+    P, run, info, index, vals = run_gsp2(s.H, Pp, tau, part, n_parts, s.n_occ, **kw)
+    print(f"N={s.n} parts={n_parts} tau={tau} s=[{min(ref.sizes)},{max(ref.sizes)}] "
+          f"gpu products={run['n_products']} oracle products={ref.sp2.n_products}", flush=True)
+    assert run["status"] == 0, run
+    assert np.isfinite(vals).all()
+    for k in range(n_parts):
+        assert np.array_equal(index[k], ref.index[k]), k
+    err = rel_fro(P, ref.csc())
+    print(f"  rel_err={err:.3e}", flush=True)
+    assert err <= TOL, err
+    return P, run, ref
+
+
+def test_tiny_config_dense_threshold():
+    # 64 molecules, 384 orbitals, 8 uneven parts, tau = 1e-5 (halos cover nearly all)
+    _check_parity(pins.water(64, 0), 1e-5, 8)
+
+
+@pytest.mark.parametrize("tau", [1e-3, 1e-2])
+def test_tiny_config_truncated_halos(tau):
+    _check_parity(pins.water(64, 0), tau, 8)
+
+
+def test_several_tiles_and_ragged_tail():
+    # 200 molecules: sub-problems of several 128-tiles with a ragged last tile
+    _check_parity(pins.water(200, 1), 1e-4, 6)
+
+
+def test_single_part_is_dense_sp2():
+    s = pins.water(48, 2)
+    part = np.zeros(s.n, dtype=np.int32)
+    P, run, ref = _check_parity(s, 1e-5, 1, part=part)
+    Ps = oracle.eig_projector(s.H, s.n_occ)
+    from tests._gpu import rel_fro
+    assert rel_fro(P, Ps) <= TOL
+
+
+def test_fp32_inputs():
+    import torch
+    _check_parity(pins.water(64, 1), 1e-3, 8, h_dtype=torch.float32, p_dtype=torch.float32)
+
+
+def test_monomers_exact():
+    s = pins.water(40, 3, hop_a=0.0)
+    part = molecule_partition(s)
+    from tests._gpu import rel_fro, run_gsp2
+    P, run, info, index, vals = run_gsp2(s.H, s.H, 1e-5, part, s.n_mol, s.n_occ)
+    assert run["status"] == 0 and info["max_s"] == 6
+    assert rel_fro(P, oracle.eig_projector(s.H, s.n_occ)) <= TOL
+
+
+def test_bitwise_deterministic():
+    from tests._gpu import run_gsp2
+    s = pins.water(64, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 8, seed=0)
+    a = run_gsp2(s.H, Pp, 1e-3, part, 8, s.n_occ)[4]
+    b = run_gsp2(s.H, Pp, 1e-3, part, 8, s.n_occ)[4]
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("seq", [[], [-1], [1], [-1, 1, -1]])
+def test_replayed_prefix_matches_oracle(seq):
+    # replaying a fixed branch prefix isolates the stages: no product (gather
+    # and scatter of eq. (1)), then one or a few products of eq. (2)
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(100, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 3, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, alpha_seq=seq)
+    P, run, info, index, vals = run_gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, alpha_seq=seq, trace_tol=1e9)
+    err = rel_fro(P, ref.csc())
+    print(f"replay {seq}: rel_err={err:.3e} eps=({run['eps_min']:.6f},{run['eps_max']:.6f}) "
+          f"oracle eps={ref.eps}", flush=True)
+    assert abs(run["eps_min"] - ref.eps[0]) <= 1e-12 * abs(ref.eps[0])
+    assert abs(run["eps_max"] - ref.eps[1]) <= 1e-12 * abs(ref.eps[1])
+    assert err <= TOL, err
