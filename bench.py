@@ -1,0 +1,242 @@
+#!/usr/bin/env python3
+"""Time per G-SP2 density matrix on one MI355X.
+
+Workload (defaults): 3,500 synthetic water molecules (21,000 orbitals,
+14,000 occupied states), 128 spatial parts of uneven size (cores drawn
+U[60, 300] orbitals), graph of the previous P thresholded at tau = 1e-5.
+The previous P is the regular (dense, single-part) SP2 density matrix of
+the same H, computed by the library beforehand; it is thresholded on the
+GPU when the plan is built.  Plan construction is timed separately: the
+paper reuses a partition over several MD steps.
+
+A step is one density matrix: Gershgorin bounds, gather of every core+halo
+block with eq. (1), every SP2 product with its trace/branch/stop control,
+and the scatter of core columns into P, replayed from one HIP graph with H
+and P resident in HBM.  Prints one JSON line on stdout; progress goes to
+stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+METRIC = "ms per density matrix P + batched-GEMM TFLOP/s (frac. of MFMA peak) at 10k atoms"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-mol", type=int, default=3500)
+    ap.add_argument("--n-parts", type=int, default=128)
+    ap.add_argument("--core-lo", type=float, default=60.0)
+    ap.add_argument("--core-hi", type=float, default=300.0)
+    ap.add_argument("--tau", type=float, default=1e-5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--max-iter", type=int, default=60)
+    ap.add_argument("--graph", choices=["dense-sp2", "surrogate"], default="dense-sp2",
+                    help="previous P: regular SP2 on the GPU, or the distance-based stand-in")
+    ap.add_argument("--cpu-sample-parts", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def dense_bootstrap(g, torch, Hd, n, n_occ, stream):
+    """Regular SP2 on the whole H (one part, no halo) -> previous P as a device CSR."""
+    part = np.zeros(n, dtype=np.int32)
+    with torch.cuda.stream(stream):
+        with g.gsp2_plan_create(Hd, 0.0, part, 1, stream=stream) as plan:
+            info, _, _ = g.gsp2_plan_query(plan)
+            assert info["nnz_P"] == n * n
+            P = torch.empty(n * n, dtype=torch.float32, device="cuda")
+            run = g.gsp2_density(plan, Hd, n_occ, P)
+            torch.cuda.synchronize()
+    # with a single part every column holds all n rows in ascending order
+    col_ptr = torch.arange(0, n * n + 1, n, dtype=torch.int64, device="cuda")
+    row_idx = torch.arange(n, dtype=torch.int32, device="cuda").repeat(n)
+    return g.DeviceCSR(n, col_ptr, row_idx, P), run
+
+
+def cpu_baseline(system, part, n_parts, tau, n_products, sub_sizes, n_sample):
+    """Time the FP64 oracle's SP2 products on a few parts and scale by sum s^3."""
+    import oracle
+    from synth.locality import surrogate_prev_density
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") == "openblas"]
+                      or [os.cpu_count() or 1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    Q = surrogate_prev_density(system)
+    adj = oracle.threshold_graph(Q, tau)
+    cores, halos = oracle.core_halo(adj, part, n_parts)
+    sizes = np.array([len(c) + len(h) for c, h in zip(cores, halos)])
+    order = np.argsort(sizes)
+    pick = [int(order[int(q * (n_parts - 1))]) for q in np.linspace(0.0, 1.0, n_sample)]
+    emin, emax = oracle.gershgorin_bounds(system.H)
+    X0 = []
+    for k in pick:
+        idx = oracle.subproblem_index(cores[k], halos[k])
+        X0.append(oracle.initial_guess(system.H[idx][:, idx].toarray(), emin, emax))
+    seq = [(-1) ** t for t in range(n_products)]
+    t0 = time.perf_counter()
+    oracle.sp2_blocks(X0, [len(cores[k]) for k in pick], system.n_occ, alpha_seq=seq, trace_tol=1e30)
+    dt = time.perf_counter() - t0
+    s3_sample = float(sum(sizes[k] ** 3 for k in pick))
+    s3_all = float(np.sum(np.asarray(sub_sizes, dtype=np.float64) ** 3))
+    ms = dt * 1e3 * s3_all / s3_sample
+    return {"value": ms, "unit": "ms/P", "cores": int(threads), "kind": "oracle",
+            "sample": (f"FP64 numpy/OpenBLAS SP2 products of {len(pick)} of {n_parts} parts "
+                       f"(s = {', '.join(str(int(sizes[k])) for k in pick)}), {n_products} products each, "
+                       f"{dt:.1f} s, scaled by sum_k s_k^3 of the timed workload")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+    import torch
+
+    import paper_1801_10016_amd as g
+    from synth.locality import surrogate_prev_density
+    from synth.partition import uneven_spatial_partition
+    from synth.water import make_water
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    g.load()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    t = time.perf_counter()
+    system = make_water(args.n_mol, seed=args.seed)
+    n, n_occ = system.n, system.n_occ
+    part = uneven_spatial_partition(system, args.n_parts, args.core_lo, args.core_hi, seed=args.seed)
+    log(f"system: {args.n_mol} molecules, N={n}, nnz(H)={system.H.nnz}, {time.perf_counter() - t:.1f} s")
+    Hd = g.csr_to_device(system.H)
+
+    t = time.perf_counter()
+    if args.graph == "dense-sp2":
+        Pprev, boot = dense_bootstrap(g, torch, Hd, n, n_occ, stream)
+        boot_desc = f"regular SP2 of H on the GPU ({boot['n_products']} products)"
+    else:
+        Pprev = g.csr_to_device(surrogate_prev_density(system))
+        boot_desc = "distance-based stand-in for the previous P"
+    boot_s = time.perf_counter() - t
+    log(f"previous P: {boot_desc}, {boot_s:.1f} s")
+
+    t = time.perf_counter()
+    with torch.cuda.stream(stream):
+        plan = g.gsp2_plan_create(Pprev, args.tau, part, args.n_parts, stream=stream)
+    plan_s = time.perf_counter() - t
+    del Pprev
+    torch.cuda.empty_cache()
+    info, core_sizes, sub_sizes = g.gsp2_plan_query(plan)
+    log(f"plan: s in [{info['min_s']}, {info['max_s']}], sum s^3 = {info['sum_s3']:.3e}, "
+        f"tiles/product = {info['n_tiles']}, workspace = {info['workspace_bytes'] / 2**30:.2f} GiB, {plan_s:.1f} s")
+    P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
+
+    # first run finds where the stop rule fires; later runs form exactly that
+    # many products (the same stop fires at the same product), so no empty
+    # launches follow the stop
+    with torch.cuda.stream(stream):
+        first = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=args.max_iter)
+    n_prod = first["n_products"]
+    log(f"first run: status {first['status_name']}, {n_prod} products, Tr P = {first['trace']:.6f}")
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            w = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=True)
+            assert w["status"] == 0 and w["n_products"] == n_prod, w
+            log(f"warmup {i + 1}/{args.warmup}: {g.gsp2_run_timing(plan)['total_ms']:.1f} ms")
+
+        totals, product_ms, setup, sp2, scatter = [], [], [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=True, want_info=False)
+            tm = g.gsp2_run_timing(plan)
+            totals.append(tm["total_ms"]); product_ms += tm["product_ms"]
+            setup.append(tm["setup_ms"]); sp2.append(tm["sp2_ms"]); scatter.append(tm["scatter_ms"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        last = g.gsp2_run_status(plan)
+    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.1f} ms per P")
+    assert last["status"] == 0, last
+
+    s = np.asarray(sub_sizes, dtype=np.float64)
+    syrk_flops = float(np.sum(s * s * (s + 1.0)))        # distinct entries s(s+1)/2, 2s flops each
+    gemm_flops = float(np.sum(2.0 * s ** 3))
+    avg_prod_ms = statistics.fmean(product_ms)
+    achieved = syrk_flops / (avg_prod_ms * 1e-3) / 1e12
+    ms_per_step = wall * 1e3 / args.steps
+    sp2_med = statistics.median(sp2)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: timing the FP64 oracle on a sample of parts")
+        cpu = cpu_baseline(system, part, args.n_parts, args.tau, n_prod, sub_sizes, args.cpu_sample_parts)
+        log(f"cpu baseline: {cpu['value']:.0f} ms/P on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC,
+        "value": round(ms_per_step, 3),
+        "unit": "ms/P",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"G-SP2 density matrix of {args.n_mol} synthetic water molecules ({n} orbitals), "
+                         f"{args.n_parts} uneven spatial parts, graph of the previous P at tau={args.tau:g}"),
+            "n_mol": args.n_mol, "n_orbitals": n, "n_occ": n_occ, "n_parts": args.n_parts,
+            "tau": args.tau, "previous_P": boot_desc, "s_min": info["min_s"], "s_max": info["max_s"],
+            "s_mean": round(float(s.mean()), 1), "sum_s3": info["sum_s3"], "n_products": n_prod,
+            "tiles_per_product": info["n_tiles"], "precision": "FP32 MFMA products, FP64 traces",
+        },
+        "batched_gemm_tflops": round(n_prod * gemm_flops / (sp2_med * 1e-3) / 1e12, 2),
+        "batched_gemm_tflops_convention": "n_products * sum_k 2 s_k^3 / SP2-phase time (GEMM convention)",
+        "roofline": {
+            "bound": "mfma", "kernel": "k_sp2_step",
+            "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+            "flops_per_launch": syrk_flops, "avg_launch_ms": round(avg_prod_ms, 4),
+            "flops_convention": "symmetric product: sum_k s_k^2 (s_k + 1) per launch (one launch = one product)",
+        },
+        "phase_ms": {"setup": round(statistics.median(setup), 3), "sp2": round(sp2_med, 3),
+                     "scatter": round(statistics.median(scatter), 3),
+                     "event_total_median": round(statistics.median(totals), 3)},
+        "plan_ms": round(plan_s * 1e3, 1),
+        "previous_P_s": round(boot_s, 2),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -96,6 +96,8 @@ typedef struct {
     int32_t stop_rule;         /* trace mode: 1 = stop when idempotency stops improving
                                   (default); 0 = always form max_iter products */
     double trace_tol;          /* replay mode: allowed |Tr P - n_occ|, default 0.5 */
+    int32_t timing;            /* 1 = record HIP events around every phase and product
+                                  (read with gsp2_run_timing); default 0 */
 } gsp2_run_options;
 
 #define GSP2_MAX_ITER 100
@@ -113,6 +115,16 @@ typedef struct {
     double traces[GSP2_MAX_ITER + 1];      /* Tr[X_t], t = 0 .. n_alpha */
     double errors[GSP2_MAX_ITER];          /* e_t for each product t */
 } gsp2_run_info;
+
+/* Device times of the last timed run (gsp2_run_options.timing = 1). */
+typedef struct {
+    int32_t n_products;                    /* products formed (entries of product_ms) */
+    float setup_ms;                        /* Gershgorin bounds, X0 gather, first trace */
+    float sp2_ms;                          /* all products with their control steps */
+    float scatter_ms;                      /* core columns into P */
+    float total_ms;                        /* first to last kernel of the run */
+    float product_ms[GSP2_MAX_ITER];       /* the product kernel of product t alone */
+} gsp2_timing;
 
 /* Human-readable name of a status code (static string). */
 const char *gsp2_status_string(gsp2_status s);
@@ -188,6 +200,11 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
  */
 gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ,
                          const gsp2_run_options *run, float *P_val, gsp2_run_info *info);
+
+/* Wait for the last gsp2_density on this plan and report its device times,
+ * measured with HIP events on the plan's stream.  Errors: GSP2_E_INVALID
+ * when the last run was not timed. */
+gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out);
 
 /* Wait for the last gsp2_density on this plan and report it. */
 gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info);

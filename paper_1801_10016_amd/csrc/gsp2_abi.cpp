@@ -148,9 +148,11 @@ struct GraphKey {
     int32_t h_dtype = -1;
     float *p_val = nullptr;
     RunParams rp{};
+    bool timing = false;
     bool operator==(const GraphKey &o) const {
         return h_ptr == o.h_ptr && h_col == o.h_col && h_val == o.h_val && h_nnz == o.h_nnz &&
-               h_dtype == o.h_dtype && p_val == o.p_val && std::memcmp(&rp, &o.rp, sizeof(rp)) == 0;
+               h_dtype == o.h_dtype && p_val == o.p_val && timing == o.timing &&
+               std::memcmp(&rp, &o.rp, sizeof(rp)) == 0;
     }
 };
 
@@ -182,9 +184,27 @@ struct gsp2_plan_s {
     bool have_graph = false;
     RunParams last_rp{};
     bool ran = false;
+    bool last_timed = false;
+    RunEvents ev{};
+    bool have_events = false;
+
+    void make_events() {
+        if (have_events) return;
+        check_hip(hipEventCreate(&ev.begin), "event");
+        check_hip(hipEventCreate(&ev.setup_end), "event");
+        check_hip(hipEventCreate(&ev.sp2_end), "event");
+        check_hip(hipEventCreate(&ev.end), "event");
+        for (auto &x : ev.step) check_hip(hipEventCreate(&x), "event");
+        have_events = true;
+    }
 
     ~gsp2_plan_s() {
         if (stream) (void)hipStreamSynchronize(stream); else (void)hipDeviceSynchronize();
+        if (have_events) {
+            (void)hipEventDestroy(ev.begin); (void)hipEventDestroy(ev.setup_end);
+            (void)hipEventDestroy(ev.sp2_end); (void)hipEventDestroy(ev.end);
+            for (auto &x : ev.step) (void)hipEventDestroy(x);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         for (void *p : dev_ptrs) (void)hipFree(p);
@@ -224,6 +244,7 @@ gsp2_status gsp2_run_options_default(gsp2_run_options *opt) {
         opt->n_alpha = 0;
         opt->stop_rule = 1;
         opt->trace_tol = 0.5;
+        opt->timing = 0;
     });
 }
 
@@ -569,17 +590,19 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         }
         GraphKey k;
         k.h_ptr = H->row_ptr; k.h_col = H->col; k.h_val = H->val; k.h_nnz = H->nnz; k.h_dtype = H->dtype;
-        k.p_val = P_val; k.rp = rp;
+        k.p_val = P_val; k.rp = rp; k.timing = o.timing != 0;
+        const RunEvents *evp = nullptr;
+        if (o.timing) { plan->make_events(); evp = &plan->ev; }
         const bool eager = plan->stream == nullptr || std::getenv("GSP2_EAGER") != nullptr;
         if (eager) {
-            check_hip(launch_density(plan->dp, *H, rp, P_val, plan->stream), "launch density");
+            check_hip(launch_density(plan->dp, *H, rp, P_val, plan->stream, evp), "launch density");
         } else {
             if (!plan->have_graph || !(plan->key == k)) {
                 if (plan->exec) { check_hip(hipGraphExecDestroy(plan->exec), "graph destroy"); plan->exec = nullptr; }
                 if (plan->graph) { check_hip(hipGraphDestroy(plan->graph), "graph destroy"); plan->graph = nullptr; }
                 plan->have_graph = false;
                 check_hip(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal), "begin capture");
-                const hipError_t le = launch_density(plan->dp, *H, rp, P_val, plan->stream);
+                const hipError_t le = launch_density(plan->dp, *H, rp, P_val, plan->stream, evp);
                 hipGraph_t g = nullptr;
                 const hipError_t ce = hipStreamEndCapture(plan->stream, &g);
                 check_hip(le, "launch density (capture)");
@@ -593,6 +616,7 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         }
         plan->last_rp = rp;
         plan->ran = true;
+        plan->last_timed = o.timing != 0;
     });
     if (st != GSP2_OK || !info) return st;
     return collect(plan, info);
@@ -602,6 +626,26 @@ gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info) {
     if (!plan) { g_last_error = "null plan"; return GSP2_E_INVALID; }
     if (!plan->ran) { g_last_error = "no run on this plan"; return GSP2_E_INVALID; }
     return collect(plan, info);
+}
+
+gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out) {
+    return guarded([&] {
+        if (!plan || !out) fail(GSP2_E_INVALID, "null argument");
+        if (!plan->ran || !plan->last_timed) fail(GSP2_E_INVALID, "the last run on this plan was not timed");
+        check_hip(hipMemcpyAsync(plan->h_state, plan->dp.state, sizeof(RunState), hipMemcpyDeviceToHost,
+                                 plan->stream), "copy run state");
+        check_hip(hipStreamSynchronize(plan->stream), "timed run");
+        std::memset(out, 0, sizeof(*out));
+        const RunEvents &e = plan->ev;
+        check_hip(hipEventElapsedTime(&out->setup_ms, e.begin, e.setup_end), "elapsed");
+        check_hip(hipEventElapsedTime(&out->sp2_ms, e.setup_end, e.sp2_end), "elapsed");
+        check_hip(hipEventElapsedTime(&out->scatter_ms, e.sp2_end, e.end), "elapsed");
+        check_hip(hipEventElapsedTime(&out->total_ms, e.begin, e.end), "elapsed");
+        const int np = std::min(plan->h_state->n_products, plan->last_rp.n_steps);
+        out->n_products = np;
+        for (int t = 0; t < np; ++t)
+            check_hip(hipEventElapsedTime(&out->product_ms[t], e.step[2 * t], e.step[2 * t + 1]), "elapsed");
+    });
 }
 
 void gsp2_plan_destroy(gsp2_plan plan) { delete plan; }

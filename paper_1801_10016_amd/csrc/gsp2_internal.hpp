@@ -97,11 +97,18 @@ struct DevicePlan {
     RunState *state;
 };
 
+// Optional event records of a timed run.  step[2t] / step[2t+1] bracket the
+// product kernel of product t.
+struct RunEvents {
+    hipEvent_t begin, setup_end, sp2_end, end;
+    hipEvent_t step[2 * GSP2_MAX_ITER];
+};
+
 // Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.
 hipError_t launch_threshold_count(const gsp2_csr &P, double tau, int32_t *counts, hipStream_t s);
 hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *out_ptr,
                                  int32_t *out_col, hipStream_t s);
 hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp,
-                          float *P_val, hipStream_t s);
+                          float *P_val, hipStream_t s, const RunEvents *ev);
 
 }  // namespace gsp2

@@ -42,7 +42,8 @@ class gsp2_plan_info(C.Structure):
 
 class gsp2_run_options(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("alpha_mode", C.c_int32), ("alpha_seq", C.POINTER(C.c_int8)),
-                ("n_alpha", C.c_int32), ("stop_rule", C.c_int32), ("trace_tol", C.c_double)]
+                ("n_alpha", C.c_int32), ("stop_rule", C.c_int32), ("trace_tol", C.c_double),
+                ("timing", C.c_int32)]
 
 
 class gsp2_run_info(C.Structure):
@@ -51,6 +52,11 @@ class gsp2_run_info(C.Structure):
                 ("trace", C.c_double), ("idempotency", C.c_double),
                 ("alpha", C.c_int8 * GSP2_MAX_ITER), ("traces", C.c_double * (GSP2_MAX_ITER + 1)),
                 ("errors", C.c_double * GSP2_MAX_ITER)]
+
+
+class gsp2_timing(C.Structure):
+    _fields_ = [("n_products", C.c_int32), ("setup_ms", C.c_float), ("sp2_ms", C.c_float),
+                ("scatter_ms", C.c_float), ("total_ms", C.c_float), ("product_ms", C.c_float * GSP2_MAX_ITER)]
 
 
 _PLAN = C.c_void_p
@@ -69,6 +75,7 @@ SIGNATURES = {
     "gsp2_density": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.c_double, C.POINTER(gsp2_run_options),
                                C.c_void_p, C.POINTER(gsp2_run_info)]),
     "gsp2_run_status": (C.c_int, [_PLAN, C.POINTER(gsp2_run_info)]),
+    "gsp2_run_timing": (C.c_int, [_PLAN, C.POINTER(gsp2_timing)]),
     "gsp2_plan_destroy": (None, [_PLAN]),
     "gsp2_core_halo_host": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int64),
@@ -226,9 +233,10 @@ def gsp2_plan_set_stream(plan: Plan, stream=None):
     _check(load().gsp2_plan_set_stream(plan.handle, C.c_void_p(_stream_handle(stream))))
 
 
-def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5):
+def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5, timing=False):
     o = gsp2_run_options_default()
     o.max_iter = int(max_iter)
+    o.timing = 1 if timing else 0
     o.stop_rule = 1 if stop_rule else 0
     o.trace_tol = float(trace_tol)
     keep = None
@@ -253,7 +261,7 @@ def run_info_dict(info: gsp2_run_info) -> dict:
 
 
 def gsp2_density(plan: Plan, H: DeviceCSR, n_occ: float, P_val, max_iter=60, alpha_seq=None,
-                 stop_rule=True, trace_tol=0.5, want_info=True, check=True):
+                 stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False):
     """Enqueue one density matrix into P_val (torch float32 on the GPU, nnz_P
     entries).  With want_info the call waits and returns the run's info dict;
     with check a failing status raises Gsp2Error."""
@@ -263,7 +271,7 @@ def gsp2_density(plan: Plan, H: DeviceCSR, n_occ: float, P_val, max_iter=60, alp
     if P_val.numel() < plan.nnz_P:
         raise ValueError(f"P_val holds {P_val.numel()} values, the plan needs {plan.nnz_P}")
     c = H.as_c()
-    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol)
+    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing)
     info = gsp2_run_info() if want_info else None
     st = load().gsp2_density(plan.handle, C.byref(c), float(n_occ), C.byref(o), C.c_void_p(P_val.data_ptr()),
                              C.byref(info) if info is not None else None)
@@ -285,6 +293,14 @@ def gsp2_run_status(plan: Plan) -> dict:
     d = run_info_dict(info)
     d["call_status"] = st
     return d
+
+
+def gsp2_run_timing(plan: Plan) -> dict:
+    t = gsp2_timing()
+    _check(load().gsp2_run_timing(plan.handle, C.byref(t)))
+    return {"n_products": t.n_products, "setup_ms": t.setup_ms, "sp2_ms": t.sp2_ms,
+            "scatter_ms": t.scatter_ms, "total_ms": t.total_ms,
+            "product_ms": [float(x) for x in t.product_ms[:t.n_products]]}
 
 
 def gsp2_plan_destroy(plan: Plan):
