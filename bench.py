@@ -53,8 +53,14 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=60)
     ap.add_argument("--graph", choices=["dense-sp2", "surrogate"], default="dense-sp2",
                     help="previous P: regular SP2 on the GPU, or the distance-based stand-in")
-    ap.add_argument("--cpu-sample-parts", type=int, default=3)
+    ap.add_argument("--cpu-sample-parts", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    ap.add_argument("--save-state", help="write the thresholded graph and product count to this .npz")
+    ap.add_argument("--load-state", help="reuse a graph and product count saved by --save-state "
+                    "(skips the previous-P computation and the first, stop-finding run)")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="only run a plain device copy of this many GiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -72,6 +78,32 @@ def dense_bootstrap(g, torch, Hd, n, n_occ, stream):
     col_ptr = torch.arange(0, n * n + 1, n, dtype=torch.int64, device="cuda")
     row_idx = torch.arange(n, dtype=torch.int32, device="cuda").repeat(n)
     return g.DeviceCSR(n, col_ptr, row_idx, P), run
+
+
+def threshold_on_host(Pprev, tau):
+    """Graph of a device CSR thresholded at tau, as host CSR arrays (for --save-state)."""
+    import scipy.sparse as sp
+    ptr = Pprev.row_ptr.cpu().numpy()
+    col = Pprev.col.cpu().numpy()
+    n = Pprev.n
+    keep = np.abs(Pprev.val.double().cpu().numpy()) > tau
+    rows = np.repeat(np.arange(n), np.diff(ptr))
+    keep &= rows != col
+    A = sp.csr_matrix((np.ones(int(keep.sum()), dtype=np.int8), (rows[keep], col[keep])), shape=(n, n))
+    A.sort_indices()
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32)
+
+
+def copy_probe(torch, gib):
+    """A plain device-to-device copy of known size, for scaling HBM counters."""
+    n = int(gib * 2**30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "copies": 3}))
+    return 0
 
 
 def cpu_baseline(system, part, n_parts, tau, n_products, sub_sizes, n_sample):
@@ -126,6 +158,8 @@ def main():
         return 2
     g.load()
     torch.cuda.set_device(0)
+    if args.copy_probe_gib > 0:
+        return copy_probe(torch, args.copy_probe_gib)
     stream = torch.cuda.Stream()
     t = time.perf_counter()
     system = make_water(args.n_mol, seed=args.seed)
@@ -135,19 +169,33 @@ def main():
     Hd = g.csr_to_device(system.H)
 
     t = time.perf_counter()
-    if args.graph == "dense-sp2":
+    saved = None
+    if args.load_state:
+        saved = np.load(args.load_state)
+        # the saved graph as a 0/1 matrix: thresholding it at 0.5 gives the same graph
+        adj_ptr, adj_col = saved["adj_ptr"], saved["adj_col"]
+        Pprev = g.DeviceCSR(n, torch.as_tensor(adj_ptr).cuda(), torch.as_tensor(adj_col).cuda(),
+                            torch.ones(len(adj_col), dtype=torch.float32, device="cuda"))
+        tau = 0.5
+        boot_desc = str(saved["previous_P"])
+    elif args.graph == "dense-sp2":
         Pprev, boot = dense_bootstrap(g, torch, Hd, n, n_occ, stream)
         boot_desc = f"regular SP2 of H on the GPU ({boot['n_products']} products)"
+        tau = args.tau
     else:
         Pprev = g.csr_to_device(surrogate_prev_density(system))
         boot_desc = "distance-based stand-in for the previous P"
+        tau = args.tau
     boot_s = time.perf_counter() - t
     log(f"previous P: {boot_desc}, {boot_s:.1f} s")
 
     t = time.perf_counter()
     with torch.cuda.stream(stream):
-        plan = g.gsp2_plan_create(Pprev, args.tau, part, args.n_parts, stream=stream)
+        plan = g.gsp2_plan_create(Pprev, tau, part, args.n_parts, stream=stream)
     plan_s = time.perf_counter() - t
+    if args.save_state:
+        adj_ptr, adj_col = threshold_on_host(Pprev, args.tau)
+        np.savez(args.save_state, adj_ptr=adj_ptr, adj_col=adj_col, previous_P=boot_desc)
     del Pprev
     torch.cuda.empty_cache()
     info, core_sizes, sub_sizes = g.gsp2_plan_query(plan)
@@ -155,32 +203,46 @@ def main():
         f"tiles/product = {info['n_tiles']}, workspace = {info['workspace_bytes'] / 2**30:.2f} GiB, {plan_s:.1f} s")
     P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
 
-    # first run finds where the stop rule fires; later runs form exactly that
-    # many products (the same stop fires at the same product), so no empty
-    # launches follow the stop
-    with torch.cuda.stream(stream):
-        first = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=args.max_iter)
-    n_prod = first["n_products"]
-    log(f"first run: status {first['status_name']}, {n_prod} products, Tr P = {first['trace']:.6f}")
+    # the first run finds where the stop rule fires; later runs form exactly
+    # that many products (the same stop fires at the same product), so no
+    # empty launches follow the stop
+    if saved is not None:
+        n_prod = int(saved["n_products"])
+    else:
+        with torch.cuda.stream(stream):
+            first = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=args.max_iter)
+        n_prod = first["n_products"]
+        log(f"first run: status {first['status_name']}, {n_prod} products, Tr P = {first['trace']:.6f}")
+    if args.save_state:
+        with np.load(args.save_state) as z:
+            d = dict(z)
+        np.savez(args.save_state, n_products=n_prod, **d)
+        log(f"state saved to {args.save_state}")
+    timed = not args.no_kernel_timing
     with torch.cuda.stream(stream):
         for i in range(args.warmup):
-            w = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=True)
+            w = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=timed)
             assert w["status"] == 0 and w["n_products"] == n_prod, w
-            log(f"warmup {i + 1}/{args.warmup}: {g.gsp2_run_timing(plan)['total_ms']:.1f} ms")
+            log(f"warmup {i + 1}/{args.warmup}" +
+                (f": {g.gsp2_run_timing(plan)['total_ms']:.1f} ms" if timed else ""))
 
         totals, product_ms, setup, sp2, scatter = [], [], [], [], []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
-            g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=True, want_info=False)
-            tm = g.gsp2_run_timing(plan)
-            totals.append(tm["total_ms"]); product_ms += tm["product_ms"]
-            setup.append(tm["setup_ms"]); sp2.append(tm["sp2_ms"]); scatter.append(tm["scatter_ms"])
+            g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=timed, want_info=False)
+            if timed:
+                tm = g.gsp2_run_timing(plan)
+                totals.append(tm["total_ms"]); product_ms += tm["product_ms"]
+                setup.append(tm["setup_ms"]); sp2.append(tm["sp2_ms"]); scatter.append(tm["scatter_ms"])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         last = g.gsp2_run_status(plan)
     log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.1f} ms per P")
     assert last["status"] == 0, last
+    if not timed:
+        product_ms, setup, sp2, scatter, totals = [float("nan")], [float("nan")], [wall * 1e3 / args.steps], \
+            [float("nan")], [float("nan")]
 
     s = np.asarray(sub_sizes, dtype=np.float64)
     syrk_flops = float(np.sum(s * s * (s + 1.0)))        # distinct entries s(s+1)/2, 2s flops each
@@ -230,6 +292,7 @@ def main():
                      "scatter": round(statistics.median(scatter), 3),
                      "event_total_median": round(statistics.median(totals), 3)},
         "plan_ms": round(plan_s * 1e3, 1),
+        "plan_info": {k: info[k] for k in ("nnz_graph", "nnz_P", "sum_s", "workspace_bytes")},
         "previous_P_s": round(boot_s, 2),
         "cpu_baseline": cpu,
     }

@@ -194,6 +194,8 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
  *  P_val   device, nnz_P floats in the order of gsp2_plan_pattern; caller-owned.
  *  info    nullable.  When given, the call waits for the result and returns
  *          the run's status; otherwise it returns after enqueueing.
+ * All kernels of the run form one HIP graph, built on the first call and
+ * replayed while H's arrays, P_val, n_occ and the options stay the same.
  * Errors: GSP2_E_INVALID (arguments, non-finite H, eps_max <= eps_min),
  * GSP2_E_NOT_CONVERGED, GSP2_E_WRONG_TRACE, GSP2_E_HIP.  On error the
  * contents of P_val are unspecified.

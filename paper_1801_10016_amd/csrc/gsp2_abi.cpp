@@ -593,21 +593,20 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         k.p_val = P_val; k.rp = rp; k.timing = o.timing != 0;
         const RunEvents *evp = nullptr;
         if (o.timing) { plan->make_events(); evp = &plan->ev; }
-        const bool eager = plan->stream == nullptr || std::getenv("GSP2_EAGER") != nullptr;
+        const bool eager = std::getenv("GSP2_EAGER") != nullptr;
         if (eager) {
-            check_hip(launch_density(plan->dp, *H, rp, P_val, plan->stream, evp), "launch density");
+            Recorder rec;
+            rec.stream = plan->stream;
+            check_hip(launch_density(plan->dp, *H, rp, P_val, rec, evp), "launch density");
         } else {
             if (!plan->have_graph || !(plan->key == k)) {
                 if (plan->exec) { check_hip(hipGraphExecDestroy(plan->exec), "graph destroy"); plan->exec = nullptr; }
                 if (plan->graph) { check_hip(hipGraphDestroy(plan->graph), "graph destroy"); plan->graph = nullptr; }
                 plan->have_graph = false;
-                check_hip(hipStreamBeginCapture(plan->stream, hipStreamCaptureModeThreadLocal), "begin capture");
-                const hipError_t le = launch_density(plan->dp, *H, rp, P_val, plan->stream, evp);
-                hipGraph_t g = nullptr;
-                const hipError_t ce = hipStreamEndCapture(plan->stream, &g);
-                check_hip(le, "launch density (capture)");
-                check_hip(ce, "end capture");
-                plan->graph = g;
+                check_hip(hipGraphCreate(&plan->graph, 0), "graph create");
+                Recorder rec;
+                rec.graph = plan->graph;
+                check_hip(launch_density(plan->dp, *H, rp, P_val, rec, evp), "build graph");
                 check_hip(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0), "graph instantiate");
                 plan->key = k;
                 plan->have_graph = true;

@@ -104,11 +104,49 @@ struct RunEvents {
     hipEvent_t step[2 * GSP2_MAX_ITER];
 };
 
-// Launchers (kernels.hip).  All enqueue on `stream` and return the launch error.
+// Sink for the kernels and event records of one run: launched directly on a
+// stream (graph == nullptr), or appended as a linear chain of nodes to a HIP
+// graph built explicitly (event-record nodes keep their timestamps there).
+struct Recorder {
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphNode_t last = nullptr;
+    hipError_t err = hipSuccess;
+
+    void add_kernel(const void *func, dim3 grid, dim3 block, void **args) {
+        if (err != hipSuccess) return;
+        if (!graph) {
+            err = hipLaunchKernel(func, grid, block, args, 0, stream);
+            return;
+        }
+        hipKernelNodeParams p{};
+        p.func = const_cast<void *>(func);
+        p.gridDim = grid;
+        p.blockDim = block;
+        p.sharedMemBytes = 0;
+        p.kernelParams = args;
+        p.extra = nullptr;
+        hipGraphNode_t node = nullptr;
+        err = hipGraphAddKernelNode(&node, graph, last ? &last : nullptr, last ? 1 : 0, &p);
+        if (err == hipSuccess) last = node;
+    }
+    void add_event(hipEvent_t e) {
+        if (err != hipSuccess || !e) return;
+        if (!graph) {
+            err = hipEventRecord(e, stream);
+            return;
+        }
+        hipGraphNode_t node = nullptr;
+        err = hipGraphAddEventRecordNode(&node, graph, last ? &last : nullptr, last ? 1 : 0, e);
+        if (err == hipSuccess) last = node;
+    }
+};
+
+// Launchers (kernels.hip).  The threshold launchers enqueue on `stream`.
 hipError_t launch_threshold_count(const gsp2_csr &P, double tau, int32_t *counts, hipStream_t s);
 hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *out_ptr,
                                  int32_t *out_col, hipStream_t s);
 hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp,
-                          float *P_val, hipStream_t s, const RunEvents *ev);
+                          float *P_val, Recorder &rec, const RunEvents *ev);
 
 }  // namespace gsp2

@@ -9,6 +9,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <tuple>
+#include <utility>
+
 #include "gsp2_internal.hpp"
 
 namespace gsp2 {
@@ -500,36 +503,45 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const PartDesc *__restrict__
     for (int t = lane; t < pd.s; t += kWave) out[t] = Xr[perm[t]];
 }
 
+// Hand a kernel and its arguments (converted to the kernel's parameter types)
+// to the recorder; the recorder copies them at launch or node creation.
+template <typename... KArgs, std::size_t... I, typename... Args>
+void record_impl(Recorder &rec, void (*f)(KArgs...), dim3 grid, dim3 block, std::index_sequence<I...>,
+                 Args &&...args) {
+    std::tuple<KArgs...> vals(std::forward<Args>(args)...);
+    void *ptrs[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1] = {static_cast<void *>(&std::get<I>(vals))...};
+    rec.add_kernel(reinterpret_cast<const void *>(f), grid, block, ptrs);
+}
+template <typename... KArgs, typename... Args>
+void record(Recorder &rec, void (*f)(KArgs...), dim3 grid, dim3 block, Args &&...args) {
+    record_impl(rec, f, grid, block, std::index_sequence_for<KArgs...>{}, std::forward<Args>(args)...);
+}
+
 template <typename T>
 hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, float *P_val,
-                         hipStream_t s, const RunEvents *ev) {
+                         Recorder &rec, const RunEvents *ev) {
     const T *hv = static_cast<const T *>(H.val);
-    hipError_t e = hipSuccess;
-    auto mark = [&](hipEvent_t x) {
-        if (ev && e == hipSuccess) e = hipEventRecord(x, s);
-    };
-    mark(ev ? ev->begin : nullptr);
-    hipLaunchKernelGGL(k_gershgorin<T>, dim3(dp.gersh_blocks), dim3(kBlock), 0, s, H.row_ptr, H.col, hv, dp.n,
-                       dp.gersh_partials);
-    hipLaunchKernelGGL(k_run_init, dim3(1), dim3(kBlock), 0, s, dp.gersh_partials, dp.gersh_blocks, rp, dp.state);
-    hipLaunchKernelGGL(k_gather_x0<T>, dim3(dp.n_chunks), dim3(kBlock), 0, s, H.row_ptr, H.col, hv, dp.parts,
-                       dp.chunks, dp.idx, dp.buf[0], dp.state, dp.x0_partials);
-    hipLaunchKernelGGL(k_run_start, dim3(1), dim3(kBlock), 0, s, dp.x0_partials, dp.n_chunks, dp.state);
-    mark(ev ? ev->setup_end : nullptr);
+    const dim3 blk(kBlock);
+    if (ev) rec.add_event(ev->begin);
+    record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.gersh_partials);
+    record(rec, k_run_init, dim3(1), blk, dp.gersh_partials, dp.gersh_blocks, rp, dp.state);
+    record(rec, k_gather_x0<T>, dim3(dp.n_chunks), blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx,
+           dp.buf[0], dp.state, dp.x0_partials);
+    record(rec, k_run_start, dim3(1), blk, dp.x0_partials, dp.n_chunks, dp.state);
+    if (ev) rec.add_event(ev->setup_end);
     for (int it = 0; it < rp.n_steps; ++it) {
-        mark(ev ? ev->step[2 * it] : nullptr);
-        hipLaunchKernelGGL(k_sp2_step, dim3(dp.n_tiles), dim3(kBlock), 0, s, dp.tiles, dp.parts, dp.buf[0],
-                           dp.buf[1], dp.state, dp.diag_partials);
-        mark(ev ? ev->step[2 * it + 1] : nullptr);
-        hipLaunchKernelGGL(k_sp2_decide, dim3(1), dim3(kBlock), 0, s, dp.diag_partials, dp.n_diag, dp.state);
+        if (ev) rec.add_event(ev->step[2 * it]);
+        record(rec, k_sp2_step, dim3(dp.n_tiles), blk, dp.tiles, dp.parts, dp.buf[0], dp.buf[1], dp.state,
+               dp.diag_partials);
+        if (ev) rec.add_event(ev->step[2 * it + 1]);
+        record(rec, k_sp2_decide, dim3(1), blk, dp.diag_partials, dp.n_diag, dp.state);
     }
-    mark(ev ? ev->sp2_end : nullptr);
+    if (ev) rec.add_event(ev->sp2_end);
     const int wpb = kBlock / kWave;
-    hipLaunchKernelGGL(k_scatter, dim3((dp.n + wpb - 1) / wpb), dim3(kBlock), 0, s, dp.parts, dp.perm, dp.col_ptr,
-                       dp.col_part, dp.col_local, dp.n, dp.buf[0], dp.buf[1], dp.state, P_val);
-    mark(ev ? ev->end : nullptr);
-    if (e != hipSuccess) return e;
-    return hipGetLastError();
+    record(rec, k_scatter, dim3((dp.n + wpb - 1) / wpb), blk, dp.parts, dp.perm, dp.col_ptr, dp.col_part,
+           dp.col_local, dp.n, dp.buf[0], dp.buf[1], dp.state, P_val);
+    if (ev) rec.add_event(ev->end);
+    return rec.err;
 }
 
 }  // namespace
@@ -560,9 +572,9 @@ hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *o
 }
 
 hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, float *P_val,
-                          hipStream_t s, const RunEvents *ev) {
-    if (H.dtype == GSP2_F64) return density_typed<double>(dp, H, rp, P_val, s, ev);
-    return density_typed<float>(dp, H, rp, P_val, s, ev);
+                          Recorder &rec, const RunEvents *ev) {
+    if (H.dtype == GSP2_F64) return density_typed<double>(dp, H, rp, P_val, rec, ev);
+    return density_typed<float>(dp, H, rp, P_val, rec, ev);
 }
 
 }  // namespace gsp2
