@@ -19,8 +19,10 @@ notes):
   that is being squared; the error bound applies to its magnitude, since in
   finite precision e_t turns negative once X_t is idempotent to rounding.
   Stop at the first product t >= 2 with |e_t| >= |e_{t-2}| and
-  |e_{t-2}| < 1 (the error has stopped falling), and return X_t (the square
-  just formed is discarded).  At most ``max_iter``
+  |e_{t-2}| < max(1, n u) (the error has stopped falling, and has reached
+  the level the arithmetic can resolve: n = sum of core sizes, u = unit
+  roundoff of the product operands, 2^-53 here, so the floor is 1), and
+  return X_t (the square just formed is discarded).  At most ``max_iter``
   products; if the rule never fires the result is the last iterate and the
   run is "not converged".
 * Replay.  With a stored branch sequence, exactly that many products are
@@ -86,7 +88,7 @@ class SP2Result:
 
 def sp2_blocks(X0: list, cores: list, n_occ: float, max_iter: int = 60,
                alpha_seq=None, stop_rule: bool = True, trace_tol: float = 0.5,
-               raise_on_failure: bool = False) -> SP2Result:
+               raise_on_failure: bool = False, unit_roundoff: float = 2.0 ** -53) -> SP2Result:
     """Run the SP2 recursion eq. (2) on every block at once, all blocks sharing
     one branch sequence chosen from the summed core trace.
 
@@ -97,12 +99,13 @@ def sp2_blocks(X0: list, cores: list, n_occ: float, max_iter: int = 60,
     traces, errors, alphas = [tr], [], []
     replay = alpha_seq is not None
     n_steps = len(alpha_seq) if replay else max_iter
+    floor = max(1.0, sum(cores) * unit_roundoff)
     for t in range(n_steps):
         Y = [x @ x for x in X]                 # the product of eq. (2)
         trY = _core_trace(Y, cores)
         errors.append(tr - trY)
         if (not replay and stop_rule and t >= 2 and abs(errors[t]) >= abs(errors[t - 2])
-                and abs(errors[t - 2]) < 1.0):
+                and abs(errors[t - 2]) < floor):
             return SP2Result(X, t + 1, alphas, traces, errors, True)
         if replay:
             alpha = int(alpha_seq[t])

@@ -20,7 +20,7 @@ MUTANTS = {
     "radius_keeps_diag": ("sp2.py", "radius = absrow - np.abs(diag)", "radius = absrow"),
     "radius_no_abs": ("sp2.py", "absrow = np.abs(H).sum(axis=1)", "absrow = H.sum(axis=1)"),
     "trace_all_rows": ("sp2.py", "np.trace(b[:c, :c])", "np.trace(b)"),
-    "stop_no_safeguard": ("sp2.py", "and abs(errors[t - 2]) < 1.0", "and abs(errors[t - 2]) < 1e300"),
+    "stop_no_safeguard": ("sp2.py", "and abs(errors[t - 2]) < floor", "and abs(errors[t - 2]) < 1e300"),
     "stop_inverted": ("sp2.py", "abs(errors[t]) >= abs(errors[t - 2])", "abs(errors[t]) <= abs(errors[t - 2])"),
     "threshold_not_strict": ("graph.py", "> tau)", ">= tau)"),
     "graph_not_symmetrised": ("graph.py", "A = ((A + A.T) > 0)", "A = ((A + 0 * A.T) > 0)"),
