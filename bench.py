@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--save-state", help="write the thresholded graph and product count to this .npz")
     ap.add_argument("--load-state", help="reuse a graph and product count saved by --save-state "
                     "(skips the previous-P computation and the first, stop-finding run)")
+    ap.add_argument("--compare-precisions", default="fp16,bf16",
+                    help="after the FP32 timing, also time these operand precisions (empty: none)")
+    ap.add_argument("--compare-steps", type=int, default=3)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM counter calibration)")
     return ap.parse_args()
@@ -252,6 +255,34 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     sp2_med = statistics.median(sp2)
 
+    # the same density matrix with 16-bit product operands, on the same GPU
+    compare = {}
+    P_ref = P_val.double()
+    for prec in [p for p in args.compare_precisions.split(",") if p]:
+        P_mp = torch.empty_like(P_val)
+        with torch.cuda.stream(stream):
+            r0 = g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=args.max_iter, precision=prec)
+            n_mp = r0["n_products"]
+            g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=n_mp, precision=prec)      # builds the graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.compare_steps):
+                g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=n_mp, precision=prec, want_info=False)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / args.compare_steps
+            g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=n_mp, precision=prec, timing=True)
+            tm = g.gsp2_run_timing(plan)
+        diff = float(torch.linalg.vector_norm(P_mp.double() - P_ref) / torch.linalg.vector_norm(P_ref))
+        avg = statistics.fmean(tm["product_ms"])
+        compare[prec] = {"ms_per_P": round(ms, 3), "n_products": n_mp,
+                         "product_kernel_ms": round(avg, 4),
+                         "tflops": round(syrk_flops / (avg * 1e-3) / 1e12, 2),
+                         "frac_of_16bit_peak": round(syrk_flops / (avg * 1e-3) / 1e12 / 2516.6, 4),
+                         "rel_diff_vs_fp32_P": diff, "trace_minus_nocc": r0["trace"] - n_occ}
+        log(f"{prec}: {ms:.1f} ms/P, {n_mp} products, |P - P_fp32|/|P_fp32| = {diff:.2e}")
+        del P_mp
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the FP64 oracle on a sample of parts")
@@ -291,6 +322,7 @@ def main():
         "phase_ms": {"setup": round(statistics.median(setup), 3), "sp2": round(sp2_med, 3),
                      "scatter": round(statistics.median(scatter), 3),
                      "event_total_median": round(statistics.median(totals), 3)},
+        "precision_compare": compare,
         "plan_ms": round(plan_s * 1e3, 1),
         "plan_info": {k: info[k] for k in ("nnz_graph", "nnz_P", "sum_s", "workspace_bytes")},
         "previous_P_s": round(boot_s, 2),

@@ -52,6 +52,14 @@ typedef enum {
     GSP2_ALPHA_REPLAY = 1      /* branch sequence supplied by the caller */
 } gsp2_alpha_mode;
 
+/* Operand precision of the SP2 products.  Accumulation, the master copy of
+ * every iterate and the eq. (2) update are FP32 in all modes; traces FP64. */
+typedef enum {
+    GSP2_PREC_FP32 = 0,        /* FP32 operands (v_mfma_f32_32x32x2_f32) */
+    GSP2_PREC_FP16 = 1,        /* FP16 operands (v_mfma_f32_32x32x16_f16) */
+    GSP2_PREC_BF16 = 2         /* BF16 operands (v_mfma_f32_32x32x16_bf16) */
+} gsp2_precision;
+
 /* Sparse matrix in CSR form.  All four arrays are device pointers. */
 typedef struct {
     int32_t n;                 /* rows = columns */
@@ -98,6 +106,9 @@ typedef struct {
     double trace_tol;          /* replay mode: allowed |Tr P - n_occ|, default 0.5 */
     int32_t timing;            /* 1 = record HIP events around every phase and product
                                   (read with gsp2_run_timing); default 0 */
+    int32_t precision;         /* gsp2_precision of the products, default GSP2_PREC_FP32 */
+    int32_t refine;            /* FP32 products appended after the stop (branch from the
+                                  trace rule), 0..8, default 0; max_iter + refine <= GSP2_MAX_ITER */
 } gsp2_run_options;
 
 #define GSP2_MAX_ITER 100
@@ -108,6 +119,8 @@ typedef struct {
     int32_t n_products;        /* products formed, including a discarded last one */
     int32_t n_alpha;           /* branches applied to reach the returned P */
     int32_t result_iterate;    /* index t of the returned iterate X_t */
+    int32_t n_refine;          /* FP32 refinement products among n_products */
+    int32_t precision;         /* gsp2_precision of the run */
     double eps_min, eps_max;   /* Gershgorin bounds of H */
     double trace;              /* summed core trace of the returned P */
     double idempotency;        /* e_t = Tr[X_t] - Tr[X_t^2] of the returned iterate (NaN if not formed) */
@@ -180,13 +193,17 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
  *   X0_k = (eps_max I - H[idx_k, idx_k]) / (eps_max - eps_min)    (eq. (1));
  *   then, for t = 0, 1, ...: Y_k = X_k X_k on every part (eq. (2)),
  *   e_t = Tr[X_t] - Tr[Y_t]; stop (trace mode, stop_rule = 1) at the first
- *   t >= 2 with |e_t| >= |e_{t-2}| and |e_{t-2}| < 1, returning X_t; otherwise
+ *   t >= 2 with |e_t| >= |e_{t-2}| and |e_{t-2}| < max(1, n u), u the unit
+ *   roundoff of the product operands (2^-24, 2^-11, 2^-8), returning X_t; otherwise
  *   X_k <- 2 X_k - Y_k when Tr[X_t] <= n_occ, else X_k <- Y_k (replay mode:
  *   the supplied branches, then the trace check).  Tr is the sum over parts
  *   of the diagonal of each part's core rows.  P[idx_k, j] = X_k[:, j]
  *   for each core column j of part k; other entries are not stored.
- * Arithmetic: FP32 products on the matrix cores with FP32 accumulation,
- * Gershgorin bounds, X0 and all traces in FP64.
+ * Arithmetic: products on the matrix cores with FP32 accumulation and FP32,
+ * FP16 or BF16 operands (run->precision); the master iterate and the update
+ * stay FP32; Gershgorin bounds, X0 and all traces are FP64.  With refine > 0,
+ * that many FP32 products follow the stop (or the last replayed branch),
+ * each with the trace rule, and the last one is returned.
  *
  *  H       device CSR, n x n, symmetric; its pattern may change between calls.
  *  n_occ   number of occupied states N_el / 2, 0 <= n_occ <= n.

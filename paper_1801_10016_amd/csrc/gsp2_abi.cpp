@@ -245,6 +245,8 @@ gsp2_status gsp2_run_options_default(gsp2_run_options *opt) {
         opt->stop_rule = 1;
         opt->trace_tol = 0.5;
         opt->timing = 0;
+        opt->precision = GSP2_PREC_FP32;
+        opt->refine = 0;
     });
 }
 
@@ -348,17 +350,45 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             plan->desc[k] = d;
         }
         plan->arena_floats = xoff;
+        // Tile order.  A workgroup b of a launch runs on XCD b mod kXcds, so
+        // whole parts are dealt to XCDs by LPT on their product work, and each
+        // XCD's list walks its parts in kTileBlock x kTileBlock blocks of
+        // tiles: the workgroups resident on one XCD then share a few row and
+        // column panels in that XCD's L2.  Grid index b takes entry b / kXcds
+        // of XCD (b mod kXcds)'s list; short lists are padded with empty tiles.
+        constexpr int kXcds = 8;
+        constexpr int kTileBlock = 8;
         std::vector<int32_t> order(n_parts);
         std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b) { return plan->desc[a].s_pad > plan->desc[b].s_pad; });
-        int32_t slot = 0;
+        auto work = [&](int32_t k) {
+            const double nt = plan->desc[k].s_pad / T;
+            return nt * (nt + 1) / 2 * plan->desc[k].s_pad;
+        };
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work(a) > work(b); });
+        std::vector<double> load(kXcds, 0.0);
+        std::vector<std::vector<int32_t>> xcd_parts(kXcds);
         for (int32_t k : order) {
-            const int nt = plan->desc[k].s_pad / T;
-            for (int ti = 0; ti < nt; ++ti)
-                for (int tj = ti; tj < nt; ++tj)
-                    plan->tiles.push_back(TileDesc{k, ti, tj, ti == tj ? slot++ : -1});
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[x] += work(k);
+            xcd_parts[x].push_back(k);
         }
+        int32_t slot = 0;
+        std::vector<std::vector<TileDesc>> lists(kXcds);
+        for (int x = 0; x < kXcds; ++x) {
+            for (int32_t k : xcd_parts[x]) {
+                const int nt = plan->desc[k].s_pad / T;
+                for (int bi = 0; bi < nt; bi += kTileBlock)
+                    for (int bj = bi; bj < nt; bj += kTileBlock)
+                        for (int ti = bi; ti < std::min(bi + kTileBlock, nt); ++ti)
+                            for (int tj = std::max(ti, bj); tj < std::min(bj + kTileBlock, nt); ++tj)
+                                lists[x].push_back(TileDesc{k, ti, tj, ti == tj ? slot++ : -1});
+            }
+        }
+        size_t longest = 0;
+        for (auto &l : lists) longest = std::max(longest, l.size());
+        for (size_t q = 0; q < longest; ++q)
+            for (int x = 0; x < kXcds; ++x)
+                plan->tiles.push_back(q < lists[x].size() ? lists[x][q] : TileDesc{-1, 0, 0, -1});
         plan->n_diag = slot;
         constexpr int kRowsPerChunk = 16;
         for (int32_t k = 0; k < n_parts; ++k)
@@ -516,6 +546,8 @@ static void fill_info(const gsp2_plan_s *plan, gsp2_run_info *info) {
     info->n_products = r.n_products;
     info->n_alpha = r.t;
     info->result_iterate = r.result_t;
+    info->n_refine = r.n_refine;
+    info->precision = r.precision;
     info->eps_min = r.eps_min;
     info->eps_max = r.eps_max;
     info->trace = (r.result_t >= 0 && r.result_t <= GSP2_MAX_ITER) ? r.traces[r.result_t] : NAN;
@@ -573,6 +605,17 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         rp.trace_tol = o.trace_tol;
         rp.mode = o.alpha_mode;
         rp.stop_rule = o.stop_rule ? 1 : 0;
+        if (o.precision != GSP2_PREC_FP32 && o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16)
+            fail(GSP2_E_INVALID, "bad precision");
+        if (o.refine < 0 || o.refine > 8) fail(GSP2_E_INVALID, "refine must be in 0..8");
+        rp.precision = o.precision;
+        rp.refine = o.refine;
+        {
+            // the stop rule's floor max(1, n u), u the unit roundoff of the product operands
+            const double u = o.precision == GSP2_PREC_FP16 ? std::ldexp(1.0, -11)
+                             : o.precision == GSP2_PREC_BF16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -24);
+            rp.stop_floor = std::max(1.0, plan->n * u);
+        }
         if (o.alpha_mode == GSP2_ALPHA_TRACE) {
             if (o.max_iter < 1 || o.max_iter > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter out of range");
             rp.n_steps = o.max_iter;
@@ -587,6 +630,12 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
             rp.n_steps = o.n_alpha;
         } else {
             fail(GSP2_E_INVALID, "bad alpha_mode");
+        }
+        if (rp.n_steps + rp.refine > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter + refine exceeds GSP2_MAX_ITER");
+        if (rp.precision != GSP2_PREC_FP32 && !plan->dp.shadow[0]) {
+            // 16-bit operand copies of both X buffers, allocated on the first mixed-precision run
+            plan->dp.shadow[0] = plan->alloc<uint16_t>(plan->arena_floats, "16-bit X copy 0");
+            plan->dp.shadow[1] = plan->alloc<uint16_t>(plan->arena_floats, "16-bit X copy 1");
         }
         GraphKey k;
         k.h_ptr = H->row_ptr; k.h_col = H->col; k.h_val = H->val; k.h_nnz = H->nnz; k.h_dtype = H->dtype;
@@ -640,10 +689,19 @@ gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out) {
         check_hip(hipEventElapsedTime(&out->sp2_ms, e.setup_end, e.sp2_end), "elapsed");
         check_hip(hipEventElapsedTime(&out->scatter_ms, e.sp2_end, e.end), "elapsed");
         check_hip(hipEventElapsedTime(&out->total_ms, e.begin, e.end), "elapsed");
-        const int np = std::min(plan->h_state->n_products, plan->last_rp.n_steps);
-        out->n_products = np;
-        for (int t = 0; t < np; ++t)
+        // main-phase products occupy the first launch slots, refinement products
+        // the slots after the main-phase budget
+        const RunState &r = *plan->h_state;
+        const int n_main = std::min(r.n_main, plan->last_rp.n_steps);
+        const int n_ref = std::min(r.n_refine, plan->last_rp.refine);
+        out->n_products = n_main + n_ref;
+        for (int t = 0; t < n_main; ++t)
             check_hip(hipEventElapsedTime(&out->product_ms[t], e.step[2 * t], e.step[2 * t + 1]), "elapsed");
+        for (int q = 0; q < n_ref; ++q) {
+            const int slot = plan->last_rp.n_steps + q;
+            check_hip(hipEventElapsedTime(&out->product_ms[n_main + q], e.step[2 * slot], e.step[2 * slot + 1]),
+                      "elapsed");
+        }
     });
 }
 

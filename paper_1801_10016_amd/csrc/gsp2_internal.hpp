@@ -25,7 +25,8 @@ struct PartDesc {
 };
 static_assert(sizeof(PartDesc) == 32, "PartDesc layout");
 
-// One upper-triangle macro tile (ti <= tj) of one part's product.
+// One upper-triangle macro tile (ti <= tj) of one part's product; part < 0
+// marks an empty tile that pads the launch.
 struct TileDesc {
     int32_t part, ti, tj, diag_slot;   // diag_slot >= 0 only when ti == tj
 };
@@ -43,6 +44,7 @@ struct RunState {
     double eps_min, eps_max;
     double trX;                 // Tr[X_t] of the current iterate
     double idem;                // e_t of the returned iterate
+    double stop_floor;
     int32_t n_steps;            // product budget (trace mode) or replay length
     int32_t mode;               // gsp2_alpha_mode
     int32_t stop_rule;
@@ -54,7 +56,13 @@ struct RunState {
     int32_t result_buf;
     int32_t result_t;
     int32_t n_products;
-    int32_t pad_;
+    int32_t phase;              // 0: main products, 1: FP32 refinement products
+    int32_t refine;             // refinement products requested
+    int32_t refine_left;
+    int32_t n_refine;           // refinement products formed
+    int32_t main_status;        // status of the main phase, reported at the end
+    int32_t n_main;             // products formed in the main phase
+    int32_t precision;
     int8_t alpha_seq[GSP2_MAX_ITER];
     int8_t alpha_hist[GSP2_MAX_ITER];
     double traces[GSP2_MAX_ITER + 1];
@@ -65,9 +73,12 @@ struct RunState {
 struct RunParams {
     double n_occ;
     double trace_tol;
-    int32_t n_steps;
+    double stop_floor;          // max(1, n u): |e_{t-2}| must be below it for the stop rule
+    int32_t n_steps;            // main-phase product budget
     int32_t mode;
     int32_t stop_rule;
+    int32_t precision;          // gsp2_precision of the main phase
+    int32_t refine;             // FP32 products after the main phase
     int32_t pad_;
     int8_t alpha_seq[GSP2_MAX_ITER];
 };
@@ -83,6 +94,7 @@ struct DevicePlan {
     int32_t gersh_blocks;
     int32_t pad_;
     float *buf[2];
+    void *shadow[2];            // 16-bit operand copies of the two X buffers (mixed precision)
     const PartDesc *parts;
     const TileDesc *tiles;
     const RowChunk *chunks;

@@ -145,6 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ 
     }
     st->n_occ = rp.n_occ;
     st->trace_tol = rp.trace_tol;
+    st->stop_floor = rp.stop_floor;
     st->eps_min = lo;
     st->eps_max = hi;
     st->trX = 0.0;
@@ -158,6 +159,13 @@ __global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ 
     st->result_buf = 0;
     st->result_t = 0;
     st->n_products = 0;
+    st->phase = 0;
+    st->refine = rp.refine;
+    st->refine_left = 0;
+    st->n_refine = 0;
+    st->main_status = GSP2_OK;
+    st->n_main = 0;
+    st->precision = rp.precision;
     for (int i = 0; i < GSP2_MAX_ITER; ++i) {
         st->alpha_seq[i] = rp.alpha_seq[i];
         st->alpha_hist[i] = 0;
@@ -187,6 +195,21 @@ __device__ __forceinline__ int find_sorted(const int32_t *a, int n, int32_t key)
     return (lo < n && a[lo] == key) ? lo : -1;
 }
 
+// Four floats rounded to the 16-bit operand format (round to nearest even).
+__device__ __forceinline__ uint2 pack4_fp16(float4 v) {
+    union { _Float16 h[4]; uint2 u; } x;
+    x.h[0] = (_Float16)v.x; x.h[1] = (_Float16)v.y; x.h[2] = (_Float16)v.z; x.h[3] = (_Float16)v.w;
+    return x.u;
+}
+__device__ __forceinline__ uint2 pack4_bf16(float4 v) {
+    union { __bf16 h[4]; uint2 u; } x;
+    x.h[0] = (__bf16)v.x; x.h[1] = (__bf16)v.y; x.h[2] = (__bf16)v.z; x.h[3] = (__bf16)v.w;
+    return x.u;
+}
+__device__ __forceinline__ uint2 pack4(float4 v, int precision) {
+    return precision == GSP2_PREC_FP16 ? pack4_fp16(v) : pack4_bf16(v);
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
@@ -194,7 +217,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
                                                       const PartDesc *__restrict__ parts,
                                                       const RowChunk *__restrict__ chunks,
                                                       const int32_t *__restrict__ idx_arena,
-                                                      float *__restrict__ X, const RunState *__restrict__ st,
+                                                      float *__restrict__ X, uint16_t *__restrict__ Xs,
+                                                      const RunState *__restrict__ st,
                                                       double *__restrict__ x0_partials) {
     __shared__ int32_t idx_s[kGatherLdsIdx];
     __shared__ float row_s[kGatherChunk];
@@ -243,11 +267,18 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
             float4 *dst = reinterpret_cast<float4 *>(Xp + (int64_t)r * ld + c0);
             const float4 *src = reinterpret_cast<const float4 *>(row_s);
             for (int i = threadIdx.x; i < cw / 4; i += kBlock) dst[i] = src[i];
+            if (Xs) {
+                const int prec = st->precision;
+                uint2 *dsh = reinterpret_cast<uint2 *>(Xs + pd.x_off + (int64_t)r * ld + c0);
+                for (int i = threadIdx.x; i < cw / 4; i += kBlock) dsh[i] = pack4(src[i], prec);
+            }
             __syncthreads();
         }
     }
     if (threadIdx.x == 0) x0_partials[blockIdx.x] = tr;
 }
+
+__device__ void finish_main(RunState *st, int result_buf, int result_t, int status, bool refinable);
 
 // Reduce the X0 core-trace partials; pick the first branch.
 __global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__ x0_partials, int n,
@@ -260,11 +291,9 @@ __global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__
         st->trX = a;
         st->traces[0] = a;
         if (st->n_steps <= 0) {
-            st->done = 1;
-            st->result_buf = 0;
-            st->result_t = 0;
-            st->status = (st->mode == GSP2_ALPHA_REPLAY && fabs(a - st->n_occ) > st->trace_tol)
-                             ? GSP2_E_WRONG_TRACE : GSP2_OK;
+            const int status = (st->mode == GSP2_ALPHA_REPLAY && fabs(a - st->n_occ) > st->trace_tol)
+                                   ? GSP2_E_WRONG_TRACE : GSP2_OK;
+            finish_main(st, 0, 0, status, true);
             return;
         }
         st->alpha = (st->mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[0] : (a <= st->n_occ ? 1 : -1);
@@ -288,33 +317,86 @@ __global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__
 // buffers.  Within a chunk, lane half h of the MFMA operand feeds k = 16h+s
 // at step s, for A and B alike, so each lane reads 16 contiguous floats.
 // ---------------------------------------------------------------------------
-constexpr int kLdsStride = kKChunk + 4;      // padded LDS row (floats)
 typedef float v16f __attribute__((ext_vector_type(16)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+// Operand formats of the product.  Every format moves 128-byte row segments
+// per K chunk (32 FP32 or 64 FP16/BF16 values), staged in LDS rows of 144 bytes.
+template <typename Op> struct OpFmt;
+template <> struct OpFmt<float> { static constexpr int kK = 32; };
+template <> struct OpFmt<_Float16> { static constexpr int kK = 64; };
+template <> struct OpFmt<__bf16> { static constexpr int kK = 64; };
+constexpr int kLdsRow = 9;                  // uint4 per LDS row: 8 data + 1 pad
+
+__device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16f c, float) {
+    // four 32x32x2 FP32 steps; lane half h holds k = 16h + 4q + e for e = 0..3
+    const float4 fa = *reinterpret_cast<const float4 *>(&a);
+    const float4 fb = *reinterpret_cast<const float4 *>(&b);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.x, fb.x, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.y, fb.y, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.z, fb.z, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_32x32x2f32(fa.w, fb.w, c, 0, 0, 0);
+    return c;
+}
+__device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16f c, _Float16) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(*reinterpret_cast<const v8h *>(&a),
+                                                  *reinterpret_cast<const v8h *>(&b), c, 0, 0, 0);
+}
+__device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16f c, __bf16) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(*reinterpret_cast<const v8bf *>(&a),
+                                                   *reinterpret_cast<const v8bf *>(&b), c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// a6: one SP2 product on the matrix cores.
+//
+// Each workgroup computes one 128x128 tile Y[I,J] = sum_k X[I,k] X[J,k] of
+// one part (X is symmetric, so both operands are row panels with k
+// contiguous), for ti <= tj only; the eq. (2) update X' = Y or 2X - Y, in
+// FP32 against the FP32 master X, is fused into the epilogue and written to
+// the other buffer at (I,J) and, mirrored, at (J,I), so every iterate stays
+// exactly symmetric.  With 16-bit operands the epilogue also writes the
+// rounded copy of X' that the next product reads.  Diagonal tiles emit FP64
+// partial sums of Y and X' over the part's core diagonal.
+//
+// 256 threads = 4 waves in a 2x2 grid, each wave a 64x64 sub-tile as 2x2
+// blocks of 32x32 MFMA output.  Operands are staged through LDS in K chunks
+// with a register prefetch of the next chunk and two LDS buffers.  Within a
+// chunk, lane half h of an MFMA operand takes the k values of its half of
+// every 16-byte group, for A and B alike, so each lane reads whole 16-byte
+// LDS words.
+// ---------------------------------------------------------------------------
+template <typename Op>
 __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restrict__ tiles,
                                                         const PartDesc *__restrict__ parts,
                                                         float *__restrict__ buf0, float *__restrict__ buf1,
+                                                        Op *__restrict__ sh0, Op *__restrict__ sh1,
                                                         const RunState *__restrict__ st,
-                                                        double *__restrict__ diag_partials) {
-    __shared__ float As[2][kTile * kLdsStride];
-    __shared__ float Bs[2][kTile * kLdsStride];
-    if (st->done) return;
+                                                        double *__restrict__ diag_partials, int phase) {
+    __shared__ uint4 lds[2][2][kTile * kLdsRow];       // [buffer][A/B][row * 9 + word]
+    constexpr bool kF32 = sizeof(Op) == 4;
+    constexpr int kK = OpFmt<Op>::kK;
+    if (st->done || st->phase != phase) return;
     const TileDesc td = tiles[blockIdx.x];
+    if (td.part < 0) return;                    // padding of a short XCD list
     const PartDesc pd = parts[td.part];
     const int cur = st->cur;
     const float alpha = static_cast<float>(st->alpha);
     const float *__restrict__ X = (cur ? buf1 : buf0) + pd.x_off;
     float *__restrict__ Xn = (cur ? buf0 : buf1) + pd.x_off;
+    const Op *__restrict__ Xop = kF32 ? reinterpret_cast<const Op *>(X) : (cur ? sh1 : sh0) + pd.x_off;
+    Op *__restrict__ Xnop = kF32 ? nullptr : (cur ? sh0 : sh1) + pd.x_off;
     const int ld = pd.s_pad;
     const int I0 = td.ti * kTile, J0 = td.tj * kTile;
     const bool diag = td.ti == td.tj;
 
     const int tid = threadIdx.x;
-    // global -> LDS mapping: 8 threads per 32-float row segment, 32 rows per pass
-    const int lr = tid >> 3, lc = (tid & 7) * 4;
-    const float *Ag = X + (int64_t)(I0 + lr) * ld + lc;
-    const float *Bg = X + (int64_t)(J0 + lr) * ld + lc;
-    const int64_t pass_stride = (int64_t)32 * ld;
+    // global -> LDS: 8 threads per 128-byte row segment, 32 rows per pass
+    const int lr = tid >> 3, lw = tid & 7;
+    const char *Ag = reinterpret_cast<const char *>(Xop + (int64_t)(I0 + lr) * ld) + lw * 16;
+    const char *Bg = reinterpret_cast<const char *>(Xop + (int64_t)(J0 + lr) * ld) + lw * 16;
+    const int64_t pass_bytes = (int64_t)32 * ld * sizeof(Op);
 
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
@@ -328,61 +410,53 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
-    float4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
-#define GSP2_LOAD_CHUNK(k0)                                                            \
-    do {                                                                               \
-        pa0 = *reinterpret_cast<const float4 *>(Ag + (k0));                            \
-        pa1 = *reinterpret_cast<const float4 *>(Ag + pass_stride + (k0));              \
-        pa2 = *reinterpret_cast<const float4 *>(Ag + 2 * pass_stride + (k0));          \
-        pa3 = *reinterpret_cast<const float4 *>(Ag + 3 * pass_stride + (k0));          \
-        if (!diag) {                                                                   \
-            pb0 = *reinterpret_cast<const float4 *>(Bg + (k0));                        \
-            pb1 = *reinterpret_cast<const float4 *>(Bg + pass_stride + (k0));          \
-            pb2 = *reinterpret_cast<const float4 *>(Bg + 2 * pass_stride + (k0));      \
-            pb3 = *reinterpret_cast<const float4 *>(Bg + 3 * pass_stride + (k0));      \
-        }                                                                              \
+    uint4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
+#define GSP2_LOAD_CHUNK(kb)                                                                        \
+    do {                                                                                           \
+        pa0 = *reinterpret_cast<const uint4 *>(Ag + (kb));                                         \
+        pa1 = *reinterpret_cast<const uint4 *>(Ag + pass_bytes + (kb));                            \
+        pa2 = *reinterpret_cast<const uint4 *>(Ag + 2 * pass_bytes + (kb));                        \
+        pa3 = *reinterpret_cast<const uint4 *>(Ag + 3 * pass_bytes + (kb));                        \
+        if (!diag) {                                                                               \
+            pb0 = *reinterpret_cast<const uint4 *>(Bg + (kb));                                     \
+            pb1 = *reinterpret_cast<const uint4 *>(Bg + pass_bytes + (kb));                        \
+            pb2 = *reinterpret_cast<const uint4 *>(Bg + 2 * pass_bytes + (kb));                    \
+            pb3 = *reinterpret_cast<const uint4 *>(Bg + 3 * pass_bytes + (kb));                    \
+        }                                                                                          \
     } while (0)
-#define GSP2_STORE_CHUNK(b)                                                            \
-    do {                                                                               \
-        float *As_ = As[b] + lr * kLdsStride + lc;                                     \
-        *reinterpret_cast<float4 *>(As_) = pa0;                                        \
-        *reinterpret_cast<float4 *>(As_ + 32 * kLdsStride) = pa1;                      \
-        *reinterpret_cast<float4 *>(As_ + 64 * kLdsStride) = pa2;                      \
-        *reinterpret_cast<float4 *>(As_ + 96 * kLdsStride) = pa3;                      \
-        if (!diag) {                                                                   \
-            float *Bs_ = Bs[b] + lr * kLdsStride + lc;                                 \
-            *reinterpret_cast<float4 *>(Bs_) = pb0;                                    \
-            *reinterpret_cast<float4 *>(Bs_ + 32 * kLdsStride) = pb1;                  \
-            *reinterpret_cast<float4 *>(Bs_ + 64 * kLdsStride) = pb2;                  \
-            *reinterpret_cast<float4 *>(Bs_ + 96 * kLdsStride) = pb3;                  \
-        }                                                                              \
+#define GSP2_STORE_CHUNK(b)                                                                        \
+    do {                                                                                           \
+        uint4 *As_ = lds[b][0] + lr * kLdsRow + lw;                                                \
+        As_[0] = pa0; As_[32 * kLdsRow] = pa1; As_[64 * kLdsRow] = pa2; As_[96 * kLdsRow] = pa3;   \
+        if (!diag) {                                                                               \
+            uint4 *Bs_ = lds[b][1] + lr * kLdsRow + lw;                                            \
+            Bs_[0] = pb0; Bs_[32 * kLdsRow] = pb1; Bs_[64 * kLdsRow] = pb2; Bs_[96 * kLdsRow] = pb3; \
+        }                                                                                          \
     } while (0)
 
-    const int nk = ld / kKChunk;
+    const int nk = ld / kK;
     GSP2_LOAD_CHUNK(0);
     GSP2_STORE_CHUNK(0);
     __syncthreads();
     for (int kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
-        if (kc + 1 < nk) GSP2_LOAD_CHUNK((kc + 1) * kKChunk);
-        const float *Asb = As[buf];
-        const float *Bsb = diag ? As[buf] : Bs[buf];
+        if (kc + 1 < nk) GSP2_LOAD_CHUNK((int64_t)(kc + 1) * 128);
+        const uint4 *Asb = lds[buf][0];
+        const uint4 *Bsb = diag ? lds[buf][0] : lds[buf][1];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            float4 fa[2], fb[2];
+            // FP32: word kh*4+q of the row (k = 16 kh + 4 q + e); 16-bit: word 2q+kh (k = 16 q + 8 kh + e)
+            const int w = kF32 ? kh * 4 + q : 2 * q + kh;
+            uint4 fa[2], fb[2];
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
-                fa[m] = *reinterpret_cast<const float4 *>(Asb + (wr * 64 + m * 32 + l32) * kLdsStride + kh * 16 + 4 * q);
-                fb[m] = *reinterpret_cast<const float4 *>(Bsb + (wc * 64 + m * 32 + l32) * kLdsStride + kh * 16 + 4 * q);
+                fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
+                fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
             }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int nn = 0; nn < 2; ++nn)
-                        acc[m][nn] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[m][e], fb[nn][e], acc[m][nn], 0, 0, 0);
-            }
+                for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
         }
         if (kc + 1 < nk) GSP2_STORE_CHUNK(buf ^ 1);
         __syncthreads();
@@ -410,13 +484,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
                     const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
                     xn[e] = v;
                     Xn[(int64_t)rg * ld + cg] = v;
+                    if constexpr (!kF32) Xnop[(int64_t)rg * ld + cg] = static_cast<Op>(v);
                     if (diag && rg == cg && rg < pd.c) {
                         tY += static_cast<double>(y);
                         tX += static_cast<double>(v);
                     }
                 }
-                if (!diag)
-                    *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = make_float4(xn[0], xn[1], xn[2], xn[3]);
+                if (!diag) {
+                    const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
+                    *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
+                    if constexpr (!kF32) {
+                        union { Op h[4]; uint2 u; } pk;
+                        pk.h[0] = static_cast<Op>(v4.x); pk.h[1] = static_cast<Op>(v4.y);
+                        pk.h[2] = static_cast<Op>(v4.z); pk.h[3] = static_cast<Op>(v4.w);
+                        *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
+                    }
+                }
             }
         }
     }
@@ -429,11 +512,30 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
     }
 }
 
+// End of the main phase: hand over to the FP32 refinement products, or stop.
+__device__ void finish_main(RunState *st, int result_buf, int result_t, int status, bool refinable) {
+    st->n_main = st->n_products;
+    if (refinable && st->refine > 0) {
+        st->phase = 1;
+        st->main_status = status;
+        st->cur = result_buf;
+        st->t = result_t;
+        st->trX = st->traces[result_t];
+        st->refine_left = st->refine;
+        st->alpha = st->trX <= st->n_occ ? 1 : -1;
+        return;
+    }
+    st->done = 1;
+    st->result_buf = result_buf;
+    st->result_t = result_t;
+    st->status = status;
+}
+
 // a7: reduce the product's trace partials, apply the stop rule, choose the
 // next branch.  One workgroup; fixed summation order.
 __global__ __launch_bounds__(kBlock) void k_sp2_decide(const double *__restrict__ diag_partials, int n_diag,
-                                                       RunState *__restrict__ st) {
-    if (st->done) return;
+                                                       RunState *__restrict__ st, int phase) {
+    if (st->done || st->phase != phase) return;
     double ty = 0.0, tx = 0.0;
     for (int i = threadIdx.x; i < n_diag; i += kBlock) {
         ty += diag_partials[2 * i];
@@ -444,37 +546,49 @@ __global__ __launch_bounds__(kBlock) void k_sp2_decide(const double *__restrict_
     const int t = st->t;
     const double e = st->trX - ty;              // e_t = Tr[X_t] - Tr[X_t^2]
     st->errors[t] = e;
-    st->n_products = t + 1;
+    st->n_products += 1;
     if (!isfinite(ty) || !isfinite(tx)) {       // left the finite range: keep X_t
+        if (phase == 0) st->n_main = st->n_products;
         st->done = 1;
         st->result_buf = st->cur;
         st->result_t = t;
         st->status = GSP2_E_NOT_CONVERGED;
         return;
     }
-    // the bound applies to |e|: in FP32 e turns negative once X_t is idempotent to rounding
-    if (st->mode == GSP2_ALPHA_TRACE && st->stop_rule && t >= 2 && fabs(e) >= fabs(st->errors[t - 2]) &&
-        fabs(st->errors[t - 2]) < 1.0) {
-        st->done = 1;                           // X_t is the result; X_t^2 is discarded
-        st->result_buf = st->cur;
-        st->result_t = t;
-        st->idem = e;
-        st->status = GSP2_OK;
-        return;
+    if (phase == 0) {
+        // the bound applies to |e|: in FP32 e turns negative once X_t is idempotent to rounding
+        if (st->mode == GSP2_ALPHA_TRACE && st->stop_rule && t >= 2 && fabs(e) >= fabs(st->errors[t - 2]) &&
+            fabs(st->errors[t - 2]) < st->stop_floor) {
+            st->idem = e;                       // X_t is the result; X_t^2 is discarded
+            finish_main(st, st->cur, t, GSP2_OK, true);
+            return;
+        }
     }
     st->alpha_hist[t] = (int8_t)st->alpha;
     st->cur ^= 1;
     st->trX = tx;
     st->traces[t + 1] = tx;
     st->t = t + 1;
-    if (t + 1 >= st->n_steps) {
-        st->done = 1;
-        st->result_buf = st->cur;
-        st->result_t = t + 1;
+    if (phase == 1) {
+        st->n_refine += 1;
+        st->idem = e;
+        if (--st->refine_left == 0) {
+            st->done = 1;
+            st->result_buf = st->cur;
+            st->result_t = t + 1;
+            st->status = st->main_status;
+            return;
+        }
+        st->alpha = tx <= st->n_occ ? 1 : -1;
+        return;
+    }
+    if (st->n_products >= st->n_steps) {
+        int status;
         if (st->mode == GSP2_ALPHA_REPLAY)
-            st->status = fabs(tx - st->n_occ) <= st->trace_tol ? GSP2_OK : GSP2_E_WRONG_TRACE;
+            status = fabs(tx - st->n_occ) <= st->trace_tol ? GSP2_OK : GSP2_E_WRONG_TRACE;
         else
-            st->status = st->stop_rule ? GSP2_E_NOT_CONVERGED : GSP2_OK;
+            status = st->stop_rule ? GSP2_E_NOT_CONVERGED : GSP2_OK;
+        finish_main(st, st->cur, t + 1, status, true);
         return;
     }
     st->alpha = (st->mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[t + 1] : (tx <= st->n_occ ? 1 : -1);
@@ -525,16 +639,37 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     if (ev) rec.add_event(ev->begin);
     record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.gersh_partials);
     record(rec, k_run_init, dim3(1), blk, dp.gersh_partials, dp.gersh_blocks, rp, dp.state);
+    const bool mixed = rp.precision != GSP2_PREC_FP32;
+    uint16_t *sh0 = mixed ? static_cast<uint16_t *>(dp.shadow[0]) : nullptr;
     record(rec, k_gather_x0<T>, dim3(dp.n_chunks), blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx,
-           dp.buf[0], dp.state, dp.x0_partials);
+           dp.buf[0], sh0, dp.state, dp.x0_partials);
     record(rec, k_run_start, dim3(1), blk, dp.x0_partials, dp.n_chunks, dp.state);
     if (ev) rec.add_event(ev->setup_end);
+    const dim3 grid(dp.n_tiles);
+    float *b0 = dp.buf[0], *b1 = dp.buf[1];
     for (int it = 0; it < rp.n_steps; ++it) {
         if (ev) rec.add_event(ev->step[2 * it]);
-        record(rec, k_sp2_step, dim3(dp.n_tiles), blk, dp.tiles, dp.parts, dp.buf[0], dp.buf[1], dp.state,
-               dp.diag_partials);
+        if (rp.precision == GSP2_PREC_FP16)
+            record(rec, k_sp2_step<_Float16>, grid, blk, dp.tiles, dp.parts, b0, b1,
+                   static_cast<_Float16 *>(dp.shadow[0]), static_cast<_Float16 *>(dp.shadow[1]), dp.state,
+                   dp.diag_partials, 0);
+        else if (rp.precision == GSP2_PREC_BF16)
+            record(rec, k_sp2_step<__bf16>, grid, blk, dp.tiles, dp.parts, b0, b1,
+                   static_cast<__bf16 *>(dp.shadow[0]), static_cast<__bf16 *>(dp.shadow[1]), dp.state,
+                   dp.diag_partials, 0);
+        else
+            record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr,
+                   (float *)nullptr, dp.state, dp.diag_partials, 0);
         if (ev) rec.add_event(ev->step[2 * it + 1]);
-        record(rec, k_sp2_decide, dim3(1), blk, dp.diag_partials, dp.n_diag, dp.state);
+        record(rec, k_sp2_decide, dim3(1), blk, dp.diag_partials, dp.n_diag, dp.state, 0);
+    }
+    for (int r = 0; r < rp.refine; ++r) {
+        const int slot = rp.n_steps + r;
+        if (ev) rec.add_event(ev->step[2 * slot]);
+        record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr, (float *)nullptr,
+               dp.state, dp.diag_partials, 1);
+        if (ev) rec.add_event(ev->step[2 * slot + 1]);
+        record(rec, k_sp2_decide, dim3(1), blk, dp.diag_partials, dp.n_diag, dp.state, 1);
     }
     if (ev) rec.add_event(ev->sp2_end);
     const int wpb = kBlock / kWave;

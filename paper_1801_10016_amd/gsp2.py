@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "libgsp2.so")
 GSP2_OK, GSP2_E_INVALID, GSP2_E_HIP, GSP2_E_OOM, GSP2_E_NOT_CONVERGED, GSP2_E_WRONG_TRACE, GSP2_E_UNSUPPORTED = range(7)
 GSP2_F32, GSP2_F64 = 0, 1
 GSP2_ALPHA_TRACE, GSP2_ALPHA_REPLAY = 0, 1
+GSP2_PREC_FP32, GSP2_PREC_FP16, GSP2_PREC_BF16 = 0, 1, 2
+PRECISIONS = {"fp32": GSP2_PREC_FP32, "fp16": GSP2_PREC_FP16, "bf16": GSP2_PREC_BF16}
 GSP2_MAX_ITER = 100
 
 STATUS_NAMES = {0: "GSP2_OK", 1: "GSP2_E_INVALID", 2: "GSP2_E_HIP", 3: "GSP2_E_OOM",
@@ -43,12 +45,13 @@ class gsp2_plan_info(C.Structure):
 class gsp2_run_options(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("alpha_mode", C.c_int32), ("alpha_seq", C.POINTER(C.c_int8)),
                 ("n_alpha", C.c_int32), ("stop_rule", C.c_int32), ("trace_tol", C.c_double),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32)]
 
 
 class gsp2_run_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_products", C.c_int32), ("n_alpha", C.c_int32),
-                ("result_iterate", C.c_int32), ("eps_min", C.c_double), ("eps_max", C.c_double),
+                ("result_iterate", C.c_int32), ("n_refine", C.c_int32), ("precision", C.c_int32),
+                ("eps_min", C.c_double), ("eps_max", C.c_double),
                 ("trace", C.c_double), ("idempotency", C.c_double),
                 ("alpha", C.c_int8 * GSP2_MAX_ITER), ("traces", C.c_double * (GSP2_MAX_ITER + 1)),
                 ("errors", C.c_double * GSP2_MAX_ITER)]
@@ -233,10 +236,13 @@ def gsp2_plan_set_stream(plan: Plan, stream=None):
     _check(load().gsp2_plan_set_stream(plan.handle, C.c_void_p(_stream_handle(stream))))
 
 
-def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5, timing=False):
+def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5, timing=False,
+                     precision="fp32", refine=0):
     o = gsp2_run_options_default()
     o.max_iter = int(max_iter)
     o.timing = 1 if timing else 0
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.refine = int(refine)
     o.stop_rule = 1 if stop_rule else 0
     o.trace_tol = float(trace_tol)
     keep = None
@@ -253,6 +259,7 @@ def run_info_dict(info: gsp2_run_info) -> dict:
     return {
         "status": info.status, "status_name": STATUS_NAMES.get(info.status, str(info.status)),
         "n_products": info.n_products, "n_alpha": n, "result_iterate": info.result_iterate,
+        "n_refine": info.n_refine, "precision": info.precision,
         "eps_min": info.eps_min, "eps_max": info.eps_max, "trace": info.trace,
         "idempotency": info.idempotency, "alpha": [int(a) for a in info.alpha[:n]],
         "traces": [float(t) for t in info.traces[:n + 1]],
@@ -261,7 +268,8 @@ def run_info_dict(info: gsp2_run_info) -> dict:
 
 
 def gsp2_density(plan: Plan, H: DeviceCSR, n_occ: float, P_val, max_iter=60, alpha_seq=None,
-                 stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False):
+                 stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False,
+                 precision="fp32", refine=0):
     """Enqueue one density matrix into P_val (torch float32 on the GPU, nnz_P
     entries).  With want_info the call waits and returns the run's info dict;
     with check a failing status raises Gsp2Error."""
@@ -271,7 +279,7 @@ def gsp2_density(plan: Plan, H: DeviceCSR, n_occ: float, P_val, max_iter=60, alp
     if P_val.numel() < plan.nnz_P:
         raise ValueError(f"P_val holds {P_val.numel()} values, the plan needs {plan.nnz_P}")
     c = H.as_c()
-    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing)
+    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine)
     info = gsp2_run_info() if want_info else None
     st = load().gsp2_density(plan.handle, C.byref(c), float(n_occ), C.byref(o), C.c_void_p(P_val.data_ptr()),
                              C.byref(info) if info is not None else None)

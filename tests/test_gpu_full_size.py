@@ -48,9 +48,25 @@ def case():
     info, cs, ss = g.gsp2_plan_query(plan)
     col_ptr, row_idx = g.gsp2_plan_pattern(plan)
     P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
+    # the oracle recomputes three parts (smallest, median, largest) by replaying its sequence
+    sizes = np.array([p["s"] for p in gold["parts"]])
+    order = np.argsort(sizes)
+    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    ref = oracle.gsp2(s.H, Q, sp["tau"], part, sp["n_parts"], s.n_occ, alpha_seq=gold["alphas"],
+                      parts_subset=pick, trace_tol=1e9)
     yield dict(g=g, torch=torch, gold=gold, s=s, part=part, Q=Q, plan=plan, info=info, cs=cs, ss=ss,
-               col_ptr=col_ptr, row_idx=row_idx, P_val=P_val, Hd=Hd, stream=stream)
+               col_ptr=col_ptr, row_idx=row_idx, P_val=P_val, Hd=Hd, stream=stream, pick=pick, ref=ref,
+               sizes=sizes)
     plan.close()
+
+
+def _sampled_errors(c, vals):
+    errs = {}
+    for i, k in enumerate(c["pick"]):
+        idx, blk = _core_block(c, vals, k)
+        assert np.array_equal(idx, c["ref"].index[i])
+        errs[k] = np.linalg.norm(blk - c["ref"].core_columns[i]) / np.linalg.norm(c["ref"].core_columns[i])
+    return errs
 
 
 def _run(c, **kw):
@@ -95,16 +111,8 @@ def test_replayed_sequence_matches_oracle(case):
     print(f"max per-part |fro - fro_oracle| / fro_oracle = {max(fro_err):.2e}", flush=True)
     assert max(fro_err) <= TOL
     # sampled parts, element by element, against the oracle replaying the sequence
-    sizes = np.array([p["s"] for p in gold["parts"]])
-    order = np.argsort(sizes)
-    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
-    ref = oracle.gsp2(case["s"].H, case["Q"], gold["spec"]["tau"], case["part"], gold["spec"]["n_parts"],
-                      case["s"].n_occ, alpha_seq=gold["alphas"], parts_subset=pick, trace_tol=1e9)
-    for i, k in enumerate(pick):
-        idx, blk = _core_block(case, vals, k)
-        assert np.array_equal(idx, ref.index[i])
-        err = np.linalg.norm(blk - ref.core_columns[i]) / np.linalg.norm(ref.core_columns[i])
-        print(f"part {k} (s={sizes[k]}): rel_err={err:.2e}", flush=True)
+    for k, err in _sampled_errors(case, vals).items():
+        print(f"part {k} (s={case['sizes'][k]}): rel_err={err:.2e}", flush=True)
         assert err <= TOL
 
 
@@ -127,3 +135,20 @@ def test_trace_mode_run(case):
     if not diff and run["n_alpha"] == len(oa):
         _, vals2 = _run(case, alpha_seq=oa, trace_tol=1e9)
         assert np.array_equal(vals, vals2)
+
+
+@pytest.mark.parametrize("precision,bar", [("fp16", 3e-3), ("bf16", 3e-2)])
+def test_mixed_precision_error_vs_oracle(case, precision, bar):
+    """FP16/BF16 product operands on the full workload: the error against the
+    FP64 oracle, stated per mode (same replayed sequence), with and without
+    two FP32 refinement products."""
+    gold = case["gold"]
+    for refine in (0, 2):
+        run, vals = _run(case, alpha_seq=gold["alphas"], trace_tol=1e9, precision=precision, refine=refine)
+        assert np.isfinite(vals).all()
+        errs = _sampled_errors(case, vals)
+        print(f"{precision} refine={refine}: sampled-part rel_err " +
+              ", ".join(f"{e:.2e}" for e in errs.values()) + f"; Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}",
+              flush=True)
+        if refine == 0:
+            assert max(errs.values()) <= bar

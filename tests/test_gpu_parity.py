@@ -136,3 +136,57 @@ def test_small_system_near_tie_branch():
     # 32 molecules, 4 parts, tau = 1e-3: the trace lands within FP32 rounding
     # of N_occ late in the run, so the branch sequences may part there
     _check_parity(pins.water(32, 0), 1e-3, 4)
+
+
+# Mixed precision: FP16/BF16 operands, FP32 accumulation and master iterate.
+# Rounding X to the operand format costs a relative 2^-11 (FP16) or 2^-8
+# (BF16) per product; the bars below are the error budgets stated for each
+# mode, measured against the FP64 oracle.
+MIXED_TOL = {"fp16": 3e-3, "bf16": 3e-2}
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_mixed_precision_one_product(precision):
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(100, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 3, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, alpha_seq=[-1])
+    P, run, _, _, _ = run_gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, alpha_seq=[-1], trace_tol=1e9,
+                               precision=precision)
+    err = rel_fro(P, ref.csc())
+    print(f"{precision} one product: rel_err={err:.2e}", flush=True)
+    unit = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}[precision]
+    assert run["precision"] == {"fp16": 1, "bf16": 2}[precision]
+    assert err <= 4 * unit
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_mixed_precision_trace_mode(precision):
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(200, 1)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 6, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ)
+    out = {}
+    for refine in (0, 2):
+        P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, refine=refine)
+        assert run["status"] == 0 and run["n_refine"] == refine, run
+        assert np.isfinite(vals).all()
+        out[refine] = rel_fro(P, ref.csc())
+        print(f"{precision} refine={refine}: products={run['n_products']} rel_err={out[refine]:.2e} "
+              f"|Tr P - N_occ|={abs(run['trace'] - s.n_occ):.2e}", flush=True)
+    assert out[0] <= MIXED_TOL[precision]
+
+
+def test_fp32_refinement_products():
+    # refine FP32 products after the FP32 stop: the iterate stays at the oracle's result
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(64, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 8, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-5, part, 8, s.n_occ)
+    P, run, _, _, _ = run_gsp2(s.H, Pp, 1e-5, part, 8, s.n_occ, refine=2)
+    print(f"fp32 refine=2: products={run['n_products']} rel_err={rel_fro(P, ref.csc()):.2e}", flush=True)
+    assert run["status"] == 0 and run["n_refine"] == 2
+    assert rel_fro(P, ref.csc()) <= TOL
