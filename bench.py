@@ -31,6 +31,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}     # dense, per operand format
+DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16"}
 PEAK_HBM_GBS = 8000.0
 METRIC = "ms per density matrix P + batched-GEMM TFLOP/s (frac. of MFMA peak) at 10k atoms"
 
@@ -59,6 +61,8 @@ def parse():
     ap.add_argument("--save-state", help="write the thresholded graph and product count to this .npz")
     ap.add_argument("--load-state", help="reuse a graph and product count saved by --save-state "
                     "(skips the previous-P computation and the first, stop-finding run)")
+    ap.add_argument("--precision", choices=["fp32", "fp16", "bf16"], default="fp32",
+                    help="operand precision of the timed products")
     ap.add_argument("--compare-precisions", default="fp16,bf16",
                     help="after the FP32 timing, also time these operand precisions (empty: none)")
     ap.add_argument("--compare-steps", type=int, default=3)
@@ -81,6 +85,22 @@ def dense_bootstrap(g, torch, Hd, n, n_occ, stream):
     col_ptr = torch.arange(0, n * n + 1, n, dtype=torch.int64, device="cuda")
     row_idx = torch.arange(n, dtype=torch.int32, device="cuda").repeat(n)
     return g.DeviceCSR(n, col_ptr, row_idx, P), run
+
+
+def counter_traffic(precision):
+    """HBM bytes per product launch from the committed rocprofv3 counter record,
+    or None when the kernel or planner sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_sp2_step_counters.json")
+    try:
+        rec = json.load(open(path))[precision]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in rec["sources"]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
 def threshold_on_host(Pprev, tau):
@@ -213,7 +233,7 @@ def main():
         n_prod = int(saved["n_products"])
     else:
         with torch.cuda.stream(stream):
-            first = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=args.max_iter)
+            first = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=args.max_iter, precision=args.precision)
         n_prod = first["n_products"]
         log(f"first run: status {first['status_name']}, {n_prod} products, Tr P = {first['trace']:.6f}")
     if args.save_state:
@@ -224,7 +244,7 @@ def main():
     timed = not args.no_kernel_timing
     with torch.cuda.stream(stream):
         for i in range(args.warmup):
-            w = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=timed)
+            w = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=timed, precision=args.precision)
             assert w["status"] == 0 and w["n_products"] == n_prod, w
             log(f"warmup {i + 1}/{args.warmup}" +
                 (f": {g.gsp2_run_timing(plan)['total_ms']:.1f} ms" if timed else ""))
@@ -233,7 +253,8 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
-            g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=timed, want_info=False)
+            g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=timed, want_info=False,
+                           precision=args.precision)
             if timed:
                 tm = g.gsp2_run_timing(plan)
                 totals.append(tm["total_ms"]); product_ms += tm["product_ms"]
@@ -252,6 +273,7 @@ def main():
     gemm_flops = float(np.sum(2.0 * s ** 3))
     avg_prod_ms = statistics.fmean(product_ms)
     achieved = syrk_flops / (avg_prod_ms * 1e-3) / 1e12
+    peak = PEAK_MFMA_TFLOPS[args.precision]
     ms_per_step = wall * 1e3 / args.steps
     sp2_med = statistics.median(sp2)
 
@@ -277,7 +299,7 @@ def main():
         compare[prec] = {"ms_per_P": round(ms, 3), "n_products": n_mp,
                          "product_kernel_ms": round(avg, 4),
                          "tflops": round(syrk_flops / (avg * 1e-3) / 1e12, 2),
-                         "frac_of_16bit_peak": round(syrk_flops / (avg * 1e-3) / 1e12 / 2516.6, 4),
+                         "frac_of_peak": round(syrk_flops / (avg * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[prec], 4),
                          "rel_diff_vs_fp32_P": diff, "trace_minus_nocc": r0["trace"] - n_occ}
         log(f"{prec}: {ms:.1f} ms/P, {n_mp} products, |P - P_fp32|/|P_fp32| = {diff:.2e}")
         del P_mp
@@ -300,7 +322,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {
             "workload": (f"G-SP2 density matrix of {args.n_mol} synthetic water molecules ({n} orbitals), "
@@ -308,14 +330,16 @@ def main():
             "n_mol": args.n_mol, "n_orbitals": n, "n_occ": n_occ, "n_parts": args.n_parts,
             "tau": args.tau, "previous_P": boot_desc, "s_min": info["min_s"], "s_max": info["max_s"],
             "s_mean": round(float(s.mean()), 1), "sum_s3": info["sum_s3"], "n_products": n_prod,
-            "tiles_per_product": info["n_tiles"], "precision": "FP32 MFMA products, FP64 traces",
+            "tiles_per_product": info["n_tiles"],
+            "precision": f"{args.precision.upper()} MFMA operands, FP32 accumulation and iterate, FP64 traces",
         },
         "batched_gemm_tflops": round(n_prod * gemm_flops / (sp2_med * 1e-3) / 1e12, 2),
         "batched_gemm_tflops_convention": "n_products * sum_k 2 s_k^3 / SP2-phase time (GEMM convention)",
         "roofline": {
             "bound": "mfma", "kernel": "k_sp2_step",
-            "achieved": round(achieved, 2), "peak": PEAK_FP32_MFMA_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_MFMA_TFLOPS, 4), "traffic": None,
+            "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": counter_traffic(args.precision),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "flops_per_launch": syrk_flops, "avg_launch_ms": round(avg_prod_ms, 4),
             "flops_convention": "symmetric product: sum_k s_k^2 (s_k + 1) per launch (one launch = one product)",
         },
