@@ -41,7 +41,7 @@ typedef enum {
     GSP2_E_OOM = 3,            /* device or host allocation failed */
     GSP2_E_NOT_CONVERGED = 4,  /* the stop rule did not fire within max_iter products,
                                   or the iteration left the finite range */
-    GSP2_E_WRONG_TRACE = 5,    /* a replayed branch sequence ended with the wrong trace */
+    GSP2_E_WRONG_TRACE = 5,    /* a replayed branch sequence missed n_occ by more than trace_tol */
     GSP2_E_UNSUPPORTED = 6     /* option not available in this build */
 } gsp2_status;
 

@@ -27,8 +27,8 @@ notes):
   run is "not converged".
 * Replay.  With a stored branch sequence, exactly that many products are
   applied, no stop rule, and the result is rejected when its trace misses
-  N_occ by more than ``trace_tol`` ("the iteration ends with the wrong
-  trace").
+  N_occ by more than ``trace_tol`` (the paper's check on a stored
+  sequence).
 """
 from __future__ import annotations
 

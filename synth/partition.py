@@ -2,7 +2,7 @@
 of the G-SP2 plan, never computed inside it).
 
 * ``block_partition``: a fixed number of consecutive orbitals per part, in
-  index order (the paper's "block partitioning").
+  index order (the block scheme of the paper).
 * ``uneven_spatial_partition``: whole molecules grouped into compact
   spatial parts of deliberately uneven target sizes, by recursive
   coordinate bisection with weighted cuts.  It stands in for an

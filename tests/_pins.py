@@ -88,7 +88,7 @@ def check_dense_projector(sys_, tol=1e-12):
     assert np.linalg.norm(P @ P - P) / np.linalg.norm(P) <= tol
     assert abs(np.trace(P) - sys_.n_occ) <= 1e-9 * sys_.n
     assert np.linalg.norm(Hd @ P - P @ Hd) / np.linalg.norm(Hd) <= tol
-    # a few dozen products, as the paper reports
+    # tens of products, the range the paper reports for systems of this kind
     assert 15 <= res.n_products <= 60
     return P, res
 

@@ -95,7 +95,7 @@ def test_stop_rule_failures():
     # replaying the recorded sequence reproduces the result and passes the trace check
     Pr, rep = oracle.dense_sp2(s.H, s.n_occ, alpha_seq=ok.alphas)
     assert rep.converged and np.array_equal(Pr, P)
-    # a wrong sequence ends with the wrong trace
+    # a corrupted sequence must be caught by the final trace check
     bad = list(ok.alphas)
     bad[3] = -bad[3]
     _, wr = oracle.dense_sp2(s.H, s.n_occ, alpha_seq=bad)
