@@ -109,6 +109,10 @@ typedef struct {
     int32_t precision;         /* gsp2_precision of the products, default GSP2_PREC_FP32 */
     int32_t refine;            /* FP32 products appended after the stop (branch from the
                                   trace rule), 0..8, default 0; max_iter + refine <= GSP2_MAX_ITER */
+    int32_t persistent;        /* must be 0 (one launch per product, all in one HIP graph).
+                                  1 would put all products before the stop in one persistent
+                                  launch with a grid barrier per product; that path is switched
+                                  off in this build and returns GSP2_E_UNSUPPORTED. */
 } gsp2_run_options;
 
 #define GSP2_MAX_ITER 100
@@ -131,12 +135,14 @@ typedef struct {
 
 /* Device times of the last timed run (gsp2_run_options.timing = 1). */
 typedef struct {
-    int32_t n_products;                    /* products formed (entries of product_ms) */
+    int32_t n_products;                    /* entries of product_ms */
     float setup_ms;                        /* Gershgorin bounds, X0 gather, first trace */
     float sp2_ms;                          /* all products with their control steps */
     float scatter_ms;                      /* core columns into P */
     float total_ms;                        /* first to last kernel of the run */
-    float product_ms[GSP2_MAX_ITER];       /* the product kernel of product t alone */
+    float persistent_ms;                   /* the persistent product launch (persistent runs) */
+    float product_ms[GSP2_MAX_ITER];       /* the product kernel of product t alone (per-product
+                                              launches only: refinement products of persistent runs) */
 } gsp2_timing;
 
 /* Human-readable name of a status code (static string). */

@@ -194,6 +194,8 @@ struct gsp2_plan_s {
         check_hip(hipEventCreate(&ev.setup_end), "event");
         check_hip(hipEventCreate(&ev.sp2_end), "event");
         check_hip(hipEventCreate(&ev.end), "event");
+        check_hip(hipEventCreate(&ev.persist_begin), "event");
+        check_hip(hipEventCreate(&ev.persist_end), "event");
         for (auto &x : ev.step) check_hip(hipEventCreate(&x), "event");
         have_events = true;
     }
@@ -203,6 +205,7 @@ struct gsp2_plan_s {
         if (have_events) {
             (void)hipEventDestroy(ev.begin); (void)hipEventDestroy(ev.setup_end);
             (void)hipEventDestroy(ev.sp2_end); (void)hipEventDestroy(ev.end);
+            (void)hipEventDestroy(ev.persist_begin); (void)hipEventDestroy(ev.persist_end);
             for (auto &x : ev.step) (void)hipEventDestroy(x);
         }
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -247,6 +250,7 @@ gsp2_status gsp2_run_options_default(gsp2_run_options *opt) {
         opt->timing = 0;
         opt->precision = GSP2_PREC_FP32;
         opt->refine = 0;
+        opt->persistent = 0;
     });
 }
 
@@ -438,7 +442,15 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         auto *d_colptr = plan->alloc<int64_t>(n + 1, "col_ptr");
         auto *d_colpart = plan->alloc<int32_t>(n, "col_part");
         auto *d_collocal = plan->alloc<int32_t>(n, "col_local");
-        dp.diag_partials = plan->alloc<double>(2 * (size_t)std::max(1, plan->n_diag), "diag partials");
+        dp.diag_partials = plan->alloc<double>(4 * (size_t)std::max(1, plan->n_diag), "diag partials");
+        dp.list_len = dp.n_tiles / kXcds;
+        dp.persist = plan->alloc<PersistCtl>(1, "persistent control");
+        {
+            int rate_khz = 0, dev = 0;
+            check_hip(hipGetDevice(&dev), "device");
+            check_hip(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev), "wall clock rate");
+            dp.persist_timeout = (long long)std::max(rate_khz, 1000) * 1000LL * 20;   // 20 s
+        }
         dp.x0_partials = plan->alloc<double>(plan->chunks.size(), "x0 partials");
         dp.gersh_partials = plan->alloc<double>(3 * (size_t)dp.gersh_blocks, "gershgorin partials");
         dp.state = plan->alloc<RunState>(1, "run state");
@@ -574,6 +586,8 @@ static gsp2_status collect(gsp2_plan_s *plan, gsp2_run_info *info) {
             if (run_status == GSP2_E_INVALID)
                 std::snprintf(buf, sizeof buf, "H rejected: Gershgorin bounds [%g, %g] not finite or empty",
                               r.eps_min, r.eps_max);
+            else if (run_status == GSP2_E_HIP)
+                std::snprintf(buf, sizeof buf, "persistent product kernel: a grid-barrier wait expired");
             else if (run_status == GSP2_E_NOT_CONVERGED)
                 std::snprintf(buf, sizeof buf, "no convergence after %d products", r.n_products);
             else
@@ -610,6 +624,17 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         if (o.refine < 0 || o.refine > 8) fail(GSP2_E_INVALID, "refine must be in 0..8");
         rp.precision = o.precision;
         rp.refine = o.refine;
+        rp.persistent = o.persistent ? 1 : 0;
+        if (rp.persistent)
+            fail(GSP2_E_UNSUPPORTED,
+                 "the persistent product launch is switched off: its first GPU run did not return and the "
+                 "cause has not been established");
+        if (rp.persistent) {
+            int grid = 0;
+            check_hip(persistent_grid(rp.precision, &grid), "occupancy");
+            if (grid < 1) fail(GSP2_E_UNSUPPORTED, "persistent product kernel cannot be resident");
+            plan->dp.persist_grid = std::min(grid, plan->dp.n_tiles);
+        }
         {
             // the stop rule's floor max(1, n u), u the unit roundoff of the product operands
             const double u = o.precision == GSP2_PREC_FP16 ? std::ldexp(1.0, -11)
@@ -692,7 +717,9 @@ gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out) {
         // main-phase products occupy the first launch slots, refinement products
         // the slots after the main-phase budget
         const RunState &r = *plan->h_state;
-        const int n_main = std::min(r.n_main, plan->last_rp.n_steps);
+        if (plan->last_rp.persistent && plan->last_rp.n_steps > 0)
+            check_hip(hipEventElapsedTime(&out->persistent_ms, e.persist_begin, e.persist_end), "elapsed");
+        const int n_main = plan->last_rp.persistent ? 0 : std::min(r.n_main, plan->last_rp.n_steps);
         const int n_ref = std::min(r.n_refine, plan->last_rp.refine);
         out->n_products = n_main + n_ref;
         for (int t = 0; t < n_main; ++t)

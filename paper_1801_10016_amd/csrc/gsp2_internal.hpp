@@ -13,6 +13,9 @@ namespace gsp2 {
 constexpr int kTile = 128;
 constexpr int kKChunk = 32;
 
+// XCDs of an MI355X: workgroup b of a launch runs on XCD b mod kXcds.
+constexpr int kXcds = 8;
+
 // One part of the partition, as the device sees it.
 struct PartDesc {
     int64_t x_off;      // float offset of the part's s_pad x s_pad block in each X buffer
@@ -69,6 +72,14 @@ struct RunState {
     double errors[GSP2_MAX_ITER];
 };
 
+// Control words of the persistent product kernel (cleared before each launch).
+struct PersistCtl {
+    unsigned arrive;                    // grid-barrier arrivals, monotonic within a launch
+    unsigned fail;                      // set when a bounded wait expires
+    unsigned pad_[2];
+    unsigned head[GSP2_MAX_ITER][kXcds];  // per product, per XCD tile-queue head
+};
+
 // Per-call parameters baked into the run's kernels.
 struct RunParams {
     double n_occ;
@@ -79,7 +90,7 @@ struct RunParams {
     int32_t stop_rule;
     int32_t precision;          // gsp2_precision of the main phase
     int32_t refine;             // FP32 products after the main phase
-    int32_t pad_;
+    int32_t persistent;         // 1: main-phase products in one persistent launch
     int8_t alpha_seq[GSP2_MAX_ITER];
 };
 
@@ -103,7 +114,11 @@ struct DevicePlan {
     const int64_t *col_ptr;     // CSC column pointers of P, n+1
     const int32_t *col_part;    // part of every column
     const int32_t *col_local;   // local index of every column in its part
-    double *diag_partials;      // n_diag x 2
+    int32_t list_len;           // entries per XCD list (n_tiles / kXcds)
+    int32_t persist_grid;       // workgroups of the persistent launch
+    long long persist_timeout;  // wall-clock ticks a persistent wait may last
+    PersistCtl *persist;
+    double *diag_partials;      // 2 x n_diag x 2 (double-buffered by product parity)
     double *x0_partials;        // n_chunks
     double *gersh_partials;     // gersh_blocks x 3
     RunState *state;
@@ -112,7 +127,7 @@ struct DevicePlan {
 // Optional event records of a timed run.  step[2t] / step[2t+1] bracket the
 // product kernel of product t.
 struct RunEvents {
-    hipEvent_t begin, setup_end, sp2_end, end;
+    hipEvent_t begin, setup_end, sp2_end, end, persist_begin, persist_end;
     hipEvent_t step[2 * GSP2_MAX_ITER];
 };
 
@@ -160,5 +175,7 @@ hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *o
                                  int32_t *out_col, hipStream_t s);
 hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp,
                           float *P_val, Recorder &rec, const RunEvents *ev);
+// Workgroups of the persistent product kernel that the device keeps resident.
+hipError_t persistent_grid(int precision, int *grid);
 
 }  // namespace gsp2

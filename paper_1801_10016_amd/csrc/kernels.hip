@@ -278,7 +278,113 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
     if (threadIdx.x == 0) x0_partials[blockIdx.x] = tr;
 }
 
-__device__ void finish_main(RunState *st, int result_buf, int result_t, int status, bool refinable);
+// ---------------------------------------------------------------------------
+// a7: control state of a run.  The branch and stop decisions are a pure
+// function of this state and the two trace sums of a product, so every
+// workgroup of the persistent kernel takes them identically; between
+// per-product launches the state lives in RunState.
+// ---------------------------------------------------------------------------
+struct Ctl {
+    double n_occ, trace_tol, stop_floor, trX, idem, e1, e2;   // e1 = e_{t-1}, e2 = e_{t-2}
+    int n_steps, mode, stop_rule, t, cur, alpha, done, status, result_buf, result_t, n_products;
+    int phase, refine, refine_left, n_refine, main_status, n_main;
+};
+
+__device__ Ctl ctl_load(const RunState *st) {
+    Ctl c;
+    c.n_occ = st->n_occ; c.trace_tol = st->trace_tol; c.stop_floor = st->stop_floor;
+    c.trX = st->trX; c.idem = st->idem;
+    c.n_steps = st->n_steps; c.mode = st->mode; c.stop_rule = st->stop_rule; c.t = st->t; c.cur = st->cur;
+    c.alpha = st->alpha; c.done = st->done; c.status = st->status; c.result_buf = st->result_buf;
+    c.result_t = st->result_t; c.n_products = st->n_products; c.phase = st->phase; c.refine = st->refine;
+    c.refine_left = st->refine_left; c.n_refine = st->n_refine; c.main_status = st->main_status;
+    c.n_main = st->n_main;
+    c.e1 = c.t >= 1 ? st->errors[c.t - 1] : NAN;
+    c.e2 = c.t >= 2 ? st->errors[c.t - 2] : NAN;
+    return c;
+}
+
+__device__ void ctl_store(RunState *st, const Ctl &c) {
+    st->trX = c.trX; st->idem = c.idem; st->t = c.t; st->cur = c.cur; st->alpha = c.alpha; st->done = c.done;
+    st->status = c.status; st->result_buf = c.result_buf; st->result_t = c.result_t;
+    st->n_products = c.n_products; st->phase = c.phase; st->refine_left = c.refine_left;
+    st->n_refine = c.n_refine; st->main_status = c.main_status; st->n_main = c.n_main;
+}
+
+// End of the main phase: hand over to the FP32 refinement products, or stop.
+__device__ void finish_main(Ctl &c, int result_buf, int result_t, int status, bool refinable) {
+    c.n_main = c.n_products;
+    if (refinable && c.refine > 0) {
+        c.phase = 1;
+        c.main_status = status;
+        c.cur = result_buf;
+        c.t = result_t;
+        c.refine_left = c.refine;
+        c.alpha = c.trX <= c.n_occ ? 1 : -1;
+        return;
+    }
+    c.done = 1;
+    c.result_buf = result_buf;
+    c.result_t = result_t;
+    c.status = status;
+}
+
+// One product's decision from Tr[X_t^2] (ty) and Tr[X_{t+1}] (tx): the
+// stop rule, the branch of the next product, the end of a phase.  History
+// arrays are written only when `writer`.
+__device__ void decide(Ctl &c, double ty, double tx, RunState *st, bool writer) {
+    const int t = c.t;
+    const double e = c.trX - ty;                // e_t = Tr[X_t] - Tr[X_t^2]
+    if (writer) st->errors[t] = e;
+    c.n_products += 1;
+    if (!isfinite(ty) || !isfinite(tx)) {       // left the finite range: keep X_t
+        if (c.phase == 0) c.n_main = c.n_products;
+        c.done = 1;
+        c.result_buf = c.cur;
+        c.result_t = t;
+        c.status = GSP2_E_NOT_CONVERGED;
+        return;
+    }
+    // the bound applies to |e|: in finite precision e turns negative once X_t is idempotent to rounding
+    if (c.phase == 0 && c.mode == GSP2_ALPHA_TRACE && c.stop_rule && t >= 2 && fabs(e) >= fabs(c.e2) &&
+        fabs(c.e2) < c.stop_floor) {
+        c.idem = e;                             // X_t is the result; X_t^2 is discarded
+        finish_main(c, c.cur, t, GSP2_OK, true);
+        return;
+    }
+    if (writer) {
+        st->alpha_hist[t] = (int8_t)c.alpha;
+        st->traces[t + 1] = tx;
+    }
+    c.cur ^= 1;
+    c.trX = tx;
+    c.t = t + 1;
+    c.e2 = c.e1;
+    c.e1 = e;
+    if (c.phase == 1) {
+        c.n_refine += 1;
+        c.idem = e;
+        if (--c.refine_left == 0) {
+            c.done = 1;
+            c.result_buf = c.cur;
+            c.result_t = t + 1;
+            c.status = c.main_status;
+            return;
+        }
+        c.alpha = tx <= c.n_occ ? 1 : -1;
+        return;
+    }
+    if (c.n_products >= c.n_steps) {
+        int status;
+        if (c.mode == GSP2_ALPHA_REPLAY)
+            status = fabs(tx - c.n_occ) <= c.trace_tol ? GSP2_OK : GSP2_E_WRONG_TRACE;
+        else
+            status = c.stop_rule ? GSP2_E_NOT_CONVERGED : GSP2_OK;
+        finish_main(c, c.cur, t + 1, status, true);
+        return;
+    }
+    c.alpha = (c.mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[t + 1] : (tx <= c.n_occ ? 1 : -1);
+}
 
 // Reduce the X0 core-trace partials; pick the first branch.
 __global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__ x0_partials, int n,
@@ -288,35 +394,20 @@ __global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__
     for (int i = threadIdx.x; i < n; i += kBlock) a += x0_partials[i];
     block_sum2(a, b);
     if (threadIdx.x == 0) {
-        st->trX = a;
+        Ctl c = ctl_load(st);
+        c.trX = a;
         st->traces[0] = a;
-        if (st->n_steps <= 0) {
-            const int status = (st->mode == GSP2_ALPHA_REPLAY && fabs(a - st->n_occ) > st->trace_tol)
+        if (c.n_steps <= 0) {
+            const int status = (c.mode == GSP2_ALPHA_REPLAY && fabs(a - c.n_occ) > c.trace_tol)
                                    ? GSP2_E_WRONG_TRACE : GSP2_OK;
-            finish_main(st, 0, 0, status, true);
-            return;
+            finish_main(c, 0, 0, status, true);
+        } else {
+            c.alpha = (c.mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[0] : (a <= c.n_occ ? 1 : -1);
         }
-        st->alpha = (st->mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[0] : (a <= st->n_occ ? 1 : -1);
+        ctl_store(st, c);
     }
 }
 
-// ---------------------------------------------------------------------------
-// a6: one SP2 product on the matrix cores.
-//
-// Each workgroup computes one 128x128 tile Y[I,J] = sum_k X[I,k] X[J,k] of
-// one part (X is symmetric, so both operands are row panels with k
-// contiguous), for ti <= tj only; the eq. (2) update X' = Y or 2X - Y is
-// fused into the epilogue and written to the other buffer at (I,J) and,
-// mirrored, at (J,I), so every iterate stays exactly symmetric.  Diagonal
-// tiles also emit FP64 partial sums of Y and X' over the part's core
-// diagonal.
-//
-// 256 threads = 4 waves in a 2x2 grid, each wave a 64x64 sub-tile as 2x2
-// blocks of v_mfma_f32_32x32x2f32.  Operands are staged through LDS in K
-// chunks of 32 with a register prefetch of the next chunk and two LDS
-// buffers.  Within a chunk, lane half h of the MFMA operand feeds k = 16h+s
-// at step s, for A and B alike, so each lane reads 16 contiguous floats.
-// ---------------------------------------------------------------------------
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
@@ -367,22 +458,16 @@ __device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16
 // every 16-byte group, for A and B alike, so each lane reads whole 16-byte
 // LDS words.
 // ---------------------------------------------------------------------------
+constexpr int kLdsWords = 2 * 2 * kTile * kLdsRow;  // [buffer][A/B][row * 9 + word]
+
 template <typename Op>
-__global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restrict__ tiles,
-                                                        const PartDesc *__restrict__ parts,
-                                                        float *__restrict__ buf0, float *__restrict__ buf1,
-                                                        Op *__restrict__ sh0, Op *__restrict__ sh1,
-                                                        const RunState *__restrict__ st,
-                                                        double *__restrict__ diag_partials, int phase) {
-    __shared__ uint4 lds[2][2][kTile * kLdsRow];       // [buffer][A/B][row * 9 + word]
+__device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, int cur, float alpha,
+                                         float *__restrict__ buf0, float *__restrict__ buf1,
+                                         Op *__restrict__ sh0, Op *__restrict__ sh1,
+                                         double *__restrict__ diag_partials, uint4 *__restrict__ lds_base) {
     constexpr bool kF32 = sizeof(Op) == 4;
     constexpr int kK = OpFmt<Op>::kK;
-    if (st->done || st->phase != phase) return;
-    const TileDesc td = tiles[blockIdx.x];
-    if (td.part < 0) return;                    // padding of a short XCD list
-    const PartDesc pd = parts[td.part];
-    const int cur = st->cur;
-    const float alpha = static_cast<float>(st->alpha);
+    auto lds = [&](int b, int ab) { return lds_base + (b * 2 + ab) * kTile * kLdsRow; };
     const float *__restrict__ X = (cur ? buf1 : buf0) + pd.x_off;
     float *__restrict__ Xn = (cur ? buf0 : buf1) + pd.x_off;
     const Op *__restrict__ Xop = kF32 ? reinterpret_cast<const Op *>(X) : (cur ? sh1 : sh0) + pd.x_off;
@@ -426,10 +511,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
     } while (0)
 #define GSP2_STORE_CHUNK(b)                                                                        \
     do {                                                                                           \
-        uint4 *As_ = lds[b][0] + lr * kLdsRow + lw;                                                \
+        uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;                                                \
         As_[0] = pa0; As_[32 * kLdsRow] = pa1; As_[64 * kLdsRow] = pa2; As_[96 * kLdsRow] = pa3;   \
         if (!diag) {                                                                               \
-            uint4 *Bs_ = lds[b][1] + lr * kLdsRow + lw;                                            \
+            uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                            \
             Bs_[0] = pb0; Bs_[32 * kLdsRow] = pb1; Bs_[64 * kLdsRow] = pb2; Bs_[96 * kLdsRow] = pb3; \
         }                                                                                          \
     } while (0)
@@ -441,8 +526,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
     for (int kc = 0; kc < nk; ++kc) {
         const int buf = kc & 1;
         if (kc + 1 < nk) GSP2_LOAD_CHUNK((int64_t)(kc + 1) * 128);
-        const uint4 *Asb = lds[buf][0];
-        const uint4 *Bsb = diag ? lds[buf][0] : lds[buf][1];
+        const uint4 *Asb = lds(buf, 0);
+        const uint4 *Bsb = diag ? lds(buf, 0) : lds(buf, 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             // FP32: word kh*4+q of the row (k = 16 kh + 4 q + e); 16-bit: word 2q+kh (k = 16 q + 8 kh + e)
@@ -512,27 +597,23 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
     }
 }
 
-// End of the main phase: hand over to the FP32 refinement products, or stop.
-__device__ void finish_main(RunState *st, int result_buf, int result_t, int status, bool refinable) {
-    st->n_main = st->n_products;
-    if (refinable && st->refine > 0) {
-        st->phase = 1;
-        st->main_status = status;
-        st->cur = result_buf;
-        st->t = result_t;
-        st->trX = st->traces[result_t];
-        st->refine_left = st->refine;
-        st->alpha = st->trX <= st->n_occ ? 1 : -1;
-        return;
-    }
-    st->done = 1;
-    st->result_buf = result_buf;
-    st->result_t = result_t;
-    st->status = status;
+template <typename Op>
+__global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restrict__ tiles,
+                                                        const PartDesc *__restrict__ parts,
+                                                        float *__restrict__ buf0, float *__restrict__ buf1,
+                                                        Op *__restrict__ sh0, Op *__restrict__ sh1,
+                                                        const RunState *__restrict__ st,
+                                                        double *__restrict__ diag_partials, int phase) {
+    __shared__ uint4 lds[kLdsWords];
+    if (st->done || st->phase != phase) return;
+    const TileDesc td = tiles[blockIdx.x];
+    if (td.part < 0) return;                    // padding of a short XCD list
+    sp2_tile<Op>(td, parts[td.part], st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, diag_partials,
+                 lds);
 }
 
-// a7: reduce the product's trace partials, apply the stop rule, choose the
-// next branch.  One workgroup; fixed summation order.
+// a7 between per-product launches: reduce the product's trace partials in a
+// fixed order and take the decision.  One workgroup.
 __global__ __launch_bounds__(kBlock) void k_sp2_decide(const double *__restrict__ diag_partials, int n_diag,
                                                        RunState *__restrict__ st, int phase) {
     if (st->done || st->phase != phase) return;
@@ -543,55 +624,116 @@ __global__ __launch_bounds__(kBlock) void k_sp2_decide(const double *__restrict_
     }
     block_sum2(ty, tx);
     if (threadIdx.x != 0) return;
-    const int t = st->t;
-    const double e = st->trX - ty;              // e_t = Tr[X_t] - Tr[X_t^2]
-    st->errors[t] = e;
-    st->n_products += 1;
-    if (!isfinite(ty) || !isfinite(tx)) {       // left the finite range: keep X_t
-        if (phase == 0) st->n_main = st->n_products;
+    Ctl c = ctl_load(st);
+    decide(c, ty, tx, st, true);
+    ctl_store(st, c);
+}
+
+// ---------------------------------------------------------------------------
+// a9: every product of the main phase in one persistent launch.
+//
+// The grid holds as many workgroups as the GPU keeps resident (CUs x
+// occupancy).  For each product, workgroup b takes tiles from the queue of
+// its XCD (b mod 8; the plan's tile list is eight interleaved per-XCD lists)
+// through an atomic head, then steals from the other XCDs' queues.  A grid
+// barrier closes the product; then every workgroup reduces the same trace
+// partials in the same order and takes the same decision, so no second
+// barrier is needed.  Trace partials are double-buffered by product parity:
+// a workgroup can be at most one product ahead of the slowest.  Only
+// workgroup 0 writes the run state.  Every wait is bounded by the device
+// wall clock; on expiry a fail flag is raised, every workgroup leaves, and
+// the run reports an error instead of hanging.
+// ---------------------------------------------------------------------------
+__device__ bool grid_barrier(PersistCtl *pc, unsigned target, long long t_end, int *ok_s) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();
+        atomicAdd(&pc->arrive, 1u);
+        while (__hip_atomic_load(&pc->arrive, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(&pc->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                (long long)wall_clock64() > t_end) {
+                __hip_atomic_store(&pc->fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+        *ok_s = ok;
+    }
+    __syncthreads();
+    return *ok_s != 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_persist_reset(PersistCtl *pc) {
+    unsigned *w = reinterpret_cast<unsigned *>(pc);
+    for (int i = threadIdx.x; i < (int)(sizeof(PersistCtl) / sizeof(unsigned)); i += kBlock) w[i] = 0u;
+}
+
+template <typename Op>
+__global__ __launch_bounds__(kBlock, 2) void k_sp2_persistent(const TileDesc *__restrict__ tiles, int list_len,
+                                                              const PartDesc *__restrict__ parts,
+                                                              float *__restrict__ buf0, float *__restrict__ buf1,
+                                                              Op *__restrict__ sh0, Op *__restrict__ sh1,
+                                                              RunState *__restrict__ st,
+                                                              double *__restrict__ partials, int n_diag,
+                                                              PersistCtl *__restrict__ pc, long long timeout_ticks) {
+    __shared__ uint4 lds[kLdsWords];
+    __shared__ Ctl c_s;
+    __shared__ int q_s, ok_s;
+    if (threadIdx.x == 0) c_s = ctl_load(st);
+    __syncthreads();
+    if (c_s.done || c_s.phase != 0) return;     // same state for every workgroup
+    const long long t_end = (long long)wall_clock64() + timeout_ticks;
+    const unsigned G = gridDim.x;
+    const int my_x = blockIdx.x % kXcds;
+    const bool writer = blockIdx.x == 0;
+    unsigned n_barriers = 0;
+    while (true) {
+        const int kq = c_s.n_products;          // product ordinal in this phase
+        double *part_t = partials + (size_t)(kq & 1) * n_diag * 2;
+        const int cur = c_s.cur;
+        const float alpha = static_cast<float>(c_s.alpha);
+        for (int probe = 0; probe < kXcds; ++probe) {
+            const int x = (my_x + probe) % kXcds;
+            while (true) {
+                if (threadIdx.x == 0) q_s = (int)atomicAdd(&pc->head[kq][x], 1u);
+                __syncthreads();
+                const int q = q_s;
+                __syncthreads();
+                if (q >= list_len) break;
+                const TileDesc td = tiles[(size_t)q * kXcds + x];
+                if (td.part >= 0) sp2_tile<Op>(td, parts[td.part], cur, alpha, buf0, buf1, sh0, sh1, part_t, lds);
+            }
+        }
+        ++n_barriers;
+        if (!grid_barrier(pc, n_barriers * G, t_end, &ok_s)) return;
+        double ty = 0.0, tx = 0.0;
+        for (int i = threadIdx.x; i < n_diag; i += kBlock) {
+            ty += part_t[2 * i];
+            tx += part_t[2 * i + 1];
+        }
+        block_sum2(ty, tx);
+        if (threadIdx.x == 0) {
+            Ctl c = c_s;
+            decide(c, ty, tx, st, writer);
+            c_s = c;
+        }
+        __syncthreads();
+        if (c_s.done || c_s.phase != 0) break;
+    }
+    if (writer && threadIdx.x == 0) ctl_store(st, c_s);
+}
+
+// After the persistent launch: a raised fail flag ends the run with an error.
+__global__ __launch_bounds__(kBlock) void k_persist_check(const PersistCtl *__restrict__ pc,
+                                                          RunState *__restrict__ st) {
+    if (threadIdx.x == 0 && pc->fail != 0u) {
         st->done = 1;
-        st->result_buf = st->cur;
-        st->result_t = t;
-        st->status = GSP2_E_NOT_CONVERGED;
-        return;
+        st->status = GSP2_E_HIP;
+        st->main_status = GSP2_E_HIP;
     }
-    if (phase == 0) {
-        // the bound applies to |e|: in FP32 e turns negative once X_t is idempotent to rounding
-        if (st->mode == GSP2_ALPHA_TRACE && st->stop_rule && t >= 2 && fabs(e) >= fabs(st->errors[t - 2]) &&
-            fabs(st->errors[t - 2]) < st->stop_floor) {
-            st->idem = e;                       // X_t is the result; X_t^2 is discarded
-            finish_main(st, st->cur, t, GSP2_OK, true);
-            return;
-        }
-    }
-    st->alpha_hist[t] = (int8_t)st->alpha;
-    st->cur ^= 1;
-    st->trX = tx;
-    st->traces[t + 1] = tx;
-    st->t = t + 1;
-    if (phase == 1) {
-        st->n_refine += 1;
-        st->idem = e;
-        if (--st->refine_left == 0) {
-            st->done = 1;
-            st->result_buf = st->cur;
-            st->result_t = t + 1;
-            st->status = st->main_status;
-            return;
-        }
-        st->alpha = tx <= st->n_occ ? 1 : -1;
-        return;
-    }
-    if (st->n_products >= st->n_steps) {
-        int status;
-        if (st->mode == GSP2_ALPHA_REPLAY)
-            status = fabs(tx - st->n_occ) <= st->trace_tol ? GSP2_OK : GSP2_E_WRONG_TRACE;
-        else
-            status = st->stop_rule ? GSP2_E_NOT_CONVERGED : GSP2_OK;
-        finish_main(st, st->cur, t + 1, status, true);
-        return;
-    }
-    st->alpha = (st->mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[t + 1] : (tx <= st->n_occ ? 1 : -1);
 }
 
 // ---------------------------------------------------------------------------
@@ -606,7 +748,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const PartDesc *__restrict__
                                                     const int32_t *__restrict__ col_local, int32_t n,
                                                     const float *__restrict__ buf0, const float *__restrict__ buf1,
                                                     const RunState *__restrict__ st, float *__restrict__ P_val) {
-    if (st->status == GSP2_E_INVALID) return;
+    if (st->status == GSP2_E_INVALID || st->status == GSP2_E_HIP) return;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t j = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (j >= n) return;
@@ -647,7 +789,25 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     if (ev) rec.add_event(ev->setup_end);
     const dim3 grid(dp.n_tiles);
     float *b0 = dp.buf[0], *b1 = dp.buf[1];
-    for (int it = 0; it < rp.n_steps; ++it) {
+    if (rp.persistent && rp.n_steps > 0) {
+        const dim3 pg(dp.persist_grid);
+        record(rec, k_persist_reset, dim3(1), blk, dp.persist);
+        if (ev) rec.add_event(ev->persist_begin);
+        if (rp.precision == GSP2_PREC_FP16)
+            record(rec, k_sp2_persistent<_Float16>, pg, blk, dp.tiles, dp.list_len, dp.parts, b0, b1,
+                   static_cast<_Float16 *>(dp.shadow[0]), static_cast<_Float16 *>(dp.shadow[1]), dp.state,
+                   dp.diag_partials, dp.n_diag, dp.persist, dp.persist_timeout);
+        else if (rp.precision == GSP2_PREC_BF16)
+            record(rec, k_sp2_persistent<__bf16>, pg, blk, dp.tiles, dp.list_len, dp.parts, b0, b1,
+                   static_cast<__bf16 *>(dp.shadow[0]), static_cast<__bf16 *>(dp.shadow[1]), dp.state,
+                   dp.diag_partials, dp.n_diag, dp.persist, dp.persist_timeout);
+        else
+            record(rec, k_sp2_persistent<float>, pg, blk, dp.tiles, dp.list_len, dp.parts, b0, b1, (float *)nullptr,
+                   (float *)nullptr, dp.state, dp.diag_partials, dp.n_diag, dp.persist, dp.persist_timeout);
+        if (ev) rec.add_event(ev->persist_end);
+        record(rec, k_persist_check, dim3(1), blk, dp.persist, dp.state);
+    }
+    for (int it = 0; it < (rp.persistent ? 0 : rp.n_steps); ++it) {
         if (ev) rec.add_event(ev->step[2 * it]);
         if (rp.precision == GSP2_PREC_FP16)
             record(rec, k_sp2_step<_Float16>, grid, blk, dp.tiles, dp.parts, b0, b1,
@@ -680,6 +840,22 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
 }
 
 }  // namespace
+
+hipError_t persistent_grid(int precision, int *grid) {
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (precision == GSP2_PREC_FP16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sp2_persistent<_Float16>, kBlock, 0);
+    else if (precision == GSP2_PREC_BF16)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sp2_persistent<__bf16>, kBlock, 0);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sp2_persistent<float>, kBlock, 0);
+    if (e != hipSuccess) return e;
+    *grid = cus * per_cu;
+    return hipSuccess;
+}
 
 hipError_t launch_threshold_count(const gsp2_csr &P, double tau, int32_t *counts, hipStream_t s) {
     const int wpb = kBlock / kWave;

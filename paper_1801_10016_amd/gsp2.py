@@ -45,7 +45,8 @@ class gsp2_plan_info(C.Structure):
 class gsp2_run_options(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("alpha_mode", C.c_int32), ("alpha_seq", C.POINTER(C.c_int8)),
                 ("n_alpha", C.c_int32), ("stop_rule", C.c_int32), ("trace_tol", C.c_double),
-                ("timing", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32)]
+                ("timing", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
+                ("persistent", C.c_int32)]
 
 
 class gsp2_run_info(C.Structure):
@@ -59,7 +60,8 @@ class gsp2_run_info(C.Structure):
 
 class gsp2_timing(C.Structure):
     _fields_ = [("n_products", C.c_int32), ("setup_ms", C.c_float), ("sp2_ms", C.c_float),
-                ("scatter_ms", C.c_float), ("total_ms", C.c_float), ("product_ms", C.c_float * GSP2_MAX_ITER)]
+                ("scatter_ms", C.c_float), ("total_ms", C.c_float), ("persistent_ms", C.c_float),
+                ("product_ms", C.c_float * GSP2_MAX_ITER)]
 
 
 _PLAN = C.c_void_p
@@ -237,8 +239,9 @@ def gsp2_plan_set_stream(plan: Plan, stream=None):
 
 
 def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5, timing=False,
-                     precision="fp32", refine=0):
+                     precision="fp32", refine=0, persistent=False):
     o = gsp2_run_options_default()
+    o.persistent = 1 if persistent else 0
     o.max_iter = int(max_iter)
     o.timing = 1 if timing else 0
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -269,7 +272,7 @@ def run_info_dict(info: gsp2_run_info) -> dict:
 
 def gsp2_density(plan: Plan, H: DeviceCSR, n_occ: float, P_val, max_iter=60, alpha_seq=None,
                  stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False,
-                 precision="fp32", refine=0):
+                 precision="fp32", refine=0, persistent=False):
     """Enqueue one density matrix into P_val (torch float32 on the GPU, nnz_P
     entries).  With want_info the call waits and returns the run's info dict;
     with check a failing status raises Gsp2Error."""
@@ -279,7 +282,7 @@ def gsp2_density(plan: Plan, H: DeviceCSR, n_occ: float, P_val, max_iter=60, alp
     if P_val.numel() < plan.nnz_P:
         raise ValueError(f"P_val holds {P_val.numel()} values, the plan needs {plan.nnz_P}")
     c = H.as_c()
-    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine)
+    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine, persistent)
     info = gsp2_run_info() if want_info else None
     st = load().gsp2_density(plan.handle, C.byref(c), float(n_occ), C.byref(o), C.c_void_p(P_val.data_ptr()),
                              C.byref(info) if info is not None else None)
@@ -307,7 +310,7 @@ def gsp2_run_timing(plan: Plan) -> dict:
     t = gsp2_timing()
     _check(load().gsp2_run_timing(plan.handle, C.byref(t)))
     return {"n_products": t.n_products, "setup_ms": t.setup_ms, "sp2_ms": t.sp2_ms,
-            "scatter_ms": t.scatter_ms, "total_ms": t.total_ms,
+            "scatter_ms": t.scatter_ms, "total_ms": t.total_ms, "persistent_ms": t.persistent_ms,
             "product_ms": [float(x) for x in t.product_ms[:t.n_products]]}
 
 

@@ -152,3 +152,15 @@ def test_mixed_precision_error_vs_oracle(case, precision, bar):
               flush=True)
         if refine == 0:
             assert max(errs.values()) <= bar
+
+
+@pytest.mark.skip(reason="persistent product launch switched off: its first GPU run did not return "
+                         "within 120 s and the cause has not been established (see the design notes)")
+def test_persistent_launch_full_size(case):
+    """The full workload with every product in one persistent launch gives the
+    same bits as one launch per product."""
+    gold = case["gold"]
+    _, v1 = _run(case, alpha_seq=gold["alphas"], trace_tol=1e9)
+    run, v2 = _run(case, alpha_seq=gold["alphas"], trace_tol=1e9, persistent=True)
+    assert run["n_products"] == len(gold["alphas"])
+    assert np.array_equal(v1, v2)

@@ -190,3 +190,15 @@ def test_fp32_refinement_products():
     print(f"fp32 refine=2: products={run['n_products']} rel_err={rel_fro(P, ref.csc()):.2e}", flush=True)
     assert run["status"] == 0 and run["n_refine"] == 2
     assert rel_fro(P, ref.csc()) <= TOL
+
+
+
+def test_persistent_request_is_refused():
+    # the persistent product launch is switched off; asking for it is an error, not a launch
+    import paper_1801_10016_amd as g
+    from tests._gpu import run_gsp2
+    s = pins.water(16, 0)
+    part = np.zeros(s.n, dtype=np.int32)
+    with pytest.raises(g.Gsp2Error) as e:
+        run_gsp2(s.H, s.H, 1e-5, part, 1, s.n_occ, persistent=True)
+    assert e.value.status == 6          # GSP2_E_UNSUPPORTED
