@@ -226,3 +226,45 @@ def perturb(system: WaterSystem, sigma: float, seed: int) -> WaterSystem:
     return WaterSystem(n_mol=system.n_mol, box=system.box, atoms=atoms, H=H,
                        n_occ=system.n_occ, seed=system.seed, hop_a=system.hop_a,
                        hop_lam=system.hop_lam, meta={"perturbed": sigma, "perturb_seed": seed})
+
+
+def hopping_derivatives(system: WaterSystem) -> tuple[sp.csr_matrix, sp.csr_matrix]:
+    """dH/dA and dH/dlam of the intermolecular hopping -A exp(-(r - r0)/lam),
+    as CSR matrices on the intermolecular entries of H (input generator
+    derivatives, for chain-rule checks of gradients with respect to H)."""
+    atoms, L = system.atoms, system.box
+    N = system.n
+    tree = cKDTree(atoms, boxsize=L)
+    pairs = tree.query_pairs(HOP_RCUT, output_type="ndarray")
+    if len(pairs):
+        pairs = pairs[(pairs[:, 0] // 3) != (pairs[:, 1] // 3)]
+    rows, cols, dA, dl = [], [], [], []
+    if len(pairs):
+        d = _min_image(atoms[pairs[:, 1]] - atoms[pairs[:, 0]], L)
+        r = np.linalg.norm(d, axis=1)
+        keep = r < HOP_RCUT
+        pairs, r = pairs[keep], r[keep]
+        ex = np.exp(-(r - HOP_R0) / system.hop_lam)
+        ga = -ex
+        gl = -system.hop_a * ex * (r - HOP_R0) / system.hop_lam ** 2
+        for ka in range(3):
+            for kb in range(3):
+                sel = ((pairs[:, 0] % 3) == ka) & ((pairs[:, 1] % 3) == kb)
+                if not sel.any():
+                    continue
+                pa, pb = pairs[sel, 0], pairs[sel, 1]
+                oa = ORB_PER_MOL * (pa // 3)[:, None] + _ATOM_ORBS[ka][None, :]
+                ob = ORB_PER_MOL * (pb // 3)[:, None] + _ATOM_ORBS[kb][None, :]
+                ra = np.repeat(oa, ob.shape[1], axis=1).ravel()
+                cb = np.tile(ob, (1, oa.shape[1])).ravel()
+                m = oa.shape[1] * ob.shape[1]
+                va, vl = np.repeat(ga[sel], m), np.repeat(gl[sel], m)
+                rows += [ra, cb]; cols += [cb, ra]; dA += [va, va]; dl += [vl, vl]
+    if not rows:
+        z = sp.csr_matrix((N, N))
+        return z, z
+    r_, c_ = np.concatenate(rows), np.concatenate(cols)
+    DA = sp.coo_matrix((np.concatenate(dA), (r_, c_)), shape=(N, N)).tocsr()
+    DL = sp.coo_matrix((np.concatenate(dl), (r_, c_)), shape=(N, N)).tocsr()
+    DA.sum_duplicates(); DL.sum_duplicates()
+    return DA, DL

@@ -310,7 +310,69 @@ def battery():
     check_gsp2_truncation(water(64, 0))
     check_gsp2_blocks_share_sequence(water(64, 0))
     check_core_column_layout(water(64, 0))
+    check_adjoint_finite_differences()
+    check_adjoint_closed_form()
 
 
 if __name__ == "__main__":
     battery()
+
+
+# -- adjoint of the recursion (oracle/adjoint.py) -----------------------------
+
+def _grad_case():
+    from synth.water import hopping_derivatives
+    s = water(16, 0)
+    P0 = cached(("dense", s.n_mol, s.seed, s.hop_a), lambda: oracle.dense_sp2(s.H, s.n_occ)[0])
+    part = uneven_spatial_partition(s, 3, seed=0)
+    tau = 1e-2
+    fw = oracle.gsp2(s.H, P0, tau, part, 3, s.n_occ)
+    rng = np.random.default_rng(2)
+    W = rng.normal(size=(s.n, s.n))
+    W = W + W.T
+    adj = oracle.threshold_graph(P0, tau)
+
+    def L_of(H):
+        g = oracle.gsp2(H, P0, tau, part, 3, s.n_occ, alpha_seq=fw.sp2.alphas, trace_tol=1e9, adjacency=adj)
+        return float(np.sum(W * g.dense()))
+    gr = oracle.gsp2_grad(s.H, P0, tau, part, 3, fw.sp2.alphas, W)
+    Hc = s.H.tocsr()
+    E = sp.csr_matrix((rng.normal(size=Hc.nnz), Hc.indices, Hc.indptr), shape=Hc.shape)
+    E = 0.5 * (E + E.T)
+    return s, gr, L_of, E, hopping_derivatives(s), fw
+
+
+def check_adjoint_finite_differences():
+    """Central differences (replayed branches) along a random symmetric
+    direction and along dH/dA, dH/dlam of the hopping model."""
+    s, gr, L_of, E, (DA, DL), fw = _grad_case()
+    assert np.array_equal(gr.P, fw.dense())
+    # the gradient under symmetric perturbations is split evenly between H_uv and H_vu
+    assert np.allclose(gr.dH, gr.dH.T, rtol=0, atol=1e-12 * np.abs(gr.dH).max())
+    for D, h, tol in ((E, 1e-4, 1e-6), (DA, 1e-4, 1e-6), (DL, 1e-5, 1e-5)):
+        fd = (L_of(s.H + h * D) - L_of(s.H - h * D)) / (2 * h)
+        an = float(np.sum(gr.dH * D.toarray()))
+        assert abs(fd - an) <= tol * abs(fd), (fd, an)
+
+
+def check_adjoint_closed_form():
+    """Converged dense SP2: the adjoint of the recursion is the derivative of
+    the spectral projector, sum_{o,u} [v_o (v_o^T W v_u) v_u^T + transpose] / (e_o - e_u),
+    and for L = Tr(P H) the part through P vanishes (Hellmann-Feynman)."""
+    s = water(8, 1)
+    Pd, rd = oracle.dense_sp2(s.H, s.n_occ)
+    rng = np.random.default_rng(5)
+    W = rng.normal(size=(s.n, s.n))
+    W = W + W.T
+    one = np.zeros(s.n, dtype=np.int32)
+    g1 = oracle.gsp2_grad(s.H, Pd, 0.0, one, 1, rd.alphas, W)
+    w, V = np.linalg.eigh(s.H.toarray())
+    no = s.n_occ
+    Vo, Vu = V[:, :no], V[:, no:]
+    C = Vo @ ((Vo.T @ W @ Vu) / (w[:no, None] - w[None, no:])) @ Vu.T
+    cf = C + C.T
+    pat = s.H.toarray() != 0
+    cf = np.where(pat, cf, 0.0)
+    assert np.linalg.norm(cf - g1.dH) <= 1e-10 * np.linalg.norm(cf)
+    g2 = oracle.gsp2_grad(s.H, Pd, 0.0, one, 1, rd.alphas, s.H.toarray())
+    assert np.linalg.norm(g2.dH) <= 1e-10 * np.linalg.norm(Pd)

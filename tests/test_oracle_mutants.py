@@ -29,6 +29,11 @@ MUTANTS = {
     "assemble_rows": ("gsp2.py", "P[np.ix_(idx, core)] = blk", "P[np.ix_(core, idx)] = blk.T"),
     "bounds_local": ("gsp2.py", "X0 = [initial_guess(H[idx][:, idx].toarray(), emin, emax) for idx in index]",
                      "X0 = [initial_guess(H[idx][:, idx].toarray(), *gershgorin_bounds(H[idx][:, idx])) for idx in index]"),
+    "adjoint_step_sign": ("adjoint.py", "G = S if alpha_seq[t] < 0 else 2.0 * G - S", "G = S if alpha_seq[t] > 0 else 2.0 * G - S"),
+    "adjoint_one_sided": ("adjoint.py", "S = G @ X + X @ G", "S = 2.0 * (G @ X)"),
+    "adjoint_no_symmetrise": ("adjoint.py", "G = 0.5 * (G + G.T)", "G = G"),
+    "adjoint_x0_sign": ("adjoint.py", "dH[np.ix_(idx, idx)] += -G / D", "dH[np.ix_(idx, idx)] += G / D"),
+    "adjoint_no_bound_terms": ("adjoint.py", "                dH[row, row] += g", "                dH[row, row] += 0.0"),
 }
 
 

@@ -110,3 +110,11 @@ def test_empty_and_full_occupation():
     assert r0.converged and np.abs(P0).max() < 1e-12
     P1, r1 = oracle.dense_sp2(s.H, s.n)
     assert r1.converged and np.allclose(P1, np.eye(s.n), atol=1e-12)
+
+
+def test_adjoint_matches_central_differences():
+    pins.check_adjoint_finite_differences()
+
+
+def test_adjoint_closed_form_and_hellmann_feynman():
+    pins.check_adjoint_closed_form()
