@@ -145,6 +145,17 @@ typedef struct {
                                               launches only: refinement products of persistent runs) */
 } gsp2_timing;
 
+/* Outcome of one backward pass (filled when info != NULL). */
+typedef struct {
+    int32_t status;            /* gsp2_status of the pass */
+    int32_t n_alpha;           /* products differentiated */
+    int32_t checkpoint_every;  /* products per checkpoint segment */
+    int32_t row_min, row_max;  /* rows of H attaining eps_min and eps_max */
+    double eps_min, eps_max;
+    double d_eps_min, d_eps_max;   /* dL/d eps_min, dL/d eps_max */
+    int64_t workspace_bytes;   /* temporary device memory the pass used */
+} gsp2_backward_info;
+
 /* Human-readable name of a status code (static string). */
 const char *gsp2_status_string(gsp2_status s);
 
@@ -230,6 +241,34 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ,
  * measured with HIP events on the plan's stream.  Errors: GSP2_E_INVALID
  * when the last run was not timed. */
 gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out);
+
+/*
+ * Reverse mode of gsp2_density for a fixed branch sequence (the sequence of a
+ * forward run, from gsp2_run_info.alpha, replayed), with FP32 products:
+ *   the seed of part k is dL/dP on its core columns, symmetrised (every
+ *   iterate is symmetric; only symmetric perturbations of H are considered);
+ *   for each product in reverse, with X_t recomputed from checkpoints taken
+ *   every ceil(sqrt(n_alpha)) products: G <- GX + XG after X' = X^2, or
+ *   G <- 2G - (GX + XG) after X' = 2X - X^2 (eq. (2));
+ *   dL/dH_sub = -G_0 / (eps_max - eps_min) for every part (eq. (1)), summed
+ *   over parts into H's stored entries, plus dL/d eps_max = (tr G_0 -
+ *   <G_0, X_0>)/D and dL/d eps_min = <G_0, X_0>/D through the Gershgorin
+ *   rows that attain the bounds (lowest row on ties).
+ * The result is the gradient under symmetric perturbations of H, split evenly
+ * between H_uv and H_vu.  FP64 atomics accumulate it, so the summation order
+ * (and the last bits) may vary between runs.
+ *
+ *  H          device CSR, the H of the forward run.
+ *  alpha_seq  host, n_alpha branches (+1 / -1), 0 <= n_alpha <= GSP2_MAX_ITER.
+ *  dLdP_val   device, nnz_P floats in the order of gsp2_plan_pattern.
+ *  dLdH_val   device, H.nnz doubles (out), caller-owned.
+ *  info       nullable.
+ * Allocates (ceil(n/k) + k + 1) arena-sized FP32 buffers for the pass
+ * (k = ceil(sqrt(n_alpha))) and frees them before returning; waits for the result.
+ * Errors: GSP2_E_INVALID (arguments, non-finite H), GSP2_E_OOM, GSP2_E_HIP.
+ */
+gsp2_status gsp2_backward(gsp2_plan plan, const gsp2_csr *H, const int8_t *alpha_seq, int32_t n_alpha,
+                          const float *dLdP_val, double *dLdH_val, gsp2_backward_info *info);
 
 /* Wait for the last gsp2_density on this plan and report it. */
 gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info);

@@ -439,6 +439,16 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         auto *d_chunks = plan->alloc<RowChunk>(plan->chunks.size(), "row chunks");
         auto *d_idx = plan->alloc<int32_t>(plan->sub_idx.size(), "index arena");
         auto *d_perm = plan->alloc<int32_t>(plan->perm.size(), "perm arena");
+        auto *d_invperm = plan->alloc<int32_t>(plan->perm.size(), "inverse perm arena");
+        {
+            std::vector<int32_t> inv(plan->perm.size());
+            for (int32_t k = 0; k < n_parts; ++k) {
+                const int64_t b = plan->sub_ptr[k];
+                for (int32_t t = 0; t < plan->desc[k].s; ++t) inv[b + plan->perm[b + t]] = t;
+            }
+            upload(d_invperm, inv, s, "upload inverse perm");
+            check_hip(hipStreamSynchronize(s), "upload inverse perm");
+        }
         auto *d_colptr = plan->alloc<int64_t>(n + 1, "col_ptr");
         auto *d_colpart = plan->alloc<int32_t>(n, "col_part");
         auto *d_collocal = plan->alloc<int32_t>(n, "col_local");
@@ -452,7 +462,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             dp.persist_timeout = (long long)std::max(rate_khz, 1000) * 1000LL * 20;   // 20 s
         }
         dp.x0_partials = plan->alloc<double>(plan->chunks.size(), "x0 partials");
-        dp.gersh_partials = plan->alloc<double>(3 * (size_t)dp.gersh_blocks, "gershgorin partials");
+        dp.gersh_partials = plan->alloc<double>(5 * (size_t)dp.gersh_blocks, "gershgorin partials");
         dp.state = plan->alloc<RunState>(1, "run state");
         upload(d_parts, plan->desc, s, "upload parts");
         upload(d_tiles, plan->tiles, s, "upload tiles");
@@ -468,6 +478,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         dp.chunks = d_chunks;
         dp.idx = d_idx;
         dp.perm = d_perm;
+        dp.invperm = d_invperm;
         dp.col_ptr = d_colptr;
         dp.col_part = d_colpart;
         dp.col_local = d_collocal;
@@ -730,6 +741,80 @@ gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out) {
                       "elapsed");
         }
     });
+}
+
+gsp2_status gsp2_backward(gsp2_plan plan, const gsp2_csr *H, const int8_t *alpha_seq, int32_t n_alpha,
+                          const float *dLdP_val, double *dLdH_val, gsp2_backward_info *info) {
+    std::vector<void *> temps;
+    auto release = [&] {
+        for (void *p : temps) (void)hipFree(p);
+        temps.clear();
+    };
+    gsp2_status st = guarded([&] {
+        if (!plan) fail(GSP2_E_INVALID, "null plan");
+        if (!H || H->n != plan->n) fail(GSP2_E_INVALID, "H missing or of another size");
+        if (H->nnz < 0 || !H->row_ptr || (H->nnz > 0 && (!H->col || !H->val)))
+            fail(GSP2_E_INVALID, "bad H arrays");
+        if (H->dtype != GSP2_F32 && H->dtype != GSP2_F64) fail(GSP2_E_INVALID, "bad H.dtype");
+        if (n_alpha < 0 || n_alpha > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_alpha out of range");
+        if (n_alpha > 0 && !alpha_seq) fail(GSP2_E_INVALID, "null alpha_seq");
+        if (!dLdP_val || !dLdH_val) fail(GSP2_E_INVALID, "null gradient array");
+        for (int i = 0; i < n_alpha; ++i)
+            if (alpha_seq[i] != 1 && alpha_seq[i] != -1) fail(GSP2_E_INVALID, "alpha must be +1 or -1");
+        const int n = n_alpha;
+        int k = 1;
+        while (k * k < n) ++k;
+        const int nseg = n > 0 ? (n + k - 1) / k : 1;
+        int64_t bytes = 0;
+        BackwardBuffers bb{};
+        bb.seg = k;
+        auto arena = [&](const char *what) {
+            float *p = dev_alloc<float>(plan->arena_floats, what, bytes);
+            temps.push_back(p);
+            return p;
+        };
+        for (int i = 0; i < nseg; ++i) bb.ckpt[i] = arena("backward checkpoint");
+        for (int i = 0; i + 1 < k && i + 1 < n; ++i) bb.slot[i] = arena("backward segment iterate");
+        bb.g[0] = arena("backward cotangent");
+        bb.g[1] = arena("backward cotangent");
+        bb.eps_partials = dev_alloc<double>(2 * (size_t)plan->dp.n_chunks, "backward partials", bytes);
+        temps.push_back(bb.eps_partials);
+        bb.d_eps = dev_alloc<double>(2, "backward bound cotangents", bytes);
+        temps.push_back(bb.d_eps);
+        RunParams rp{};
+        rp.n_occ = 0.0;
+        rp.trace_tol = 1e300;
+        rp.stop_floor = 1.0;
+        rp.n_steps = n;
+        rp.mode = GSP2_ALPHA_REPLAY;
+        rp.precision = GSP2_PREC_FP32;
+        for (int i = 0; i < n; ++i) rp.alpha_seq[i] = alpha_seq[i];
+        check_hip(launch_backward(plan->dp, *H, rp, alpha_seq, n, dLdP_val, dLdH_val, bb, plan->stream),
+                  "launch backward");
+        double d_eps[2] = {0.0, 0.0};
+        check_hip(hipMemcpyAsync(plan->h_state, plan->dp.state, sizeof(RunState), hipMemcpyDeviceToHost,
+                                 plan->stream), "copy run state");
+        check_hip(hipMemcpyAsync(d_eps, bb.d_eps, sizeof d_eps, hipMemcpyDeviceToHost, plan->stream), "copy d_eps");
+        check_hip(hipStreamSynchronize(plan->stream), "backward");
+        const RunState &r = *plan->h_state;
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->status = r.status == GSP2_E_INVALID ? GSP2_E_INVALID : GSP2_OK;
+            info->n_alpha = n;
+            info->checkpoint_every = k;
+            info->row_min = r.row_min;
+            info->row_max = r.row_max;
+            info->eps_min = r.eps_min;
+            info->eps_max = r.eps_max;
+            info->d_eps_min = d_eps[0];
+            info->d_eps_max = d_eps[1];
+            info->workspace_bytes = bytes;
+        }
+        if (r.status == GSP2_E_INVALID) fail(GSP2_E_INVALID, "H rejected: Gershgorin bounds not finite or empty");
+    });
+    if (plan && plan->stream) (void)hipStreamSynchronize(plan->stream);
+    release();
+    return st;
 }
 
 void gsp2_plan_destroy(gsp2_plan plan) { delete plan; }

@@ -66,6 +66,7 @@ struct RunState {
     int32_t main_status;        // status of the main phase, reported at the end
     int32_t n_main;             // products formed in the main phase
     int32_t precision;
+    int32_t row_min, row_max;   // rows attaining eps_min and eps_max (lowest index on ties)
     int8_t alpha_seq[GSP2_MAX_ITER];
     int8_t alpha_hist[GSP2_MAX_ITER];
     double traces[GSP2_MAX_ITER + 1];
@@ -111,6 +112,7 @@ struct DevicePlan {
     const RowChunk *chunks;
     const int32_t *idx;         // index arena (local order)
     const int32_t *perm;        // per part: sorted position -> local index
+    const int32_t *invperm;     // per part: local index -> sorted position
     const int64_t *col_ptr;     // CSC column pointers of P, n+1
     const int32_t *col_part;    // part of every column
     const int32_t *col_local;   // local index of every column in its part
@@ -169,12 +171,25 @@ struct Recorder {
     }
 };
 
+// Work buffers of one backward pass (all arena-sized FP32 except where noted).
+struct BackwardBuffers {
+    int seg;                    // products per checkpoint segment
+    float *ckpt[GSP2_MAX_ITER + 1];   // X_{seg * k}
+    float *slot[GSP2_MAX_ITER];       // iterates recomputed inside one segment
+    float *g[2];                // cotangent ping-pong
+    double *eps_partials;       // n_chunks x 2
+    double *d_eps;              // 2: dL/d eps_min, dL/d eps_max
+};
+
 // Launchers (kernels.hip).  The threshold launchers enqueue on `stream`.
 hipError_t launch_threshold_count(const gsp2_csr &P, double tau, int32_t *counts, hipStream_t s);
 hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *out_ptr,
                                  int32_t *out_col, hipStream_t s);
 hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp,
                           float *P_val, Recorder &rec, const RunEvents *ev);
+// Reverse pass for a known branch sequence: dL/dH on H's stored entries.
+hipError_t launch_backward(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, const int8_t *alphas,
+                           int n, const float *dLdP, double *dLdH, const BackwardBuffers &bb, hipStream_t s);
 // Workgroups of the persistent product kernel that the device keeps resident.
 hipError_t persistent_grid(int precision, int *grid);
 

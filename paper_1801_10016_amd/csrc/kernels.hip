@@ -95,15 +95,27 @@ __global__ __launch_bounds__(kBlock) void k_threshold_fill(const int64_t *__rest
 // ---------------------------------------------------------------------------
 // a4: Gershgorin bounds.  One wave per row, FP64; per-block min/max partials.
 // ---------------------------------------------------------------------------
+// Partials per block: lo, hi, non-finite flag, row of lo, row of hi (ties
+// resolved to the lowest row, so the bounds' derivatives are well defined).
+constexpr int kGershStride = 5;
+
+__device__ __forceinline__ void keep_lo(double &lo, double &row, double l2, double r2) {
+    if (l2 < lo || (l2 == lo && r2 < row)) { lo = l2; row = r2; }
+}
+__device__ __forceinline__ void keep_hi(double &hi, double &row, double h2, double r2) {
+    if (h2 > hi || (h2 == hi && r2 < row)) { hi = h2; row = r2; }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gershgorin(const int64_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ col,
                                                        const T *__restrict__ val, int32_t n,
                                                        double *__restrict__ partials) {
-    __shared__ double lo_s[kBlock / kWave], hi_s[kBlock / kWave], bad_s[kBlock / kWave];
+    __shared__ double s_lo[kBlock / kWave], s_hi[kBlock / kWave], s_bad[kBlock / kWave];
+    __shared__ double s_rlo[kBlock / kWave], s_rhi[kBlock / kWave];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = threadIdx.x / kWave;
-    double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+    double lo = INFINITY, hi = -INFINITY, bad = 0.0, rlo = 1e300, rhi = 1e300;
     const int64_t stride = (int64_t)gridDim.x * (kBlock / kWave);
     for (int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + w; row < n; row += stride) {
         const int64_t b = row_ptr[row], e = row_ptr[row + 1];
@@ -116,20 +128,20 @@ __global__ __launch_bounds__(kBlock) void k_gershgorin(const int64_t *__restrict
         rad = wave_sum(rad);
         d = wave_sum(d);
         nf = wave_sum(nf);
-        lo = fmin(lo, d - rad);
-        hi = fmax(hi, d + rad);
+        keep_lo(lo, rlo, d - rad, (double)row);
+        keep_hi(hi, rhi, d + rad, (double)row);
         if (nf > 0.0) bad = 1.0;
     }
-    if (lane == 0) { lo_s[w] = lo; hi_s[w] = hi; bad_s[w] = bad; }
+    if (lane == 0) { s_lo[w] = lo; s_hi[w] = hi; s_bad[w] = bad; s_rlo[w] = rlo; s_rhi[w] = rhi; }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int i = 1; i < kBlock / kWave; ++i) {
-            lo = fmin(lo, lo_s[i]); hi = fmax(hi, hi_s[i]); bad = fmax(bad, bad_s[i]);
+            keep_lo(lo, rlo, s_lo[i], s_rlo[i]);
+            keep_hi(hi, rhi, s_hi[i], s_rhi[i]);
+            bad = fmax(bad, s_bad[i]);
         }
-        lo = fmin(lo, lo_s[0]); hi = fmax(hi, hi_s[0]); bad = fmax(bad, bad_s[0]);
-        partials[3 * blockIdx.x + 0] = lo;
-        partials[3 * blockIdx.x + 1] = hi;
-        partials[3 * blockIdx.x + 2] = bad;
+        double *out = partials + kGershStride * blockIdx.x;
+        out[0] = lo; out[1] = hi; out[2] = bad; out[3] = rlo; out[4] = rhi;
     }
 }
 
@@ -137,12 +149,15 @@ __global__ __launch_bounds__(kBlock) void k_gershgorin(const int64_t *__restrict
 __global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ partials, int nblk,
                                                      RunParams rp, RunState *__restrict__ st) {
     if (threadIdx.x != 0) return;
-    double lo = INFINITY, hi = -INFINITY, bad = 0.0;
+    double lo = INFINITY, hi = -INFINITY, bad = 0.0, rlo = 1e300, rhi = 1e300;
     for (int i = 0; i < nblk; ++i) {
-        lo = fmin(lo, partials[3 * i]);
-        hi = fmax(hi, partials[3 * i + 1]);
-        bad = fmax(bad, partials[3 * i + 2]);
+        const double *p = partials + kGershStride * i;
+        keep_lo(lo, rlo, p[0], p[3]);
+        keep_hi(hi, rhi, p[1], p[4]);
+        bad = fmax(bad, p[2]);
     }
+    st->row_min = rlo < 1e300 ? (int)rlo : -1;
+    st->row_max = rhi < 1e300 ? (int)rhi : -1;
     st->n_occ = rp.n_occ;
     st->trace_tol = rp.trace_tol;
     st->stop_floor = rp.stop_floor;
@@ -759,6 +774,269 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const PartDesc *__restrict__
     for (int t = lane; t < pd.s; t += kWave) out[t] = Xr[perm[t]];
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint of the recursion (reverse mode, FP32 products, FP64 reductions).
+//
+// For a fixed branch sequence, the cotangent G of X_{t+1} (kept symmetric:
+// the seed is symmetrised and the step preserves symmetry) maps to the
+// cotangent of X_t as GX + XG (alpha = -1) or 2G - (GX + XG) (alpha = +1).
+// With G and X symmetric, tile (I,J) of GX + XG is
+//     sum_k G[I,k] X[J,k] + X[I,k] G[J,k],
+// two row-panel products accumulated into one tile: the forward kernel's
+// data flow with the K loop run twice over different panel pairs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void adj_tile(const TileDesc td, const PartDesc pd, float alpha,
+                                         const float *__restrict__ Gin, float *__restrict__ Gout,
+                                         const float *__restrict__ X, uint4 *__restrict__ lds_base) {
+    auto lds = [&](int b, int ab) { return lds_base + (b * 2 + ab) * kTile * kLdsRow; };
+    const float *Gi = Gin + pd.x_off;
+    float *Go = Gout + pd.x_off;
+    const float *Xp = X + pd.x_off;
+    const int ld = pd.s_pad;
+    const int I0 = td.ti * kTile, J0 = td.tj * kTile;
+    const bool diag = td.ti == td.tj;
+    const int tid = threadIdx.x;
+    const int lr = tid >> 3, lw = tid & 7;
+    const char *A1 = reinterpret_cast<const char *>(Gi + (int64_t)(I0 + lr) * ld) + lw * 16;
+    const char *B1 = reinterpret_cast<const char *>(Xp + (int64_t)(J0 + lr) * ld) + lw * 16;
+    const char *A2 = reinterpret_cast<const char *>(Xp + (int64_t)(I0 + lr) * ld) + lw * 16;
+    const char *B2 = reinterpret_cast<const char *>(Gi + (int64_t)(J0 + lr) * ld) + lw * 16;
+    const int64_t pass_bytes = (int64_t)32 * ld * sizeof(float);
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int l32 = lane & 31, kh = lane >> 5;
+
+    v16f acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+
+    const int nk = ld / OpFmt<float>::kK;
+    const int nc = 2 * nk;
+    uint4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
+    auto load = [&](int c) {
+        const char *Ag = c < nk ? A1 : A2;
+        const char *Bg = c < nk ? B1 : B2;
+        const int64_t kb = (int64_t)(c < nk ? c : c - nk) * 128;
+        pa0 = *reinterpret_cast<const uint4 *>(Ag + kb);
+        pa1 = *reinterpret_cast<const uint4 *>(Ag + pass_bytes + kb);
+        pa2 = *reinterpret_cast<const uint4 *>(Ag + 2 * pass_bytes + kb);
+        pa3 = *reinterpret_cast<const uint4 *>(Ag + 3 * pass_bytes + kb);
+        pb0 = *reinterpret_cast<const uint4 *>(Bg + kb);
+        pb1 = *reinterpret_cast<const uint4 *>(Bg + pass_bytes + kb);
+        pb2 = *reinterpret_cast<const uint4 *>(Bg + 2 * pass_bytes + kb);
+        pb3 = *reinterpret_cast<const uint4 *>(Bg + 3 * pass_bytes + kb);
+    };
+    auto store = [&](int b) {
+        uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;
+        uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;
+        As_[0] = pa0; As_[32 * kLdsRow] = pa1; As_[64 * kLdsRow] = pa2; As_[96 * kLdsRow] = pa3;
+        Bs_[0] = pb0; Bs_[32 * kLdsRow] = pb1; Bs_[64 * kLdsRow] = pb2; Bs_[96 * kLdsRow] = pb3;
+    };
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int kc = 0; kc < nc; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nc) load(kc + 1);
+        const uint4 *Asb = lds(buf, 0);
+        const uint4 *Bsb = lds(buf, 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int w = kh * 4 + q;
+            uint4 fa[2], fb[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
+                fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], float{});
+        }
+        if (kc + 1 < nc) store(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+#pragma unroll
+        for (int nn = 0; nn < 2; ++nn) {
+            const int cg = J0 + wc * 64 + nn * 32 + l32;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int rg0 = I0 + wr * 64 + m * 32 + g * 8 + kh * 4;
+                float gn[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rg = rg0 + e;
+                    const float sv = acc[m][nn][4 * g + e];
+                    const float go = Gi[(int64_t)rg * ld + cg];
+                    const float v = alpha > 0.0f ? (2.0f * go - sv) : sv;
+                    gn[e] = v;
+                    Go[(int64_t)rg * ld + cg] = v;
+                }
+                if (!diag) *reinterpret_cast<float4 *>(Go + (int64_t)cg * ld + rg0) = make_float4(gn[0], gn[1], gn[2], gn[3]);
+            }
+        }
+    }
+}
+
+// One forward product with the buffers and branch given explicitly (the
+// backward pass replays a known sequence).
+__global__ __launch_bounds__(kBlock, 2) void k_sp2_fixed(const TileDesc *__restrict__ tiles,
+                                                         const PartDesc *__restrict__ parts,
+                                                         float *__restrict__ X_in, float *__restrict__ X_out,
+                                                         float alpha, double *__restrict__ diag_partials) {
+    __shared__ uint4 lds[kLdsWords];
+    const TileDesc td = tiles[blockIdx.x];
+    if (td.part < 0) return;
+    sp2_tile<float>(td, parts[td.part], 0, alpha, X_in, X_out, nullptr, nullptr, diag_partials, lds);
+}
+
+__global__ __launch_bounds__(kBlock, 2) void k_adj_step(const TileDesc *__restrict__ tiles,
+                                                        const PartDesc *__restrict__ parts,
+                                                        const float *__restrict__ G_in, float *__restrict__ G_out,
+                                                        const float *__restrict__ X, float alpha) {
+    __shared__ uint4 lds[kLdsWords];
+    const TileDesc td = tiles[blockIdx.x];
+    if (td.part < 0) return;
+    adj_tile(td, parts[td.part], alpha, G_in, G_out, X, lds);
+}
+
+// Seed: part k's cotangent is dL/dP on its core columns (rows in local
+// order), zero elsewhere, symmetrised.  One workgroup per row chunk.
+__global__ __launch_bounds__(kBlock) void k_adj_seed(const PartDesc *__restrict__ parts,
+                                                     const RowChunk *__restrict__ chunks,
+                                                     const int32_t *__restrict__ idx_arena,
+                                                     const int32_t *__restrict__ invperm_arena,
+                                                     const int64_t *__restrict__ col_ptr,
+                                                     const float *__restrict__ dLdP, float *__restrict__ G) {
+    const RowChunk ch = chunks[blockIdx.x];
+    const PartDesc pd = parts[ch.part];
+    const int32_t *idx = idx_arena + pd.idx_off;
+    const int32_t *inv = invperm_arena + pd.perm_off;
+    const int ld = pd.s_pad;
+    float *Gp = G + pd.x_off;
+    for (int r = ch.r0; r < ch.r1; ++r) {
+        for (int b = threadIdx.x; b < ld; b += kBlock) {
+            float g1 = 0.0f, g2 = 0.0f;
+            if (r < pd.s && b < pd.c) g1 = dLdP[col_ptr[idx[b]] + inv[r]];     // column b, row r
+            if (b < pd.s && r < pd.c) g2 = dLdP[col_ptr[idx[r]] + inv[b]];     // column r, row b
+            Gp[(int64_t)r * ld + b] = 0.5f * (g1 + g2);
+        }
+    }
+}
+
+// dL/dH_sub = -G0 / (eps_max - eps_min), accumulated over parts into H's
+// stored entries (FP64 atomics: a value's summation order may vary).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_dh(const int64_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col,
+                                                   const PartDesc *__restrict__ parts,
+                                                   const RowChunk *__restrict__ chunks,
+                                                   const int32_t *__restrict__ idx_arena,
+                                                   const float *__restrict__ G0, const RunState *__restrict__ st,
+                                                   double *__restrict__ dLdH) {
+    __shared__ int32_t idx_s[kGatherLdsIdx];
+    if (st->done) return;
+    const RowChunk ch = chunks[blockIdx.x];
+    const PartDesc pd = parts[ch.part];
+    const int32_t *idx_g = idx_arena + pd.idx_off;
+    const bool in_lds = pd.s <= kGatherLdsIdx;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < pd.s; i += kBlock) idx_s[i] = idx_g[i];
+        __syncthreads();
+    }
+    const int32_t *idx = in_lds ? idx_s : idx_g;
+    const double inv = 1.0 / (st->eps_max - st->eps_min);
+    const float *Gp = G0 + pd.x_off;
+    const int ld = pd.s_pad;
+    for (int r = ch.r0; r < min(ch.r1, pd.s); ++r) {
+        const int64_t g = idx[r];
+        for (int64_t e = row_ptr[g] + threadIdx.x; e < row_ptr[g + 1]; e += kBlock) {
+            const int32_t cg = col[e];
+            int q = find_sorted(idx, pd.c, cg);
+            if (q < 0) {
+                q = find_sorted(idx + pd.c, pd.s - pd.c, cg);
+                if (q >= 0) q += pd.c;
+            }
+            if (q >= 0) atomicAdd(dLdH + e, -static_cast<double>(Gp[(int64_t)r * ld + q]) * inv);
+        }
+    }
+}
+
+// Per row chunk: sum of G0 .* X0 and of G0's diagonal (for the bound terms).
+__global__ __launch_bounds__(kBlock) void k_adj_eps_partials(const PartDesc *__restrict__ parts,
+                                                             const RowChunk *__restrict__ chunks,
+                                                             const float *__restrict__ G0,
+                                                             const float *__restrict__ X0,
+                                                             double *__restrict__ out) {
+    const RowChunk ch = chunks[blockIdx.x];
+    const PartDesc pd = parts[ch.part];
+    const int ld = pd.s_pad;
+    double gx = 0.0, tr = 0.0;
+    for (int r = ch.r0; r < min(ch.r1, pd.s); ++r) {
+        const float *gr = G0 + pd.x_off + (int64_t)r * ld;
+        const float *xr = X0 + pd.x_off + (int64_t)r * ld;
+        for (int b = threadIdx.x; b < pd.s; b += kBlock) gx += (double)gr[b] * (double)xr[b];
+        if (threadIdx.x == 0) tr += (double)gr[r];
+    }
+    block_sum2(gx, tr);
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = gx;
+        out[2 * blockIdx.x + 1] = tr;
+    }
+}
+
+__device__ __forceinline__ double sgn(double v) { return (v > 0.0) - (v < 0.0); }
+
+// The Gershgorin bounds' share: dL/d eps_max = (tr G0 - <G0, X0>) / D falls
+// on row i of eps_max = H_ii + sum |H_ij|, dL/d eps_min = <G0, X0> / D on row
+// j of eps_min = H_jj - sum |H_jl|; off-diagonal shares are split evenly
+// between H_uv and H_vu.  One workgroup.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_adj_eps_apply(const double *__restrict__ partials, int n_chunks,
+                                                          const RunState *__restrict__ st,
+                                                          const int64_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const T *__restrict__ val, double *__restrict__ dLdH,
+                                                          double *__restrict__ d_eps) {
+    if (st->done) return;
+    double gx = 0.0, tr = 0.0;
+    for (int i = threadIdx.x; i < n_chunks; i += kBlock) {
+        gx += partials[2 * i];
+        tr += partials[2 * i + 1];
+    }
+    block_sum2(gx, tr);
+    if (threadIdx.x != 0) return;
+    const double D = st->eps_max - st->eps_min;
+    const double g_max = (tr - gx) / D, g_min = gx / D;
+    d_eps[0] = g_min;
+    d_eps[1] = g_max;
+    const int rows[2] = {st->row_max, st->row_min};
+    const double gs[2] = {g_max, -g_min};
+    for (int q = 0; q < 2; ++q) {
+        const int row = rows[q];
+        if (row < 0) continue;
+        const double g = q == 0 ? g_max : g_min;
+        for (int64_t e = row_ptr[row]; e < row_ptr[row + 1]; ++e) {
+            const int32_t c = col[e];
+            if (c == row) {
+                dLdH[e] += g;
+                continue;
+            }
+            const double w = gs[q] * sgn(as_double(val[e]));
+            dLdH[e] += 0.5 * w;
+            for (int64_t f = row_ptr[c]; f < row_ptr[c + 1]; ++f)
+                if (col[f] == row) { dLdH[f] += 0.5 * w; break; }
+        }
+    }
+}
+
 // Hand a kernel and its arguments (converted to the kernel's parameter types)
 // to the recorder; the recorder copies them at launch or node creation.
 template <typename... KArgs, std::size_t... I, typename... Args>
@@ -839,7 +1117,61 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     return rec.err;
 }
 
+template <typename T>
+hipError_t backward_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, const int8_t *alphas,
+                          int n, const float *dLdP, double *dLdH, const BackwardBuffers &bb, hipStream_t s) {
+    Recorder rec;
+    rec.stream = s;
+    const T *hv = static_cast<const T *>(H.val);
+    const dim3 blk(kBlock), grid(dp.n_tiles), chunks(dp.n_chunks);
+    record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.gersh_partials);
+    record(rec, k_run_init, dim3(1), blk, dp.gersh_partials, dp.gersh_blocks, rp, dp.state);
+    record(rec, k_gather_x0<T>, chunks, blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx, bb.ckpt[0],
+           (uint16_t *)nullptr, dp.state, dp.x0_partials);
+    const int k = bb.seg;
+    const int nseg = n > 0 ? (n + k - 1) / k : 1;
+    // forward replay, keeping X_{seg k}
+    float *cur = bb.ckpt[0];
+    for (int t = 0; t + 1 <= (nseg - 1) * k; ++t) {
+        float *out = ((t + 1) % k == 0) ? bb.ckpt[(t + 1) / k] : (cur == dp.buf[0] ? dp.buf[1] : dp.buf[0]);
+        record(rec, k_sp2_fixed, grid, blk, dp.tiles, dp.parts, cur, out, (float)alphas[t], dp.diag_partials);
+        cur = out;
+    }
+    // seed and reverse sweep, segment by segment from the last
+    float *g_cur = bb.g[0], *g_oth = bb.g[1];
+    record(rec, k_adj_seed, chunks, blk, dp.parts, dp.chunks, dp.idx, dp.invperm, dp.col_ptr, dLdP, g_cur);
+    for (int seg = nseg - 1; seg >= 0 && n > 0; --seg) {
+        const int t0 = seg * k, t1 = (t0 + k < n) ? t0 + k : n;
+        for (int i = 1; i < t1 - t0; ++i) {
+            float *in = (i == 1) ? bb.ckpt[seg] : bb.slot[i - 2];
+            record(rec, k_sp2_fixed, grid, blk, dp.tiles, dp.parts, in, bb.slot[i - 1], (float)alphas[t0 + i - 1],
+                   dp.diag_partials);
+        }
+        for (int t = t1 - 1; t >= t0; --t) {
+            const float *X = (t == t0) ? bb.ckpt[seg] : bb.slot[t - t0 - 1];
+            record(rec, k_adj_step, grid, blk, dp.tiles, dp.parts, (const float *)g_cur, g_oth, X, (float)alphas[t]);
+            float *tmp = g_cur; g_cur = g_oth; g_oth = tmp;
+        }
+    }
+    if (rec.err != hipSuccess) return rec.err;
+    hipError_t e = hipMemsetAsync(dLdH, 0, sizeof(double) * (size_t)H.nnz, s);
+    if (e != hipSuccess) return e;
+    record(rec, k_adj_dh<T>, chunks, blk, H.row_ptr, H.col, dp.parts, dp.chunks, dp.idx, (const float *)g_cur,
+           (const RunState *)dp.state, dLdH);
+    record(rec, k_adj_eps_partials, chunks, blk, dp.parts, dp.chunks, (const float *)g_cur,
+           (const float *)bb.ckpt[0], bb.eps_partials);
+    record(rec, k_adj_eps_apply<T>, dim3(1), blk, (const double *)bb.eps_partials, dp.n_chunks,
+           (const RunState *)dp.state, H.row_ptr, H.col, hv, dLdH, bb.d_eps);
+    return rec.err;
+}
+
 }  // namespace
+
+hipError_t launch_backward(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, const int8_t *alphas,
+                           int n, const float *dLdP, double *dLdH, const BackwardBuffers &bb, hipStream_t s) {
+    if (H.dtype == GSP2_F64) return backward_typed<double>(dp, H, rp, alphas, n, dLdP, dLdH, bb, s);
+    return backward_typed<float>(dp, H, rp, alphas, n, dLdP, dLdH, bb, s);
+}
 
 hipError_t persistent_grid(int precision, int *grid) {
     int dev = 0, cus = 0, per_cu = 0;

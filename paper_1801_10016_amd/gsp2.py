@@ -64,6 +64,13 @@ class gsp2_timing(C.Structure):
                 ("product_ms", C.c_float * GSP2_MAX_ITER)]
 
 
+class gsp2_backward_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_alpha", C.c_int32), ("checkpoint_every", C.c_int32),
+                ("row_min", C.c_int32), ("row_max", C.c_int32), ("eps_min", C.c_double),
+                ("eps_max", C.c_double), ("d_eps_min", C.c_double), ("d_eps_max", C.c_double),
+                ("workspace_bytes", C.c_int64)]
+
+
 _PLAN = C.c_void_p
 
 # name -> (restype, argtypes), exactly the functions declared in gsp2.h
@@ -82,6 +89,8 @@ SIGNATURES = {
     "gsp2_run_status": (C.c_int, [_PLAN, C.POINTER(gsp2_run_info)]),
     "gsp2_run_timing": (C.c_int, [_PLAN, C.POINTER(gsp2_timing)]),
     "gsp2_plan_destroy": (None, [_PLAN]),
+    "gsp2_backward": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.POINTER(C.c_int8), C.c_int32, C.c_void_p,
+                                C.c_void_p, C.POINTER(gsp2_backward_info)]),
     "gsp2_core_halo_host": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -312,6 +321,27 @@ def gsp2_run_timing(plan: Plan) -> dict:
     return {"n_products": t.n_products, "setup_ms": t.setup_ms, "sp2_ms": t.sp2_ms,
             "scatter_ms": t.scatter_ms, "total_ms": t.total_ms, "persistent_ms": t.persistent_ms,
             "product_ms": [float(x) for x in t.product_ms[:t.n_products]]}
+
+
+def gsp2_backward(plan: Plan, H: DeviceCSR, alpha_seq, dLdP_val, dLdH_val=None) -> tuple:
+    """dL/dH (torch float64 on the GPU, one value per stored entry of H) for a
+    forward run with branch sequence alpha_seq, given dL/dP_val.  Returns
+    (dLdH_val, info dict)."""
+    import torch
+    if dLdP_val.dtype != torch.float32 or not dLdP_val.is_cuda or not dLdP_val.is_contiguous():
+        raise ValueError("dLdP_val must be a contiguous float32 GPU tensor")
+    if dLdP_val.numel() < plan.nnz_P:
+        raise ValueError("dLdP_val is shorter than the plan's P")
+    if dLdH_val is None:
+        dLdH_val = torch.empty(H.nnz, dtype=torch.float64, device=dLdP_val.device)
+    if dLdH_val.dtype != torch.float64 or dLdH_val.numel() < H.nnz:
+        raise ValueError("dLdH_val must hold H.nnz float64 values")
+    seq = np.ascontiguousarray(alpha_seq, dtype=np.int8)
+    c = H.as_c()
+    info = gsp2_backward_info()
+    _check(load().gsp2_backward(plan.handle, C.byref(c), seq.ctypes.data_as(C.POINTER(C.c_int8)), int(seq.size),
+                                C.c_void_p(dLdP_val.data_ptr()), C.c_void_p(dLdH_val.data_ptr()), C.byref(info)))
+    return dLdH_val, {f: getattr(info, f) for f, _ in gsp2_backward_info._fields_}
 
 
 def gsp2_plan_destroy(plan: Plan):
