@@ -66,7 +66,10 @@ def test_backward_matches_oracle_adjoint(n_mol, seed, n_parts, tau):
           f"d_eps ({info['d_eps_min']:.4e},{info['d_eps_max']:.4e}) vs {ref.d_eps[0]:.4e},{ref.d_eps[1]:.4e}",
           flush=True)
     assert (info["row_min"], info["row_max"]) == ref.rows
-    assert np.allclose([info["d_eps_min"], info["d_eps_max"]], ref.d_eps, rtol=1e-3, atol=1e-6)
+    # once converged, P hardly depends on the bounds and both derivatives are at
+    # rounding level: compare them on the scale of the whole gradient
+    scale = 1e-5 * np.linalg.norm(ref.dH)
+    assert np.allclose([info["d_eps_min"], info["d_eps_max"]], ref.d_eps, rtol=1e-3, atol=scale)
     assert err <= TOL
 
 
