@@ -61,13 +61,19 @@ def parse():
     ap.add_argument("--save-state", help="write the thresholded graph and product count to this .npz")
     ap.add_argument("--load-state", help="reuse a graph and product count saved by --save-state "
                     "(skips the previous-P computation and the first, stop-finding run)")
-    ap.add_argument("--precision", choices=["fp32", "fp16", "bf16"], default="fp32",
-                    help="operand precision of the timed products")
+    ap.add_argument("--precision", choices=["fp32", "fp16", "bf16"], default=None,
+                    help="operand precision of the timed products (default: fp32, or fp16 for batch16)")
     ap.add_argument("--compare-precisions", default="fp16,bf16",
                     help="after the FP32 timing, also time these operand precisions (empty: none)")
     ap.add_argument("--compare-steps", type=int, default=3)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM counter calibration)")
+    ap.add_argument("--workload", choices=["water3500", "batch16"], default="water3500",
+                    help="water3500: one system (the default line); batch16: 16 independent systems of "
+                    "500-8,000 molecules, each one MD step on, in one batched plan")
+    ap.add_argument("--refine", type=int, default=None,
+                    help="FP32 refinement products after the stop (default: 0, or 2 for batch16)")
+    ap.add_argument("--no-alone", action="store_true", help="batch16: skip timing each system in a plan of its own")
     return ap.parse_args()
 
 
@@ -163,8 +169,133 @@ def cpu_baseline(system, part, n_parts, tau, n_products, sub_sizes, n_sample):
                        f"{dt:.1f} s, scaled by sum_k s_k^3 of the timed workload")}
 
 
+def syrk_flops(sizes) -> float:
+    """Flops of one symmetric product over parts of sizes s_k: s(s+1)/2 distinct
+    entries, 2 s flops each."""
+    s = np.asarray(sizes, dtype=np.float64)
+    return float(np.sum(s * s * (s + 1.0)))
+
+
+def bench_batch(args, g, torch):
+    """The uneven batch: every system's density matrix from one batched plan,
+    one launch per product carrying the tiles of all systems still iterating."""
+    from synth.batch import make_batch
+    precision, refine = args.precision, args.refine
+    t = time.perf_counter()
+    b = make_batch()
+    log(f"batch: {len(b.steps)} systems, N={b.H.shape[0]}, {b.n_parts} parts, inputs {time.perf_counter() - t:.1f} s")
+    stream = torch.cuda.Stream()
+    Hd = g.csr_to_device(b.H)
+    t = time.perf_counter()
+    with torch.cuda.stream(stream):
+        plan = g.gsp2_plan_create(g.csr_to_device(b.P_prev), b.tau, b.part, b.n_parts, stream=stream,
+                                  part_system=b.part_system)
+    plan_s = time.perf_counter() - t
+    torch.cuda.empty_cache()
+    info, _, sub_sizes = g.gsp2_plan_query(plan)
+    log(f"plan: s in [{info['min_s']}, {info['max_s']}], {info['n_tiles']} tiles per product, "
+        f"workspace {info['workspace_bytes'] / 2**30:.1f} GiB, {plan_s:.1f} s")
+    P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
+    sys_flops = [syrk_flops(sub_sizes[b.part_offs[i]:b.part_offs[i + 1]]) for i in range(len(b.steps))]
+    with torch.cuda.stream(stream):
+        first = g.gsp2_density(plan, Hd, b.n_occ, P_val, max_iter=args.max_iter, precision=precision, refine=refine)
+    n_main = [r["n_products"] - r["n_refine"] for r in first]
+    max_main = max(n_main)
+    log(f"first run: main products per system {n_main}")
+    kw = dict(max_iter=max_main, precision=precision, refine=refine)
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            runs = g.gsp2_density(plan, Hd, b.n_occ, P_val, timing=True, **kw)
+            assert all(r["status"] == 0 for r in runs), runs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        product_ms, totals = [], []
+        for i in range(args.steps):
+            g.gsp2_density(plan, Hd, b.n_occ, P_val, timing=True, want_info=False, **kw)
+            tm = g.gsp2_run_timing(plan)
+            product_ms.append(tm["product_ms"]); totals.append(tm["total_ms"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        runs = g.gsp2_run_status(plan)
+    assert all(r["status"] == 0 for r in runs), runs
+    ms_per_batch = wall * 1e3 / args.steps
+    # launch t of the main phase carries every system whose main phase formed more than t products
+    per_launch = np.median(np.asarray(product_ms), axis=0)
+    main_ms, main_flops = 0.0, 0.0
+    for t_ in range(max_main):
+        main_ms += float(per_launch[t_])
+        main_flops += sum(f for f, m in zip(sys_flops, n_main) if m > t_)
+    ref_ms = float(np.sum(per_launch[max_main:]))
+    ref_flops = refine * sum(sys_flops)
+    total_flops = main_flops + ref_flops
+    per_system = []
+    for i, (st, r) in enumerate(zip(b.steps, runs)):
+        # device time until the system's last product: setup excluded, launches it took part in
+        done = float(np.sum(per_launch[:n_main[i]])) + ref_ms
+        per_system.append({"n_mol": st.system.n_mol, "n_orbitals": st.system.n, "n_parts": st.n_parts,
+                           "n_products": r["n_products"], "n_refine": r["n_refine"],
+                           "product_kernels_ms_until_done": round(done, 3),
+                           "trace_minus_nocc": r["trace"] - st.system.n_occ})
+    alone_ms = None
+    if not args.no_alone:
+        alone_ms = []
+        for i, st in enumerate(b.steps):
+            Hs = g.csr_to_device(st.system.H)
+            with torch.cuda.stream(stream):
+                with g.gsp2_plan_create(g.csr_to_device(st.P_prev), b.tau, st.part, st.n_parts, stream=stream) as p1:
+                    Pv = torch.empty(p1.nnz_P, dtype=torch.float32, device="cuda")
+                    k1 = dict(kw, max_iter=n_main[i])
+                    g.gsp2_density(p1, Hs, st.system.n_occ, Pv, **k1)
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    for _ in range(args.compare_steps):
+                        g.gsp2_density(p1, Hs, st.system.n_occ, Pv, want_info=False, **k1)
+                    torch.cuda.synchronize()
+                    alone_ms.append((time.perf_counter() - t1) * 1e3 / args.compare_steps)
+            per_system[i]["alone_ms_per_P"] = round(alone_ms[-1], 3)
+            del Pv, Hs
+            torch.cuda.empty_cache()
+        log(f"each system in a plan of its own: {sum(alone_ms):.1f} ms in total, batch {ms_per_batch:.1f} ms")
+    peak_main = PEAK_MFMA_TFLOPS[precision]
+    main_tf = main_flops / (main_ms * 1e-3) / 1e12
+    out = {
+        "metric": "ms per batch of 16 density matrices (uneven systems, one plan) + aggregate TFLOP/s",
+        "value": round(ms_per_batch, 3), "unit": "ms/batch", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_batch, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": DTYPE[precision], "data": "synthetic",
+        "config": {
+            "workload": (f"{len(b.steps)} independent water systems of {min(s_.system.n_mol for s_ in b.steps)}-"
+                         f"{max(s_.system.n_mol for s_ in b.steps)} molecules ({b.H.shape[0]} orbitals, "
+                         f"{b.n_parts} parts), 0.05 A displacements, repartitioned, tau={b.tau:g}, "
+                         f"{precision.upper()} products + {refine} FP32 refinement products"),
+            "n_systems": len(b.steps), "n_orbitals": b.H.shape[0], "n_parts": b.n_parts, "tau": b.tau,
+            "s_min": info["min_s"], "s_max": info["max_s"], "tiles_per_product": info["n_tiles"],
+            "precision": precision, "refine": refine,
+        },
+        "aggregate_tflops": round(total_flops / (float(np.sum(per_launch)) * 1e-3) / 1e12, 2),
+        "aggregate_tflops_convention": "symmetric-product flops of every system in every launch it took part in "
+                                       "/ summed product-kernel time",
+        "roofline": {"bound": "mfma", "kernel": f"k_sp2_step<{precision}>", "achieved": round(main_tf, 2),
+                     "peak": peak_main, "unit": "TFLOP/s", "frac": round(main_tf / peak_main, 4), "traffic": None,
+                     "refine_kernel_tflops": round(ref_flops / (ref_ms * 1e-3) / 1e12, 2) if ref_ms > 0 else None},
+        "event_total_ms_median": round(statistics.median(totals), 3),
+        "main_launches": max_main, "main_launch_ms": round(main_ms, 3), "refine_launch_ms": round(ref_ms, 3),
+        "alone_total_ms": round(sum(alone_ms), 3) if alone_ms else None,
+        "per_system": per_system,
+        "plan_ms": round(plan_s * 1e3, 1),
+        "workspace_gib": round(info["workspace_bytes"] / 2**30, 2),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0
+
+
 def main():
     args = parse()
+    batch = args.workload == "batch16"
+    args.precision = args.precision or ("fp16" if batch else "fp32")
+    args.refine = (2 if batch else 0) if args.refine is None else args.refine
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
@@ -183,6 +314,8 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe_gib > 0:
         return copy_probe(torch, args.copy_probe_gib)
+    if args.workload == "batch16":
+        return bench_batch(args, g, torch)
     stream = torch.cuda.Stream()
     t = time.perf_counter()
     system = make_water(args.n_mol, seed=args.seed)

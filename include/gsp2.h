@@ -75,7 +75,11 @@ typedef struct gsp2_plan_s *gsp2_plan;   /* opaque, library-owned */
 /* Plan options.  Zero-initialised means defaults. */
 typedef struct {
     int32_t tile;              /* macro-tile edge of the SP2 product: 0 = automatic, or 128 */
-    int32_t reserved[7];
+    int32_t n_systems;         /* independent systems batched in the plan: 0 or 1 = one */
+    const int32_t *part_system;/* host, n_parts ids in [0, n_systems), every system used by at
+                                  least one part: the system of every part.  Ignored (may be
+                                  NULL) when n_systems <= 1. */
+    int32_t reserved[4];
 } gsp2_plan_options;
 
 /* Summary of a plan, filled by gsp2_plan_query. */
@@ -92,6 +96,8 @@ typedef struct {
     int32_t n_tiles;           /* product tiles per SP2 iteration (upper triangles) */
     int64_t workspace_bytes;   /* device memory held by the plan */
     double plan_ms;            /* host wall time of gsp2_plan_create */
+    int32_t n_systems;         /* independent systems in the plan (1 unless batched) */
+    int32_t pad_;
 } gsp2_plan_info;
 
 /* Options of one density-matrix computation.  Fill with
@@ -107,12 +113,18 @@ typedef struct {
     int32_t timing;            /* 1 = record HIP events around every phase and product
                                   (read with gsp2_run_timing); default 0 */
     int32_t precision;         /* gsp2_precision of the products, default GSP2_PREC_FP32 */
-    int32_t refine;            /* FP32 products appended after the stop (branch from the
-                                  trace rule), 0..8, default 0; max_iter + refine <= GSP2_MAX_ITER */
+    int32_t refine;            /* FP32 products appended after the stop, alternating X^2 and
+                                  2X - X^2, 0..8, default 0; max_iter + refine <= GSP2_MAX_ITER */
     int32_t persistent;        /* must be 0 (one launch per product, all in one HIP graph).
                                   1 would put all products before the stop in one persistent
                                   launch with a grid barrier per product; that path is switched
                                   off in this build and returns GSP2_E_UNSUPPORTED. */
+    /* Batched plans only (n_systems > 1); NULL otherwise. */
+    const double *n_occ_system;      /* host, n_systems: occupation of every system (required;
+                                        replaces the n_occ argument of gsp2_density) */
+    const int8_t *alpha_seq_system;  /* host, replay mode: n_systems rows of GSP2_MAX_ITER
+                                        branches, row-major; NULL = alpha_seq for every system */
+    const int32_t *n_alpha_system;   /* host, n_systems lengths of those rows (<= GSP2_MAX_ITER) */
 } gsp2_run_options;
 
 #define GSP2_MAX_ITER 100
@@ -181,7 +193,16 @@ gsp2_status gsp2_run_options_default(gsp2_run_options *opt);
  *  stream  hipStream_t to use (NULL = default stream).
  *  out     receives the plan; NULL on failure.
  * Blocks the calling thread until the graph has been built.
- * Errors: GSP2_E_INVALID (sizes, ids, empty part), GSP2_E_OOM, GSP2_E_HIP.
+ * Batched plans (opt->n_systems > 1) hold several independent systems, the
+ * paper's sub-problem batch taken across systems as well as parts: P_prev, H
+ * and P are the block-diagonal unions of the systems (a system's vertices
+ * need not be contiguous), opt->part_system names the system of every part,
+ * and every product launch carries the tiles of all systems still iterating.
+ * Each system keeps its own Gershgorin bounds, occupation, core trace, branch
+ * sequence, stop and status, so its P is what a plan of that system alone
+ * computes (bit for bit when its parts keep their relative order).
+ * Errors: GSP2_E_INVALID (sizes, ids, empty part or system, a graph edge
+ * between two systems), GSP2_E_OOM, GSP2_E_HIP.
  */
 gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *part,
                              int32_t n_parts, const gsp2_plan_options *opt, void *stream,
@@ -216,20 +237,30 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
  *   the supplied branches, then the trace check).  Tr is the sum over parts
  *   of the diagonal of each part's core rows.  P[idx_k, j] = X_k[:, j]
  *   for each core column j of part k; other entries are not stored.
+ *   In a batched plan every quantity above (bounds, n, n_occ, traces,
+ *   branches, stop) is per system; n is then the system's vertex count and
+ *   H must not couple two systems (such entries would only widen the
+ *   Gershgorin discs of their rows).
  * Arithmetic: products on the matrix cores with FP32 accumulation and FP32,
  * FP16 or BF16 operands (run->precision); the master iterate and the update
  * stay FP32; Gershgorin bounds, X0 and all traces are FP64.  With refine > 0,
  * that many FP32 products follow the stop (or the last replayed branch),
- * each with the trace rule, and the last one is returned.
+ * alternating X^2 and 2X - X^2 (each pair a purification sweep that drives
+ * every eigenvalue to the nearer of 0 and 1), and the last one is returned.
  *
  *  H       device CSR, n x n, symmetric; its pattern may change between calls.
- *  n_occ   number of occupied states N_el / 2, 0 <= n_occ <= n.
+ *  n_occ   number of occupied states N_el / 2, 0 <= n_occ <= n (ignored by
+ *          batched plans, which take run->n_occ_system).
  *  run     nullable (defaults).
  *  P_val   device, nnz_P floats in the order of gsp2_plan_pattern; caller-owned.
- *  info    nullable.  When given, the call waits for the result and returns
- *          the run's status; otherwise it returns after enqueueing.
+ *  info    nullable; otherwise n_systems structs, one per system of the plan.
+ *          When given, the call waits for the results and returns the first
+ *          failing system's status (GSP2_OK if none); otherwise it returns
+ *          after enqueueing.
  * All kernels of the run form one HIP graph, built on the first call and
- * replayed while H's arrays, P_val, n_occ and the options stay the same.
+ * replayed while H's arrays, P_val and the options other than the
+ * occupations and replayed branches stay the same (those two are uploaded
+ * to the device before each launch).
  * Errors: GSP2_E_INVALID (arguments, non-finite H, eps_max <= eps_min),
  * GSP2_E_NOT_CONVERGED, GSP2_E_WRONG_TRACE, GSP2_E_HIP.  On error the
  * contents of P_val are unspecified.
@@ -265,12 +296,13 @@ gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out);
  *  info       nullable.
  * Allocates (ceil(n/k) + k + 1) arena-sized FP32 buffers for the pass
  * (k = ceil(sqrt(n_alpha))) and frees them before returning; waits for the result.
- * Errors: GSP2_E_INVALID (arguments, non-finite H), GSP2_E_OOM, GSP2_E_HIP.
+ * Errors: GSP2_E_INVALID (arguments, non-finite H), GSP2_E_OOM, GSP2_E_HIP,
+ * GSP2_E_UNSUPPORTED (batched plans).
  */
 gsp2_status gsp2_backward(gsp2_plan plan, const gsp2_csr *H, const int8_t *alpha_seq, int32_t n_alpha,
                           const float *dLdP_val, double *dLdH_val, gsp2_backward_info *info);
 
-/* Wait for the last gsp2_density on this plan and report it. */
+/* Wait for the last gsp2_density on this plan and report it (info: n_systems structs). */
 gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info);
 
 /* Release the plan and its device memory (waits for its stream).  NULL is a no-op. */

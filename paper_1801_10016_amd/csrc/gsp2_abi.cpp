@@ -160,6 +160,12 @@ struct GraphKey {
 
 struct gsp2_plan_s {
     int32_t n = 0, n_parts = 0, tile = kTile;
+    int32_t n_sys = 1;
+    std::vector<int32_t> part_system;     // system of every part
+    std::vector<int32_t> sys_size;        // vertices of every system
+    SysParams *h_sys = nullptr;           // pinned staging of the per-system parameters
+    hipEvent_t sys_uploaded = nullptr;    // recorded after each upload from h_sys
+    bool sys_upload_pending = false;
     hipStream_t stream = nullptr;
     int64_t nnz_graph = 0;
     double plan_ms = 0.0;
@@ -212,6 +218,20 @@ struct gsp2_plan_s {
         if (graph) (void)hipGraphDestroy(graph);
         for (void *p : dev_ptrs) (void)hipFree(p);
         if (h_state) (void)hipHostFree(h_state);
+        if (h_sys) (void)hipHostFree(h_sys);
+        if (sys_uploaded) (void)hipEventDestroy(sys_uploaded);
+    }
+    // Copy h_sys to the device in stream order.  The staging buffer is
+    // rewritten only after the previous copy from it has completed.
+    void wait_sys_staging() {
+        if (sys_upload_pending) check_hip(hipEventSynchronize(sys_uploaded), "parameter upload");
+        sys_upload_pending = false;
+    }
+    void upload_sys() {
+        check_hip(hipMemcpyAsync(dp.sys_params, h_sys, sizeof(SysParams) * (size_t)n_sys, hipMemcpyHostToDevice,
+                                 stream), "upload system parameters");
+        check_hip(hipEventRecord(sys_uploaded, stream), "parameter upload");
+        sys_upload_pending = true;
     }
     template <typename T>
     T *alloc(size_t count, const char *what) {
@@ -251,6 +271,9 @@ gsp2_status gsp2_run_options_default(gsp2_run_options *opt) {
         opt->precision = GSP2_PREC_FP32;
         opt->refine = 0;
         opt->persistent = 0;
+        opt->n_occ_system = nullptr;
+        opt->alpha_seq_system = nullptr;
+        opt->n_alpha_system = nullptr;
     });
 }
 
@@ -284,13 +307,30 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         if (!(tau >= 0.0) || !std::isfinite(tau)) fail(GSP2_E_INVALID, "tau must be finite and >= 0");
         if (n_parts < 1 || n_parts > P_prev->n) fail(GSP2_E_INVALID, "need 1 <= n_parts <= n");
         if (opt && opt->tile != 0 && opt->tile != kTile) fail(GSP2_E_UNSUPPORTED, "tile must be 0 or 128");
+        const int32_t n_sys = (opt && opt->n_systems > 1) ? opt->n_systems : 1;
+        if (opt && opt->n_systems < 0) fail(GSP2_E_INVALID, "n_systems must be >= 0");
+        if (n_sys > n_parts) fail(GSP2_E_INVALID, "more systems than parts");
+        if (n_sys > 1 && !opt->part_system) fail(GSP2_E_INVALID, "null part_system for a batched plan");
         plan = new gsp2_plan_s();
         plan->n = P_prev->n;
         plan->n_parts = n_parts;
+        plan->n_sys = n_sys;
         plan->stream = static_cast<hipStream_t>(stream);
         hipStream_t s = plan->stream;
         const int32_t n = plan->n;
         plan->part.assign(part, part + n);
+        plan->part_system.assign(n_parts, 0);
+        if (n_sys > 1) {
+            std::vector<int32_t> used(n_sys, 0);
+            for (int32_t k = 0; k < n_parts; ++k) {
+                const int32_t y = opt->part_system[k];
+                if (y < 0 || y >= n_sys) fail(GSP2_E_INVALID, "part_system out of range at part " + std::to_string(k));
+                plan->part_system[k] = y;
+                used[y] = 1;
+            }
+            for (int32_t y = 0; y < n_sys; ++y)
+                if (!used[y]) fail(GSP2_E_INVALID, "system " + std::to_string(y) + " has no part");
+        }
 
         // a1: threshold on the GPU, then bring the directed adjacency home
         int64_t tmp_bytes = 0;
@@ -332,6 +372,19 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         // a3: cores and halos (host)
         plan_core_halo(n, adj_ptr.data(), adj_col.data(), part, n_parts, plan->sub_ptr, plan->sub_idx,
                        plan->core_count);
+        if (n_sys > 1) {
+            // systems are independent: no edge of the graph may join two of them
+            for (int32_t v = 0; v < n; ++v) {
+                const int32_t yv = plan->part_system[part[v]];
+                for (int64_t e = adj_ptr[v]; e < adj_ptr[v + 1]; ++e) {
+                    const int32_t w = adj_col[e];
+                    if (plan->part_system[part[w]] != yv)
+                        fail(GSP2_E_INVALID, "graph edge " + std::to_string(v) + "-" + std::to_string(w) +
+                                                 " joins systems " + std::to_string(yv) + " and " +
+                                                 std::to_string(plan->part_system[part[w]]));
+                }
+            }
+        }
         plan->nnz_graph = (int64_t)adj_col.size();
         std::vector<int64_t>().swap(adj_ptr);
         std::vector<int32_t>().swap(adj_col);
@@ -349,6 +402,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             d.idx_off = (int32_t)plan->sub_ptr[k];
             d.perm_off = (int32_t)plan->sub_ptr[k];
             d.x_off = xoff;
+            d.sys = plan->part_system[k];
             xoff += (int64_t)d.s_pad * d.s_pad;
             max_s_pad = std::max(max_s_pad, d.s_pad);
             plan->desc[k] = d;
@@ -376,7 +430,21 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             load[x] += work(k);
             xcd_parts[x].push_back(k);
         }
+        // Trace partials of the diagonal tiles: slots grouped by system, then
+        // by part and tile row, so a system's traces are reduced in an order
+        // that does not depend on the other systems of the batch.
+        std::vector<std::vector<int32_t>> sys_parts(n_sys);
+        for (int32_t k = 0; k < n_parts; ++k) sys_parts[plan->part_system[k]].push_back(k);
+        std::vector<int32_t> diag_base(n_parts, 0);
+        std::vector<int32_t> sys_diag_ptr(n_sys + 1, 0), sys_chunk_ptr(n_sys + 1, 0);
         int32_t slot = 0;
+        for (int32_t y = 0; y < n_sys; ++y) {
+            for (int32_t k : sys_parts[y]) {
+                diag_base[k] = slot;
+                slot += plan->desc[k].s_pad / T;
+            }
+            sys_diag_ptr[y + 1] = slot;
+        }
         std::vector<std::vector<TileDesc>> lists(kXcds);
         for (int x = 0; x < kXcds; ++x) {
             for (int32_t k : xcd_parts[x]) {
@@ -385,7 +453,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
                     for (int bj = bi; bj < nt; bj += kTileBlock)
                         for (int ti = bi; ti < std::min(bi + kTileBlock, nt); ++ti)
                             for (int tj = std::max(ti, bj); tj < std::min(bj + kTileBlock, nt); ++tj)
-                                lists[x].push_back(TileDesc{k, ti, tj, ti == tj ? slot++ : -1});
+                                lists[x].push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + ti : -1});
             }
         }
         size_t longest = 0;
@@ -395,9 +463,21 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
                 plan->tiles.push_back(q < lists[x].size() ? lists[x][q] : TileDesc{-1, 0, 0, -1});
         plan->n_diag = slot;
         constexpr int kRowsPerChunk = 16;
-        for (int32_t k = 0; k < n_parts; ++k)
-            for (int r0 = 0; r0 < plan->desc[k].s_pad; r0 += kRowsPerChunk)
-                plan->chunks.push_back(RowChunk{k, r0, std::min(r0 + kRowsPerChunk, plan->desc[k].s_pad), 0});
+        for (int32_t y = 0; y < n_sys; ++y) {
+            for (int32_t k : sys_parts[y])
+                for (int r0 = 0; r0 < plan->desc[k].s_pad; r0 += kRowsPerChunk)
+                    plan->chunks.push_back(RowChunk{k, r0, std::min(r0 + kRowsPerChunk, plan->desc[k].s_pad), 0});
+            sys_chunk_ptr[y + 1] = (int32_t)plan->chunks.size();
+        }
+        // vertices of every system, ascending, for the per-system Gershgorin bounds
+        std::vector<int32_t> sys_row_ptr(n_sys + 1, 0), sys_rows(n);
+        plan->sys_size.assign(n_sys, 0);
+        for (int32_t v = 0; v < n; ++v) plan->sys_size[plan->part_system[part[v]]]++;
+        for (int32_t y = 0; y < n_sys; ++y) sys_row_ptr[y + 1] = sys_row_ptr[y] + plan->sys_size[y];
+        {
+            std::vector<int32_t> fill(sys_row_ptr.begin(), sys_row_ptr.end() - 1);
+            for (int32_t v = 0; v < n; ++v) sys_rows[fill[plan->part_system[part[v]]]++] = v;
+        }
         plan->perm.resize(plan->sub_idx.size());
         for (int32_t k = 0; k < n_parts; ++k) {
             const int64_t b = plan->sub_ptr[k];
@@ -431,7 +511,8 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         dp.n_diag = plan->n_diag;
         dp.n_chunks = (int32_t)plan->chunks.size();
         dp.max_s_pad = max_s_pad;
-        dp.gersh_blocks = std::max(1, std::min(1024, (n + 3) / 4));
+        dp.gersh_blocks = (n + kRowsPerBlock - 1) / kRowsPerBlock;
+        dp.n_sys = n_sys;
         dp.buf[0] = plan->alloc<float>(plan->arena_floats, "X buffer 0");
         dp.buf[1] = plan->alloc<float>(plan->arena_floats, "X buffer 1");
         auto *d_parts = plan->alloc<PartDesc>(n_parts, "part descriptors");
@@ -462,8 +543,21 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             dp.persist_timeout = (long long)std::max(rate_khz, 1000) * 1000LL * 20;   // 20 s
         }
         dp.x0_partials = plan->alloc<double>(plan->chunks.size(), "x0 partials");
-        dp.gersh_partials = plan->alloc<double>(5 * (size_t)dp.gersh_blocks, "gershgorin partials");
-        dp.state = plan->alloc<RunState>(1, "run state");
+        dp.row_bounds = plan->alloc<double>(3 * (size_t)n, "gershgorin discs");
+        auto *d_sys_rows = plan->alloc<int32_t>(n, "system rows");
+        auto *d_sys_row_ptr = plan->alloc<int32_t>(n_sys + 1, "system row pointer");
+        auto *d_sys_chunk_ptr = plan->alloc<int32_t>(n_sys + 1, "system chunk pointer");
+        auto *d_sys_diag_ptr = plan->alloc<int32_t>(n_sys + 1, "system slot pointer");
+        dp.sys_params = plan->alloc<SysParams>(n_sys, "system parameters");
+        dp.state = plan->alloc<RunState>(n_sys, "run state");
+        upload(d_sys_rows, sys_rows, s, "upload system rows");
+        upload(d_sys_row_ptr, sys_row_ptr, s, "upload system rows");
+        upload(d_sys_chunk_ptr, sys_chunk_ptr, s, "upload system chunks");
+        upload(d_sys_diag_ptr, sys_diag_ptr, s, "upload system slots");
+        dp.sys_rows = d_sys_rows;
+        dp.sys_row_ptr = d_sys_row_ptr;
+        dp.sys_chunk_ptr = d_sys_chunk_ptr;
+        dp.sys_diag_ptr = d_sys_diag_ptr;
         upload(d_parts, plan->desc, s, "upload parts");
         upload(d_tiles, plan->tiles, s, "upload tiles");
         upload(d_chunks, plan->chunks, s, "upload chunks");
@@ -472,7 +566,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         upload(d_colptr, plan->col_ptr, s, "upload col_ptr");
         upload(d_colpart, plan->col_part, s, "upload col_part");
         upload(d_collocal, plan->col_local, s, "upload col_local");
-        check_hip(hipMemsetAsync(dp.state, 0, sizeof(RunState), s), "clear state");
+        check_hip(hipMemsetAsync(dp.state, 0, sizeof(RunState) * (size_t)n_sys, s), "clear state");
         dp.parts = d_parts;
         dp.tiles = d_tiles;
         dp.chunks = d_chunks;
@@ -482,7 +576,11 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         dp.col_ptr = d_colptr;
         dp.col_part = d_colpart;
         dp.col_local = d_collocal;
-        check_hip(hipHostMalloc((void **)&plan->h_state, sizeof(RunState), hipHostMallocDefault), "pinned state");
+        check_hip(hipHostMalloc((void **)&plan->h_state, sizeof(RunState) * (size_t)n_sys, hipHostMallocDefault),
+                  "pinned state");
+        check_hip(hipHostMalloc((void **)&plan->h_sys, sizeof(SysParams) * (size_t)n_sys, hipHostMallocDefault),
+                  "pinned parameters");
+        check_hip(hipEventCreateWithFlags(&plan->sys_uploaded, hipEventDisableTiming), "event");
         check_hip(hipStreamSynchronize(s), "plan upload");
         plan->plan_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -518,6 +616,7 @@ gsp2_status gsp2_plan_query(gsp2_plan plan, gsp2_plan_info *info, int32_t *core_
             info->n_tiles = (int32_t)plan->tiles.size();
             info->workspace_bytes = plan->workspace_bytes;
             info->plan_ms = plan->plan_ms;
+            info->n_systems = plan->n_sys;
         }
         for (int32_t k = 0; k < plan->n_parts; ++k) {
             if (core_sizes) core_sizes[k] = plan->desc[k].c;
@@ -562,8 +661,7 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream) {
     });
 }
 
-static void fill_info(const gsp2_plan_s *plan, gsp2_run_info *info) {
-    const RunState &r = *plan->h_state;
+static void fill_info(const RunState &r, gsp2_run_info *info) {
     std::memset(info, 0, sizeof(*info));
     info->status = r.status;
     info->n_products = r.n_products;
@@ -586,13 +684,17 @@ static void fill_info(const gsp2_plan_s *plan, gsp2_run_info *info) {
 static gsp2_status collect(gsp2_plan_s *plan, gsp2_run_info *info) {
     gsp2_status run_status = GSP2_OK;
     const gsp2_status st = guarded([&] {
-        check_hip(hipMemcpyAsync(plan->h_state, plan->dp.state, sizeof(RunState), hipMemcpyDeviceToHost,
-                                 plan->stream), "copy run state");
+        check_hip(hipMemcpyAsync(plan->h_state, plan->dp.state, sizeof(RunState) * (size_t)plan->n_sys,
+                                 hipMemcpyDeviceToHost, plan->stream), "copy run state");
         check_hip(hipStreamSynchronize(plan->stream), "run");
-        if (info) fill_info(plan, info);
-        run_status = (gsp2_status)plan->h_state->status;
-        if (run_status != GSP2_OK) {
-            const RunState &r = *plan->h_state;
+        int32_t bad = -1;
+        for (int32_t y = 0; y < plan->n_sys; ++y) {
+            if (info) fill_info(plan->h_state[y], info + y);
+            if (bad < 0 && plan->h_state[y].status != GSP2_OK) bad = y;
+        }
+        if (bad >= 0) {
+            run_status = (gsp2_status)plan->h_state[bad].status;
+            const RunState &r = plan->h_state[bad];
             char buf[256];
             if (run_status == GSP2_E_INVALID)
                 std::snprintf(buf, sizeof buf, "H rejected: Gershgorin bounds [%g, %g] not finite or empty",
@@ -605,6 +707,7 @@ static gsp2_status collect(gsp2_plan_s *plan, gsp2_run_info *info) {
                 std::snprintf(buf, sizeof buf, "trace %.6f differs from n_occ %.6f by more than %g",
                               r.traces[r.result_t], r.n_occ, r.trace_tol);
             g_last_error = buf;
+            if (plan->n_sys > 1) g_last_error = "system " + std::to_string(bad) + ": " + g_last_error;
         }
     });
     if (st != GSP2_OK) return st;
@@ -621,12 +724,12 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
             fail(GSP2_E_INVALID, "bad H arrays");
         if (H->dtype != GSP2_F32 && H->dtype != GSP2_F64) fail(GSP2_E_INVALID, "bad H.dtype");
         if (!P_val) fail(GSP2_E_INVALID, "null P_val");
-        if (!(n_occ >= 0.0) || !(n_occ <= (double)plan->n)) fail(GSP2_E_INVALID, "need 0 <= n_occ <= n");
         gsp2_run_options def;
         gsp2_run_options_default(&def);
         const gsp2_run_options &o = run ? *run : def;
+        const int32_t n_sys = plan->n_sys;
+        if (n_sys > 1 && !o.n_occ_system) fail(GSP2_E_INVALID, "a batched plan needs n_occ_system");
         RunParams rp{};
-        rp.n_occ = n_occ;
         rp.trace_tol = o.trace_tol;
         rp.mode = o.alpha_mode;
         rp.stop_rule = o.stop_rule ? 1 : 0;
@@ -646,26 +749,43 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
             if (grid < 1) fail(GSP2_E_UNSUPPORTED, "persistent product kernel cannot be resident");
             plan->dp.persist_grid = std::min(grid, plan->dp.n_tiles);
         }
-        {
-            // the stop rule's floor max(1, n u), u the unit roundoff of the product operands
-            const double u = o.precision == GSP2_PREC_FP16 ? std::ldexp(1.0, -11)
-                             : o.precision == GSP2_PREC_BF16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -24);
-            rp.stop_floor = std::max(1.0, plan->n * u);
-        }
-        if (o.alpha_mode == GSP2_ALPHA_TRACE) {
-            if (o.max_iter < 1 || o.max_iter > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter out of range");
-            rp.n_steps = o.max_iter;
-        } else if (o.alpha_mode == GSP2_ALPHA_REPLAY) {
-            if (o.n_alpha < 0 || o.n_alpha > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_alpha out of range");
-            if (o.n_alpha > 0 && !o.alpha_seq) fail(GSP2_E_INVALID, "null alpha_seq");
+        // per-system parameters, staged for the upload that precedes the launch
+        plan->wait_sys_staging();
+        std::memset(plan->h_sys, 0, sizeof(SysParams) * (size_t)n_sys);
+        // the stop rule's floor max(1, n u), u the unit roundoff of the product operands
+        const double u = o.precision == GSP2_PREC_FP16 ? std::ldexp(1.0, -11)
+                         : o.precision == GSP2_PREC_BF16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -24);
+        if (o.alpha_mode == GSP2_ALPHA_REPLAY) {
             if (!(o.trace_tol >= 0.0)) fail(GSP2_E_INVALID, "trace_tol must be >= 0");
-            for (int i = 0; i < o.n_alpha; ++i) {
-                if (o.alpha_seq[i] != 1 && o.alpha_seq[i] != -1) fail(GSP2_E_INVALID, "alpha must be +1 or -1");
-                rp.alpha_seq[i] = o.alpha_seq[i];
-            }
-            rp.n_steps = o.n_alpha;
+        } else if (o.alpha_mode == GSP2_ALPHA_TRACE) {
+            if (o.max_iter < 1 || o.max_iter > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter out of range");
         } else {
             fail(GSP2_E_INVALID, "bad alpha_mode");
+        }
+        const bool own_seq = n_sys > 1 && o.alpha_mode == GSP2_ALPHA_REPLAY && o.alpha_seq_system;
+        if (own_seq && !o.n_alpha_system) fail(GSP2_E_INVALID, "null n_alpha_system");
+        rp.n_steps = 0;
+        for (int32_t y = 0; y < n_sys; ++y) {
+            SysParams &sp = plan->h_sys[y];
+            const std::string who = n_sys > 1 ? " (system " + std::to_string(y) + ")" : "";
+            const double occ = n_sys > 1 ? o.n_occ_system[y] : n_occ;
+            if (!(occ >= 0.0) || !(occ <= (double)plan->sys_size[y])) fail(GSP2_E_INVALID, "need 0 <= n_occ <= n" + who);
+            sp.n_occ = occ;
+            sp.stop_floor = std::max(1.0, plan->sys_size[y] * u);
+            if (o.alpha_mode == GSP2_ALPHA_TRACE) {
+                sp.n_steps = o.max_iter;
+            } else {
+                const int32_t na = own_seq ? o.n_alpha_system[y] : o.n_alpha;
+                const int8_t *seq = own_seq ? o.alpha_seq_system + (size_t)y * GSP2_MAX_ITER : o.alpha_seq;
+                if (na < 0 || na > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_alpha out of range" + who);
+                if (na > 0 && !seq) fail(GSP2_E_INVALID, "null alpha_seq");
+                for (int i = 0; i < na; ++i) {
+                    if (seq[i] != 1 && seq[i] != -1) fail(GSP2_E_INVALID, "alpha must be +1 or -1" + who);
+                    sp.alpha_seq[i] = seq[i];
+                }
+                sp.n_steps = na;
+            }
+            rp.n_steps = std::max(rp.n_steps, sp.n_steps);
         }
         if (rp.n_steps + rp.refine > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter + refine exceeds GSP2_MAX_ITER");
         if (rp.precision != GSP2_PREC_FP32 && !plan->dp.shadow[0]) {
@@ -678,6 +798,7 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         k.p_val = P_val; k.rp = rp; k.timing = o.timing != 0;
         const RunEvents *evp = nullptr;
         if (o.timing) { plan->make_events(); evp = &plan->ev; }
+        plan->upload_sys();
         const bool eager = std::getenv("GSP2_EAGER") != nullptr;
         if (eager) {
             Recorder rec;
@@ -716,8 +837,8 @@ gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out) {
     return guarded([&] {
         if (!plan || !out) fail(GSP2_E_INVALID, "null argument");
         if (!plan->ran || !plan->last_timed) fail(GSP2_E_INVALID, "the last run on this plan was not timed");
-        check_hip(hipMemcpyAsync(plan->h_state, plan->dp.state, sizeof(RunState), hipMemcpyDeviceToHost,
-                                 plan->stream), "copy run state");
+        check_hip(hipMemcpyAsync(plan->h_state, plan->dp.state, sizeof(RunState) * (size_t)plan->n_sys,
+                                 hipMemcpyDeviceToHost, plan->stream), "copy run state");
         check_hip(hipStreamSynchronize(plan->stream), "timed run");
         std::memset(out, 0, sizeof(*out));
         const RunEvents &e = plan->ev;
@@ -727,11 +848,16 @@ gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out) {
         check_hip(hipEventElapsedTime(&out->total_ms, e.begin, e.end), "elapsed");
         // main-phase products occupy the first launch slots, refinement products
         // the slots after the main-phase budget
-        const RunState &r = *plan->h_state;
+        // launches that carried work: the most any system formed
+        int max_main = 0, max_ref = 0;
+        for (int32_t y = 0; y < plan->n_sys; ++y) {
+            max_main = std::max(max_main, plan->h_state[y].n_main);
+            max_ref = std::max(max_ref, plan->h_state[y].n_refine);
+        }
         if (plan->last_rp.persistent && plan->last_rp.n_steps > 0)
             check_hip(hipEventElapsedTime(&out->persistent_ms, e.persist_begin, e.persist_end), "elapsed");
-        const int n_main = plan->last_rp.persistent ? 0 : std::min(r.n_main, plan->last_rp.n_steps);
-        const int n_ref = std::min(r.n_refine, plan->last_rp.refine);
+        const int n_main = plan->last_rp.persistent ? 0 : std::min(max_main, plan->last_rp.n_steps);
+        const int n_ref = std::min(max_ref, plan->last_rp.refine);
         out->n_products = n_main + n_ref;
         for (int t = 0; t < n_main; ++t)
             check_hip(hipEventElapsedTime(&out->product_ms[t], e.step[2 * t], e.step[2 * t + 1]), "elapsed");
@@ -752,6 +878,7 @@ gsp2_status gsp2_backward(gsp2_plan plan, const gsp2_csr *H, const int8_t *alpha
     };
     gsp2_status st = guarded([&] {
         if (!plan) fail(GSP2_E_INVALID, "null plan");
+        if (plan->n_sys > 1) fail(GSP2_E_UNSUPPORTED, "backward pass of a batched plan");
         if (!H || H->n != plan->n) fail(GSP2_E_INVALID, "H missing or of another size");
         if (H->nnz < 0 || !H->row_ptr || (H->nnz > 0 && (!H->col || !H->val)))
             fail(GSP2_E_INVALID, "bad H arrays");
@@ -782,13 +909,17 @@ gsp2_status gsp2_backward(gsp2_plan plan, const gsp2_csr *H, const int8_t *alpha
         bb.d_eps = dev_alloc<double>(2, "backward bound cotangents", bytes);
         temps.push_back(bb.d_eps);
         RunParams rp{};
-        rp.n_occ = 0.0;
         rp.trace_tol = 1e300;
-        rp.stop_floor = 1.0;
         rp.n_steps = n;
         rp.mode = GSP2_ALPHA_REPLAY;
         rp.precision = GSP2_PREC_FP32;
-        for (int i = 0; i < n; ++i) rp.alpha_seq[i] = alpha_seq[i];
+        plan->wait_sys_staging();
+        SysParams &sp = plan->h_sys[0];
+        std::memset(&sp, 0, sizeof sp);
+        sp.stop_floor = 1.0;
+        sp.n_steps = n;
+        for (int i = 0; i < n; ++i) sp.alpha_seq[i] = alpha_seq[i];
+        plan->upload_sys();
         check_hip(launch_backward(plan->dp, *H, rp, alpha_seq, n, dLdP_val, dLdH_val, bb, plan->stream),
                   "launch backward");
         double d_eps[2] = {0.0, 0.0};

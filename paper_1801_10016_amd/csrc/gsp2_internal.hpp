@@ -16,6 +16,10 @@ constexpr int kKChunk = 32;
 // XCDs of an MI355X: workgroup b of a launch runs on XCD b mod kXcds.
 constexpr int kXcds = 8;
 
+// Row kernels (threshold, Gershgorin, scatter) give one wave to a row in
+// 256-thread workgroups: rows per workgroup.
+constexpr int kRowsPerBlock = 4;
+
 // One part of the partition, as the device sees it.
 struct PartDesc {
     int64_t x_off;      // float offset of the part's s_pad x s_pad block in each X buffer
@@ -24,7 +28,7 @@ struct PartDesc {
     int32_t c;          // core size
     int32_t s_pad;      // s rounded up to a multiple of kTile (padding is zero)
     int32_t perm_off;   // offset of its sorted-position -> local-index map
-    int32_t pad_;
+    int32_t sys;        // system of the part (0 unless the plan is batched)
 };
 static_assert(sizeof(PartDesc) == 32, "PartDesc layout");
 
@@ -39,8 +43,9 @@ struct RowChunk {
     int32_t part, r0, r1, pad_;
 };
 
-// Run-time state of one density-matrix computation, in device memory.
-// Written only by the single-workgroup control kernels.
+// Run-time state of one system's density-matrix computation, in device
+// memory (one per system of the plan).  Written only by the control kernels,
+// one workgroup per system.
 struct RunState {
     double n_occ;
     double trace_tol;
@@ -81,19 +86,27 @@ struct PersistCtl {
     unsigned head[GSP2_MAX_ITER][kXcds];  // per product, per XCD tile-queue head
 };
 
-// Per-call parameters baked into the run's kernels.
+// Per-call parameters baked into the run's kernels (the same for every system).
 struct RunParams {
-    double n_occ;
     double trace_tol;
-    double stop_floor;          // max(1, n u): |e_{t-2}| must be below it for the stop rule
-    int32_t n_steps;            // main-phase product budget
+    int32_t n_steps;            // main-phase product launches: the largest budget of any system
     int32_t mode;
     int32_t stop_rule;
     int32_t precision;          // gsp2_precision of the main phase
     int32_t refine;             // FP32 products after the main phase
     int32_t persistent;         // 1: main-phase products in one persistent launch
-    int8_t alpha_seq[GSP2_MAX_ITER];
 };
+
+// Per-call parameters of one system, uploaded to the device before each run.
+struct SysParams {
+    double n_occ;
+    double stop_floor;          // max(1, n u): |e_{t-2}| must be below it for the stop rule
+    int32_t n_steps;            // main-phase product budget of this system
+    int32_t pad_;
+    int8_t alpha_seq[GSP2_MAX_ITER];
+    int8_t pad2_[4];
+};
+static_assert(sizeof(SysParams) % 8 == 0, "SysParams layout");
 
 // Device buffers of a plan, passed to the launchers.
 struct DevicePlan {
@@ -103,8 +116,8 @@ struct DevicePlan {
     int32_t n_diag;
     int32_t n_chunks;
     int32_t max_s_pad;
-    int32_t gersh_blocks;
-    int32_t pad_;
+    int32_t gersh_blocks;       // row blocks of the Gershgorin kernel
+    int32_t n_sys;              // systems (1 unless batched)
     float *buf[2];
     void *shadow[2];            // 16-bit operand copies of the two X buffers (mixed precision)
     const PartDesc *parts;
@@ -122,8 +135,13 @@ struct DevicePlan {
     PersistCtl *persist;
     double *diag_partials;      // 2 x n_diag x 2 (double-buffered by product parity)
     double *x0_partials;        // n_chunks
-    double *gersh_partials;     // gersh_blocks x 3
-    RunState *state;
+    double *row_bounds;         // n x 3: Gershgorin lower and upper end, non-finite flag of every row
+    const int32_t *sys_rows;    // vertices of every system, ascending, grouped by system
+    const int32_t *sys_row_ptr; // n_sys + 1 offsets into sys_rows
+    const int32_t *sys_chunk_ptr;   // n_sys + 1: gather chunks are grouped by system
+    const int32_t *sys_diag_ptr;    // n_sys + 1: diagonal-tile slots are grouped by system
+    SysParams *sys_params;      // n_sys
+    RunState *state;            // n_sys
 };
 
 // Optional event records of a timed run.  step[2t] / step[2t+1] bracket the

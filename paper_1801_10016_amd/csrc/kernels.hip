@@ -1,7 +1,7 @@
 // HIP kernels of the G-SP2 hot path for CDNA4 (gfx950), wave64.
 //
 //  threshold   G_tau from a previous P                (Methods, "Graph Theory")
-//  gershgorin  spectral bounds of the whole H          (Methods, SP2: Gershgorin discs)
+//  gershgorin  spectral bounds of each system's H      (Methods, SP2: Gershgorin discs)
 //  gather_x0   dense core+halo blocks of eq. (1)       (Fig. 1 description: sub-matrices of H)
 //  sp2_step    X^2 on the matrix cores + eq. (2) update + core-trace partials
 //  control     FP64 trace reductions, branch and stop decisions (eq. (2) branch rule, idempotency)
@@ -20,6 +20,7 @@ namespace {
 
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
+static_assert(kBlock / kWave == kRowsPerBlock, "row kernels: one wave per row");
 
 template <typename T>
 __device__ __forceinline__ double as_double(T v) { return static_cast<double>(v); }
@@ -93,12 +94,11 @@ __global__ __launch_bounds__(kBlock) void k_threshold_fill(const int64_t *__rest
 }
 
 // ---------------------------------------------------------------------------
-// a4: Gershgorin bounds.  One wave per row, FP64; per-block min/max partials.
+// a4: Gershgorin bounds.  One wave per row, FP64: the lower and upper end of
+// the row's disc and a non-finite flag.  A system's bounds are the extremes
+// over its rows, taken with the lowest row winning ties, so the rows that
+// attain them (and the bounds' derivatives) are well defined.
 // ---------------------------------------------------------------------------
-// Partials per block: lo, hi, non-finite flag, row of lo, row of hi (ties
-// resolved to the lowest row, so the bounds' derivatives are well defined).
-constexpr int kGershStride = 5;
-
 __device__ __forceinline__ void keep_lo(double &lo, double &row, double l2, double r2) {
     if (l2 < lo || (l2 == lo && r2 < row)) { lo = l2; row = r2; }
 }
@@ -110,62 +110,66 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_gershgorin(const int64_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ col,
                                                        const T *__restrict__ val, int32_t n,
-                                                       double *__restrict__ partials) {
-    __shared__ double s_lo[kBlock / kWave], s_hi[kBlock / kWave], s_bad[kBlock / kWave];
-    __shared__ double s_rlo[kBlock / kWave], s_rhi[kBlock / kWave];
+                                                       double *__restrict__ row_bounds) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int w = threadIdx.x / kWave;
-    double lo = INFINITY, hi = -INFINITY, bad = 0.0, rlo = 1e300, rhi = 1e300;
-    const int64_t stride = (int64_t)gridDim.x * (kBlock / kWave);
-    for (int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + w; row < n; row += stride) {
-        const int64_t b = row_ptr[row], e = row_ptr[row + 1];
-        double rad = 0.0, d = 0.0, nf = 0.0;
-        for (int64_t i = b + lane; i < e; i += kWave) {
-            const double v = as_double(val[i]);
-            if (!isfinite(v)) nf = 1.0;
-            if (col[i] == row) d += v; else rad += fabs(v);
-        }
-        rad = wave_sum(rad);
-        d = wave_sum(d);
-        nf = wave_sum(nf);
-        keep_lo(lo, rlo, d - rad, (double)row);
-        keep_hi(hi, rhi, d + rad, (double)row);
-        if (nf > 0.0) bad = 1.0;
+    const int64_t row = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (row >= n) return;                       // whole waves leave together
+    const int64_t b = row_ptr[row], e = row_ptr[row + 1];
+    double rad = 0.0, d = 0.0, nf = 0.0;
+    for (int64_t i = b + lane; i < e; i += kWave) {
+        const double v = as_double(val[i]);
+        if (!isfinite(v)) nf = 1.0;
+        if (col[i] == row) d += v; else rad += fabs(v);
     }
-    if (lane == 0) { s_lo[w] = lo; s_hi[w] = hi; s_bad[w] = bad; s_rlo[w] = rlo; s_rhi[w] = rhi; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < kBlock / kWave; ++i) {
-            keep_lo(lo, rlo, s_lo[i], s_rlo[i]);
-            keep_hi(hi, rhi, s_hi[i], s_rhi[i]);
-            bad = fmax(bad, s_bad[i]);
-        }
-        double *out = partials + kGershStride * blockIdx.x;
-        out[0] = lo; out[1] = hi; out[2] = bad; out[3] = rlo; out[4] = rhi;
+    rad = wave_sum(rad);
+    d = wave_sum(d);
+    nf = wave_sum(nf);
+    if (lane == 0) {
+        double *out = row_bounds + 3 * row;
+        out[0] = d - rad;
+        out[1] = d + rad;
+        out[2] = nf;
     }
 }
 
-// Reduce the Gershgorin partials and initialise the run state.
-__global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ partials, int nblk,
-                                                     RunParams rp, RunState *__restrict__ st) {
-    if (threadIdx.x != 0) return;
+// Reduce the discs of every system's rows and initialise its run state.
+// One workgroup per system.
+__global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ row_bounds,
+                                                     const int32_t *__restrict__ sys_rows,
+                                                     const int32_t *__restrict__ sys_row_ptr, RunParams rp,
+                                                     const SysParams *__restrict__ sys_params,
+                                                     RunState *__restrict__ st_all) {
+    __shared__ double s_lo[kBlock], s_hi[kBlock], s_bad[kBlock], s_rlo[kBlock], s_rhi[kBlock];
+    const int sys = blockIdx.x;
     double lo = INFINITY, hi = -INFINITY, bad = 0.0, rlo = 1e300, rhi = 1e300;
-    for (int i = 0; i < nblk; ++i) {
-        const double *p = partials + kGershStride * i;
-        keep_lo(lo, rlo, p[0], p[3]);
-        keep_hi(hi, rhi, p[1], p[4]);
-        bad = fmax(bad, p[2]);
+    for (int i = sys_row_ptr[sys] + threadIdx.x; i < sys_row_ptr[sys + 1]; i += kBlock) {
+        const int32_t r = sys_rows[i];
+        const double *rb = row_bounds + 3 * (int64_t)r;
+        keep_lo(lo, rlo, rb[0], (double)r);
+        keep_hi(hi, rhi, rb[1], (double)r);
+        bad = fmax(bad, rb[2]);
     }
+    s_lo[threadIdx.x] = lo; s_hi[threadIdx.x] = hi; s_bad[threadIdx.x] = bad;
+    s_rlo[threadIdx.x] = rlo; s_rhi[threadIdx.x] = rhi;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 1; i < kBlock; ++i) {
+        keep_lo(lo, rlo, s_lo[i], s_rlo[i]);
+        keep_hi(hi, rhi, s_hi[i], s_rhi[i]);
+        bad = fmax(bad, s_bad[i]);
+    }
+    RunState *st = st_all + sys;
+    const SysParams &sp = sys_params[sys];
     st->row_min = rlo < 1e300 ? (int)rlo : -1;
     st->row_max = rhi < 1e300 ? (int)rhi : -1;
-    st->n_occ = rp.n_occ;
+    st->n_occ = sp.n_occ;
     st->trace_tol = rp.trace_tol;
-    st->stop_floor = rp.stop_floor;
+    st->stop_floor = sp.stop_floor;
     st->eps_min = lo;
     st->eps_max = hi;
     st->trX = 0.0;
     st->idem = NAN;
-    st->n_steps = rp.n_steps;
+    st->n_steps = sp.n_steps;
     st->mode = rp.mode;
     st->stop_rule = rp.stop_rule;
     st->t = 0;
@@ -182,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ 
     st->n_main = 0;
     st->precision = rp.precision;
     for (int i = 0; i < GSP2_MAX_ITER; ++i) {
-        st->alpha_seq[i] = rp.alpha_seq[i];
+        st->alpha_seq[i] = sp.alpha_seq[i];
         st->alpha_hist[i] = 0;
         st->errors[i] = NAN;
         st->traces[i] = NAN;
@@ -233,13 +237,14 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
                                                       const RowChunk *__restrict__ chunks,
                                                       const int32_t *__restrict__ idx_arena,
                                                       float *__restrict__ X, uint16_t *__restrict__ Xs,
-                                                      const RunState *__restrict__ st,
+                                                      const RunState *__restrict__ st_all,
                                                       double *__restrict__ x0_partials) {
     __shared__ int32_t idx_s[kGatherLdsIdx];
     __shared__ float row_s[kGatherChunk];
-    if (st->done) return;
     const RowChunk ch = chunks[blockIdx.x];
     const PartDesc pd = parts[ch.part];
+    const RunState *st = st_all + pd.sys;
+    if (st->done) return;
     const int32_t *idx_g = idx_arena + pd.idx_off;
     const bool in_lds = pd.s <= kGatherLdsIdx;
     if (in_lds) {
@@ -327,6 +332,12 @@ __device__ void ctl_store(RunState *st, const Ctl &c) {
 }
 
 // End of the main phase: hand over to the FP32 refinement products, or stop.
+// Refinement alternates X^2 and 2X - X^2 whatever the trace: one pair maps
+// an eigenvalue l to 2 l^2 - l^4, whose stable fixed points are 0 and 1
+// (split at (sqrt(5) - 1) / 2), so every pair drives each eigenvalue to the
+// nearer of the two, quadratically.  The trace rule would keep picking the
+// branch that moves the trace towards n_occ; once the occupation is settled
+// that doubles the distance of eigenvalues near 0 (or near 1) at each product.
 __device__ void finish_main(Ctl &c, int result_buf, int result_t, int status, bool refinable) {
     c.n_main = c.n_products;
     if (refinable && c.refine > 0) {
@@ -335,7 +346,7 @@ __device__ void finish_main(Ctl &c, int result_buf, int result_t, int status, bo
         c.cur = result_buf;
         c.t = result_t;
         c.refine_left = c.refine;
-        c.alpha = c.trX <= c.n_occ ? 1 : -1;
+        c.alpha = -1;
         return;
     }
     c.done = 1;
@@ -386,7 +397,7 @@ __device__ void decide(Ctl &c, double ty, double tx, RunState *st, bool writer) 
             c.status = c.main_status;
             return;
         }
-        c.alpha = tx <= c.n_occ ? 1 : -1;
+        c.alpha = -c.alpha;
         return;
     }
     if (c.n_products >= c.n_steps) {
@@ -401,12 +412,16 @@ __device__ void decide(Ctl &c, double ty, double tx, RunState *st, bool writer) 
     c.alpha = (c.mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[t + 1] : (tx <= c.n_occ ? 1 : -1);
 }
 
-// Reduce the X0 core-trace partials; pick the first branch.
-__global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__ x0_partials, int n,
-                                                      RunState *__restrict__ st) {
+// Reduce the X0 core-trace partials of every system (one workgroup each,
+// over the system's run of gather chunks); pick the first branch.
+__global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__ x0_partials,
+                                                      const int32_t *__restrict__ sys_chunk_ptr,
+                                                      RunState *__restrict__ st_all) {
+    RunState *st = st_all + blockIdx.x;
     if (st->done) return;
+    const int c0 = sys_chunk_ptr[blockIdx.x], c1 = sys_chunk_ptr[blockIdx.x + 1];
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) a += x0_partials[i];
+    for (int i = c0 + threadIdx.x; i < c1; i += kBlock) a += x0_partials[i];
     block_sum2(a, b);
     if (threadIdx.x == 0) {
         Ctl c = ctl_load(st);
@@ -617,23 +632,28 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
                                                         const PartDesc *__restrict__ parts,
                                                         float *__restrict__ buf0, float *__restrict__ buf1,
                                                         Op *__restrict__ sh0, Op *__restrict__ sh1,
-                                                        const RunState *__restrict__ st,
+                                                        const RunState *__restrict__ st_all,
                                                         double *__restrict__ diag_partials, int phase) {
     __shared__ uint4 lds[kLdsWords];
-    if (st->done || st->phase != phase) return;
     const TileDesc td = tiles[blockIdx.x];
     if (td.part < 0) return;                    // padding of a short XCD list
-    sp2_tile<Op>(td, parts[td.part], st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, diag_partials,
-                 lds);
+    const PartDesc pd = parts[td.part];
+    const RunState *st = st_all + pd.sys;       // each system runs, stops and branches on its own
+    if (st->done || st->phase != phase) return;
+    sp2_tile<Op>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, diag_partials, lds);
 }
 
 // a7 between per-product launches: reduce the product's trace partials in a
-// fixed order and take the decision.  One workgroup.
-__global__ __launch_bounds__(kBlock) void k_sp2_decide(const double *__restrict__ diag_partials, int n_diag,
-                                                       RunState *__restrict__ st, int phase) {
+// fixed order and take the decision.  One workgroup per system, over the
+// system's run of diagonal-tile slots.
+__global__ __launch_bounds__(kBlock) void k_sp2_decide(const double *__restrict__ diag_partials,
+                                                       const int32_t *__restrict__ sys_diag_ptr,
+                                                       RunState *__restrict__ st_all, int phase) {
+    RunState *st = st_all + blockIdx.x;
     if (st->done || st->phase != phase) return;
+    const int d0 = sys_diag_ptr[blockIdx.x], d1 = sys_diag_ptr[blockIdx.x + 1];
     double ty = 0.0, tx = 0.0;
-    for (int i = threadIdx.x; i < n_diag; i += kBlock) {
+    for (int i = d0 + threadIdx.x; i < d1; i += kBlock) {
         ty += diag_partials[2 * i];
         tx += diag_partials[2 * i + 1];
     }
@@ -762,12 +782,13 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const PartDesc *__restrict__
                                                     const int32_t *__restrict__ col_part,
                                                     const int32_t *__restrict__ col_local, int32_t n,
                                                     const float *__restrict__ buf0, const float *__restrict__ buf1,
-                                                    const RunState *__restrict__ st, float *__restrict__ P_val) {
-    if (st->status == GSP2_E_INVALID || st->status == GSP2_E_HIP) return;
+                                                    const RunState *__restrict__ st_all, float *__restrict__ P_val) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t j = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (j >= n) return;
     const PartDesc pd = parts[col_part[j]];
+    const RunState *st = st_all + pd.sys;
+    if (st->status == GSP2_E_INVALID || st->status == GSP2_E_HIP) return;
     const float *Xr = (st->result_buf ? buf1 : buf0) + pd.x_off + (int64_t)col_local[j] * pd.s_pad;
     const int32_t *perm = perm_arena + pd.perm_off;
     float *out = P_val + col_ptr[j];
@@ -1057,13 +1078,14 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     const T *hv = static_cast<const T *>(H.val);
     const dim3 blk(kBlock);
     if (ev) rec.add_event(ev->begin);
-    record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.gersh_partials);
-    record(rec, k_run_init, dim3(1), blk, dp.gersh_partials, dp.gersh_blocks, rp, dp.state);
+    const dim3 sys(dp.n_sys);
+    record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.row_bounds);
+    record(rec, k_run_init, sys, blk, dp.row_bounds, dp.sys_rows, dp.sys_row_ptr, rp, dp.sys_params, dp.state);
     const bool mixed = rp.precision != GSP2_PREC_FP32;
     uint16_t *sh0 = mixed ? static_cast<uint16_t *>(dp.shadow[0]) : nullptr;
     record(rec, k_gather_x0<T>, dim3(dp.n_chunks), blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx,
            dp.buf[0], sh0, dp.state, dp.x0_partials);
-    record(rec, k_run_start, dim3(1), blk, dp.x0_partials, dp.n_chunks, dp.state);
+    record(rec, k_run_start, sys, blk, dp.x0_partials, dp.sys_chunk_ptr, dp.state);
     if (ev) rec.add_event(ev->setup_end);
     const dim3 grid(dp.n_tiles);
     float *b0 = dp.buf[0], *b1 = dp.buf[1];
@@ -1099,7 +1121,7 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
             record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr,
                    (float *)nullptr, dp.state, dp.diag_partials, 0);
         if (ev) rec.add_event(ev->step[2 * it + 1]);
-        record(rec, k_sp2_decide, dim3(1), blk, dp.diag_partials, dp.n_diag, dp.state, 0);
+        record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 0);
     }
     for (int r = 0; r < rp.refine; ++r) {
         const int slot = rp.n_steps + r;
@@ -1107,7 +1129,7 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
         record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr, (float *)nullptr,
                dp.state, dp.diag_partials, 1);
         if (ev) rec.add_event(ev->step[2 * slot + 1]);
-        record(rec, k_sp2_decide, dim3(1), blk, dp.diag_partials, dp.n_diag, dp.state, 1);
+        record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 1);
     }
     if (ev) rec.add_event(ev->sp2_end);
     const int wpb = kBlock / kWave;
@@ -1124,8 +1146,9 @@ hipError_t backward_typed(const DevicePlan &dp, const gsp2_csr &H, const RunPara
     rec.stream = s;
     const T *hv = static_cast<const T *>(H.val);
     const dim3 blk(kBlock), grid(dp.n_tiles), chunks(dp.n_chunks);
-    record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.gersh_partials);
-    record(rec, k_run_init, dim3(1), blk, dp.gersh_partials, dp.gersh_blocks, rp, dp.state);
+    record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.row_bounds);
+    record(rec, k_run_init, dim3(dp.n_sys), blk, dp.row_bounds, dp.sys_rows, dp.sys_row_ptr, rp, dp.sys_params,
+           dp.state);
     record(rec, k_gather_x0<T>, chunks, blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx, bb.ckpt[0],
            (uint16_t *)nullptr, dp.state, dp.x0_partials);
     const int k = bb.seg;

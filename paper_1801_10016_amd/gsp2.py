@@ -32,21 +32,23 @@ class gsp2_csr(C.Structure):
 
 
 class gsp2_plan_options(C.Structure):
-    _fields_ = [("tile", C.c_int32), ("reserved", C.c_int32 * 7)]
+    _fields_ = [("tile", C.c_int32), ("n_systems", C.c_int32), ("part_system", C.POINTER(C.c_int32)),
+                ("reserved", C.c_int32 * 4)]
 
 
 class gsp2_plan_info(C.Structure):
     _fields_ = [("n", C.c_int32), ("n_parts", C.c_int32), ("max_s", C.c_int32), ("min_s", C.c_int32),
                 ("nnz_graph", C.c_int64), ("nnz_P", C.c_int64), ("sum_s", C.c_int64), ("sum_s3", C.c_double),
                 ("tile", C.c_int32), ("n_tiles", C.c_int32), ("workspace_bytes", C.c_int64),
-                ("plan_ms", C.c_double)]
+                ("plan_ms", C.c_double), ("n_systems", C.c_int32), ("pad_", C.c_int32)]
 
 
 class gsp2_run_options(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("alpha_mode", C.c_int32), ("alpha_seq", C.POINTER(C.c_int8)),
                 ("n_alpha", C.c_int32), ("stop_rule", C.c_int32), ("trace_tol", C.c_double),
                 ("timing", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
-                ("persistent", C.c_int32)]
+                ("persistent", C.c_int32), ("n_occ_system", C.POINTER(C.c_double)),
+                ("alpha_seq_system", C.POINTER(C.c_int8)), ("n_alpha_system", C.POINTER(C.c_int32))]
 
 
 class gsp2_run_info(C.Structure):
@@ -184,6 +186,7 @@ class Plan:
     def __init__(self, handle: int):
         self.handle = C.c_void_p(handle)
         self.nnz_P = None
+        self.n_systems = 1
 
     def close(self):
         if self.handle and self.handle.value:
@@ -203,17 +206,29 @@ class Plan:
         self.close()
 
 
-def gsp2_plan_create(P_prev: DeviceCSR, tau: float, part, n_parts: int, tile: int = 0, stream=None) -> Plan:
+def gsp2_plan_create(P_prev: DeviceCSR, tau: float, part, n_parts: int, tile: int = 0, stream=None,
+                     part_system=None) -> Plan:
+    """part_system (n_parts ids) batches independent systems in one plan."""
     part = np.ascontiguousarray(part, dtype=np.int32)
     if part.shape != (P_prev.n,):
         raise ValueError("part must have one entry per vertex")
     c = P_prev.as_c()
     opt = gsp2_plan_options(tile)
+    keep = None
+    if part_system is not None:
+        keep = np.ascontiguousarray(part_system, dtype=np.int32)
+        if keep.shape != (n_parts,):
+            raise ValueError("part_system must have one entry per part")
+        opt.n_systems = int(keep.max()) + 1 if keep.size else 0
+        opt.part_system = _i32(keep)
     out = _PLAN()
     _check(load().gsp2_plan_create(C.byref(c), float(tau), _i32(part), int(n_parts), C.byref(opt),
                                    C.c_void_p(_stream_handle(stream)), C.byref(out)))
+    del keep
     plan = Plan(out.value)
-    plan.nnz_P = gsp2_plan_query(plan)[0]["nnz_P"]
+    info = gsp2_plan_query(plan)[0]
+    plan.nnz_P = info["nnz_P"]
+    plan.n_systems = info["n_systems"]
     return plan
 
 
@@ -248,7 +263,10 @@ def gsp2_plan_set_stream(plan: Plan, stream=None):
 
 
 def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5, timing=False,
-                     precision="fp32", refine=0, persistent=False):
+                     precision="fp32", refine=0, persistent=False, n_occ_system=None):
+    """Options struct and the arrays it points to (keep them alive for the
+    call).  alpha_seq: one sequence, or (batched plans) a list of sequences,
+    one per system; n_occ_system: occupations of a batched plan's systems."""
     o = gsp2_run_options_default()
     o.persistent = 1 if persistent else 0
     o.max_iter = int(max_iter)
@@ -257,12 +275,30 @@ def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5,
     o.refine = int(refine)
     o.stop_rule = 1 if stop_rule else 0
     o.trace_tol = float(trace_tol)
-    keep = None
+    keep = []
     if alpha_seq is not None:
-        keep = np.ascontiguousarray(alpha_seq, dtype=np.int8)
         o.alpha_mode = GSP2_ALPHA_REPLAY
-        o.n_alpha = int(keep.size)
-        o.alpha_seq = keep.ctypes.data_as(C.POINTER(C.c_int8))
+        if len(alpha_seq) and np.ndim(alpha_seq[0]) == 1:       # one sequence per system
+            rows = np.zeros((len(alpha_seq), GSP2_MAX_ITER), dtype=np.int8)
+            lens = np.zeros(len(alpha_seq), dtype=np.int32)
+            for y, a in enumerate(alpha_seq):
+                a = np.asarray(a, dtype=np.int8)
+                if a.size > GSP2_MAX_ITER:
+                    raise ValueError("alpha sequence longer than GSP2_MAX_ITER")
+                rows[y, :a.size] = a
+                lens[y] = a.size
+            keep += [rows, lens]
+            o.alpha_seq_system = rows.ctypes.data_as(C.POINTER(C.c_int8))
+            o.n_alpha_system = _i32(lens)
+        else:
+            seq = np.ascontiguousarray(alpha_seq, dtype=np.int8)
+            keep.append(seq)
+            o.n_alpha = int(seq.size)
+            o.alpha_seq = seq.ctypes.data_as(C.POINTER(C.c_int8))
+    if n_occ_system is not None:
+        occ = np.ascontiguousarray(n_occ_system, dtype=np.float64)
+        keep.append(occ)
+        o.n_occ_system = occ.ctypes.data_as(C.POINTER(C.c_double))
     return o, keep
 
 
@@ -279,40 +315,48 @@ def run_info_dict(info: gsp2_run_info) -> dict:
     }
 
 
-def gsp2_density(plan: Plan, H: DeviceCSR, n_occ: float, P_val, max_iter=60, alpha_seq=None,
+def gsp2_density(plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=None,
                  stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False,
                  precision="fp32", refine=0, persistent=False):
     """Enqueue one density matrix into P_val (torch float32 on the GPU, nnz_P
-    entries).  With want_info the call waits and returns the run's info dict;
-    with check a failing status raises Gsp2Error."""
+    entries).  With want_info the call waits and returns the run's info dict
+    (a list of them, one per system, for a batched plan); with check a
+    failing status raises Gsp2Error.  For a batched plan n_occ lists every
+    system's occupation, and alpha_seq, if given, one sequence per system."""
     import torch
     if P_val.dtype != torch.float32 or not P_val.is_cuda or not P_val.is_contiguous():
         raise ValueError("P_val must be a contiguous float32 GPU tensor")
     if P_val.numel() < plan.nnz_P:
         raise ValueError(f"P_val holds {P_val.numel()} values, the plan needs {plan.nnz_P}")
+    batched = plan.n_systems > 1
+    if batched and np.ndim(n_occ) != 1:
+        raise ValueError("a batched plan takes one n_occ per system")
     c = H.as_c()
-    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine, persistent)
-    info = gsp2_run_info() if want_info else None
-    st = load().gsp2_density(plan.handle, C.byref(c), float(n_occ), C.byref(o), C.c_void_p(P_val.data_ptr()),
-                             C.byref(info) if info is not None else None)
+    o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine, persistent,
+                               n_occ_system=n_occ if batched else None)
+    info = (gsp2_run_info * plan.n_systems)() if want_info else None
+    st = load().gsp2_density(plan.handle, C.byref(c), 0.0 if batched else float(n_occ), C.byref(o),
+                             C.c_void_p(P_val.data_ptr()), info)
     del keep
     msg = load().gsp2_last_error().decode()
     if check and st != GSP2_OK:
         raise Gsp2Error(st, msg)
     if info is None:
         return {"status": st}
-    d = run_info_dict(info)
-    d["call_status"] = st
-    d["message"] = msg
-    return d
+    ds = [run_info_dict(x) for x in info]
+    for d in ds:
+        d["call_status"] = st
+        d["message"] = msg
+    return ds if batched else ds[0]
 
 
-def gsp2_run_status(plan: Plan) -> dict:
-    info = gsp2_run_info()
-    st = load().gsp2_run_status(plan.handle, C.byref(info))
-    d = run_info_dict(info)
-    d["call_status"] = st
-    return d
+def gsp2_run_status(plan: Plan):
+    info = (gsp2_run_info * plan.n_systems)()
+    st = load().gsp2_run_status(plan.handle, info)
+    ds = [run_info_dict(x) for x in info]
+    for d in ds:
+        d["call_status"] = st
+    return ds if plan.n_systems > 1 else ds[0]
 
 
 def gsp2_run_timing(plan: Plan) -> dict:

@@ -114,3 +114,72 @@ def test_core_halo_host_isolated_vertices_and_self_loops():
     sub_ptr, sub_idx, core = g.gsp2_core_halo_host(ptr, col, part, 3)
     assert np.diff(sub_ptr).tolist() == [2, 2, 1]
     assert sub_idx.tolist() == [0, 1, 2, 3, 4]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """sizeof and offsetof of every ABI struct, compiled from the header by the
+    host C compiler, equal the ctypes layouts of the binding."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = [binding.gsp2_csr, binding.gsp2_plan_options, binding.gsp2_plan_info, binding.gsp2_run_options,
+               binding.gsp2_run_info, binding.gsp2_timing, binding.gsp2_backward_info]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsp2.h"', "int main(void) {"]
+    for cls in structs:
+        name = cls.__name__
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                       text=True).stdout.splitlines())
+    for cls in structs:
+        name = cls.__name__
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
+
+
+def _plan_create_host(part, n_parts, n_systems, part_system):
+    """gsp2_plan_create with host arrays: only its argument checks, which run
+    before any HIP call, are reached when the arguments are invalid."""
+    import ctypes as C
+    n = part.size
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    c = binding.gsp2_csr(n, 0, row_ptr.ctypes.data, None, None, binding.GSP2_F64)
+    opt = binding.gsp2_plan_options(0)
+    keep = None
+    if part_system is not None:
+        keep = np.ascontiguousarray(part_system, dtype=np.int32)
+        opt.part_system = keep.ctypes.data_as(C.POINTER(C.c_int32))
+    opt.n_systems = n_systems
+    out = C.c_void_p()
+    part = np.ascontiguousarray(part, dtype=np.int32)
+    st = g.load().gsp2_plan_create(C.byref(c), 1e-3, part.ctypes.data_as(C.POINTER(C.c_int32)), n_parts,
+                                   C.byref(opt), None, C.byref(out))
+    return st, g.load().gsp2_last_error().decode(), out.value
+
+
+@pytest.mark.parametrize("n_systems,part_system,message", [
+    (3, [0, 1], "more systems than parts"),
+    (2, None, "null part_system"),
+    (2, [0, 2], "part_system out of range"),
+    (2, [1, 1], "system 0 has no part"),
+    (-1, [0, 0], "n_systems must be >= 0"),
+])
+def test_batched_plan_arguments_are_checked(n_systems, part_system, message):
+    part = np.array([0, 0, 1, 1], dtype=np.int32)
+    st, msg, handle = _plan_create_host(part, 2, n_systems, part_system)
+    assert st == binding.GSP2_E_INVALID and message in msg and handle is None
+
+
+def test_run_option_defaults_leave_batch_fields_empty():
+    o = g.gsp2_run_options_default()
+    assert not o.n_occ_system and not o.alpha_seq_system and not o.n_alpha_system

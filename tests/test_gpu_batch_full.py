@@ -1,0 +1,160 @@
+"""The uneven batch at full size: 16 independent water systems of 504 to
+7,823 molecules (297,456 orbitals, 1,981 parts, sub-problems of about 900 to
+1,900 orbitals), each one molecular-dynamics step on (0.05 Angstrom
+displacements, graph repartitioned), tau = 1e-4, all in one batched plan.
+
+No FP64 oracle covers the whole batch (tens of CPU-hours), so:
+* every system reaches its occupation and stops on the idempotency rule;
+* the smallest system (3,024 orbitals, 20 parts) against the FP64 oracle run
+  on it alone: <= 1e-5 relative Frobenius with FP32 products, the
+  mixed-precision bound with FP16 products and two FP32 refinement products;
+* the smallest and the largest system of the batch equal, bit for bit, a
+  plan that holds that system alone (so the oracle comparison above carries
+  over to the batch, and batching changes no system's arithmetic)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+from synth.batch import make_batch
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+MIXED_TOL_FP16 = 3e-3
+
+
+def tie_band(n):
+    return 1e-4 * max(1.0, n / 1000.0)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import time
+    import paper_1801_10016_amd as g
+    t0 = time.perf_counter()
+    b = make_batch()
+    print(f"batch inputs: {len(b.steps)} systems, N={b.H.shape[0]}, parts={b.n_parts} "
+          f"({time.perf_counter() - t0:.1f} s)", flush=True)
+    Hd = g.csr_to_device(b.H)
+    plan = g.gsp2_plan_create(g.csr_to_device(b.P_prev), b.tau, b.part, b.n_parts, part_system=b.part_system)
+    info, _, ss = g.gsp2_plan_query(plan)
+    col_ptr, _ = g.gsp2_plan_pattern(plan)
+    P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
+    print(f"plan: s in [{info['min_s']}, {info['max_s']}], {info['n_tiles']} tiles, "
+          f"workspace {info['workspace_bytes'] / 2**30:.1f} GiB, {info['plan_ms']:.0f} ms", flush=True)
+    out = {"b": b, "g": g, "Hd": Hd, "plan": plan, "P_val": P_val, "col_ptr": col_ptr, "cache": {}}
+    yield out
+    plan.close()
+
+
+def _run(c, **kw):
+    key = tuple(sorted(kw.items()))
+    if key not in c["cache"]:
+        runs = c["g"].gsp2_density(c["plan"], c["Hd"], c["b"].n_occ, c["P_val"], **kw)
+        b = c["b"]
+        vals = [c["P_val"][int(c["col_ptr"][b.offs[i]]):int(c["col_ptr"][b.offs[i + 1]])].cpu().numpy()
+                for i in (_smallest(b), _largest(b))]
+        c["cache"][key] = (runs, dict(zip((_smallest(b), _largest(b)), vals)))
+    return c["cache"][key]
+
+
+def _smallest(b):
+    return int(np.argmin(np.diff(b.offs)))
+
+
+def _largest(b):
+    return int(np.argmax(np.diff(b.offs)))
+
+
+def _alone(c, i, **kw):
+    """System i of the batch in a plan of its own: P values and run info."""
+    import torch
+    g, st, b = c["g"], c["b"].steps[i], c["b"]
+    with g.gsp2_plan_create(g.csr_to_device(st.P_prev), b.tau, st.part, st.n_parts) as plan:
+        P_val = torch.empty(plan.nnz_P, dtype=torch.float32, device="cuda")
+        run = g.gsp2_density(plan, g.csr_to_device(st.system.H.tocsr().sorted_indices()), st.system.n_occ,
+                             P_val, **kw)
+        col_ptr, row_idx = g.gsp2_plan_pattern(plan)
+        vals = P_val.cpu().numpy()
+    return vals, run, col_ptr, row_idx
+
+
+def _pattern(c, i):
+    """CSC pattern of system i's P (the batch's columns of that system, shifted)."""
+    g, st, b = c["g"], c["b"].steps[i], c["b"]
+    with g.gsp2_plan_create(g.csr_to_device(st.P_prev), b.tau, st.part, st.n_parts) as plan:
+        return g.gsp2_plan_pattern(plan)
+
+
+def _oracle_smallest(c):
+    if "oracle" not in c["cache"]:
+        b = c["b"]
+        st = b.steps[_smallest(b)]
+        c["cache"]["oracle"] = oracle.gsp2(st.system.H, st.P_prev, b.tau, st.part, st.n_parts, st.system.n_occ)
+    return c["cache"]["oracle"]
+
+
+def test_every_system_converges(batch):
+    runs, _ = _run(batch)
+    b = batch["b"]
+    for i, (st, run) in enumerate(zip(b.steps, runs)):
+        print(f"system {i}: N={st.system.n} parts={st.n_parts} products={run['n_products']} "
+              f"|Tr P - N_occ|={abs(run['trace'] - st.system.n_occ):.2e} e={run['idempotency']:.2e}", flush=True)
+        assert run["status"] == 0, (i, run)
+        assert abs(run["trace"] - st.system.n_occ) <= 0.5
+        assert abs(run["idempotency"]) <= 1.0
+
+
+@pytest.mark.parametrize("which", ["smallest", "largest"])
+def test_batch_equals_plan_of_one_system(batch, which):
+    b = batch["b"]
+    i = _smallest(b) if which == "smallest" else _largest(b)
+    runs, vals = _run(batch)
+    vals1, run1, _, _ = _alone(batch, i)
+    print(f"{which} system {i}: N={b.steps[i].system.n}, batch products {runs[i]['n_products']}, "
+          f"alone {run1['n_products']}", flush=True)
+    assert runs[i]["alpha"] == run1["alpha"] and runs[i]["traces"] == run1["traces"]
+    assert np.array_equal(vals[i], vals1)
+
+
+def test_smallest_system_against_oracle(batch):
+    from tests._gpu import rel_fro
+    b = batch["b"]
+    i = _smallest(b)
+    st = b.steps[i]
+    ref = _oracle_smallest(batch)
+    runs, vals = _run(batch)
+    ga, oa = runs[i]["alpha"], ref.sp2.alphas
+    diff = [t for t in range(min(len(ga), len(oa))) if ga[t] != oa[t]]
+    v = vals[i]
+    if diff:
+        gap = abs(ref.sp2.traces[diff[0]] - st.system.n_occ)
+        print(f"  branch sequences part at product {diff[0]}: |Tr - N_occ| = {gap:.2e}", flush=True)
+        assert gap <= tie_band(st.system.n)
+        v, _, _, _ = _alone(batch, i, alpha_seq=oa, trace_tol=1e9)
+    col_ptr, row_idx = _pattern(batch, i)
+    n = st.system.n
+    P = sp.csc_matrix((v.astype(np.float64), row_idx, col_ptr), shape=(n, n))
+    err = rel_fro(P, ref.csc())
+    print(f"smallest system: N={n} parts={st.n_parts} gpu products {runs[i]['n_products']} "
+          f"oracle {ref.sp2.n_products}; rel_err={err:.2e}", flush=True)
+    assert err <= TOL
+
+
+def test_mixed_precision_batch(batch):
+    from tests._gpu import rel_fro
+    b = batch["b"]
+    runs, vals = _run(batch, precision="fp16", refine=2)
+    for i, (st, run) in enumerate(zip(b.steps, runs)):
+        assert run["status"] == 0 and run["n_refine"] == 2, (i, run)
+    i = _smallest(b)
+    col_ptr, row_idx = _pattern(batch, i)
+    n = b.steps[i].system.n
+    P = sp.csc_matrix((vals[i].astype(np.float64), row_idx, col_ptr), shape=(n, n))
+    err = rel_fro(P, _oracle_smallest(batch).csc())
+    print(f"fp16 + 2 FP32 products, smallest system: rel_err={err:.2e}", flush=True)
+    assert err <= MIXED_TOL_FP16

@@ -177,6 +177,28 @@ def test_mixed_precision_trace_mode(precision):
         print(f"{precision} refine={refine}: products={run['n_products']} rel_err={out[refine]:.2e} "
               f"|Tr P - N_occ|={abs(run['trace'] - s.n_occ):.2e}", flush=True)
     assert out[0] <= MIXED_TOL[precision]
+    assert out[2] <= 1.05 * out[0]           # a purification pair cannot undo the subspace error, nor add to it
+
+
+def test_refinement_products_do_not_drift():
+    # 24 molecules, 3 parts: after the FP16 stop the trace sits above n_occ, so
+    # branches taken by the trace rule would square towards one side only;
+    # alternating pairs keep every eigenvalue at the nearer of 0 and 1
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(24, 3)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 3, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ)
+    err = {}
+    for refine in (0, 2, 8):
+        P, run, _, _, _ = run_gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, precision="fp16", refine=refine)
+        assert run["status"] == 0 and run["n_refine"] == refine
+        err[refine] = rel_fro(P, ref.csc())
+        n = run["n_alpha"]
+        print(f"fp16 refine={refine}: rel_err={err[refine]:.2e} branches after the stop "
+              f"{run['alpha'][n - refine:]} |Tr P - N_occ|={abs(run['trace'] - s.n_occ):.2e}", flush=True)
+        assert run["alpha"][n - refine:] == [-1, 1] * (refine // 2)
+    assert err[8] <= 1.05 * err[2] and err[2] <= MIXED_TOL["fp16"]
 
 
 def test_fp32_refinement_products():
