@@ -31,8 +31,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
-PEAK_MFMA_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0}     # dense, per operand format
-DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16"}
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp16x3": 2500.0}   # dense, per operand format
+MFMA_PRODUCTS = {"fp32": 1, "fp16": 1, "bf16": 1, "fp16x3": 3}   # matrix-core products per SP2 product
+DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp16x3": "f16x3"}
 PEAK_HBM_GBS = 8000.0
 METRIC = "ms per density matrix P + batched-GEMM TFLOP/s (frac. of MFMA peak) at 10k atoms"
 
@@ -61,9 +62,9 @@ def parse():
     ap.add_argument("--save-state", help="write the thresholded graph and product count to this .npz")
     ap.add_argument("--load-state", help="reuse a graph and product count saved by --save-state "
                     "(skips the previous-P computation and the first, stop-finding run)")
-    ap.add_argument("--precision", choices=["fp32", "fp16", "bf16"], default=None,
+    ap.add_argument("--precision", choices=["fp32", "fp16", "bf16", "fp16x3"], default=None,
                     help="operand precision of the timed products (default: fp32, or fp16 for batch16)")
-    ap.add_argument("--compare-precisions", default="fp16,bf16",
+    ap.add_argument("--compare-precisions", default="fp16,bf16,fp16x3",
                     help="after the FP32 timing, also time these operand precisions (empty: none)")
     ap.add_argument("--compare-steps", type=int, default=3)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -235,7 +236,8 @@ def bench_batch(args, g, torch):
         per_system.append({"n_mol": st.system.n_mol, "n_orbitals": st.system.n, "n_parts": st.n_parts,
                            "n_products": r["n_products"], "n_refine": r["n_refine"],
                            "product_kernels_ms_until_done": round(done, 3),
-                           "trace_minus_nocc": r["trace"] - st.system.n_occ})
+                           "trace_minus_nocc": r["trace"] - st.system.n_occ,
+                           "idempotency_e": r["errors"]})
     alone_ms = None
     if not args.no_alone:
         alone_ms = []
@@ -405,7 +407,7 @@ def main():
     syrk_flops = float(np.sum(s * s * (s + 1.0)))        # distinct entries s(s+1)/2, 2s flops each
     gemm_flops = float(np.sum(2.0 * s ** 3))
     avg_prod_ms = statistics.fmean(product_ms)
-    achieved = syrk_flops / (avg_prod_ms * 1e-3) / 1e12
+    achieved = MFMA_PRODUCTS[args.precision] * syrk_flops / (avg_prod_ms * 1e-3) / 1e12
     peak = PEAK_MFMA_TFLOPS[args.precision]
     ms_per_step = wall * 1e3 / args.steps
     sp2_med = statistics.median(sp2)
@@ -429,10 +431,12 @@ def main():
             tm = g.gsp2_run_timing(plan)
         diff = float(torch.linalg.vector_norm(P_mp.double() - P_ref) / torch.linalg.vector_norm(P_ref))
         avg = statistics.fmean(tm["product_ms"])
+        hw = MFMA_PRODUCTS[prec] * syrk_flops
         compare[prec] = {"ms_per_P": round(ms, 3), "n_products": n_mp,
                          "product_kernel_ms": round(avg, 4),
                          "tflops": round(syrk_flops / (avg * 1e-3) / 1e12, 2),
-                         "frac_of_peak": round(syrk_flops / (avg * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[prec], 4),
+                         "mfma_products_per_product": MFMA_PRODUCTS[prec],
+                         "frac_of_peak": round(hw / (avg * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[prec], 4),
                          "rel_diff_vs_fp32_P": diff, "trace_minus_nocc": r0["trace"] - n_occ}
         log(f"{prec}: {ms:.1f} ms/P, {n_mp} products, |P - P_fp32|/|P_fp32| = {diff:.2e}")
         del P_mp
@@ -473,7 +477,7 @@ def main():
             "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": counter_traffic(args.precision),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "flops_per_launch": syrk_flops, "avg_launch_ms": round(avg_prod_ms, 4),
+            "flops_per_launch": MFMA_PRODUCTS[args.precision] * syrk_flops, "avg_launch_ms": round(avg_prod_ms, 4),
             "flops_convention": "symmetric product: sum_k s_k^2 (s_k + 1) per launch (one launch = one product)",
         },
         "phase_ms": {"setup": round(statistics.median(setup), 3), "sp2": round(sp2_med, 3),

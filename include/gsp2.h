@@ -57,7 +57,11 @@ typedef enum {
 typedef enum {
     GSP2_PREC_FP32 = 0,        /* FP32 operands (v_mfma_f32_32x32x2_f32) */
     GSP2_PREC_FP16 = 1,        /* FP16 operands (v_mfma_f32_32x32x16_f16) */
-    GSP2_PREC_BF16 = 2         /* BF16 operands (v_mfma_f32_32x32x16_bf16) */
+    GSP2_PREC_BF16 = 2,        /* BF16 operands (v_mfma_f32_32x32x16_bf16) */
+    GSP2_PREC_FP16X3 = 3       /* split FP16 operands: X = A + 2^-11 B with A = fp16(X) and
+                                  B = fp16(2^11 (X - A)); X^2 as 2^-11 (A B + B A) + A A, three
+                                  FP16 products accumulated in FP32, about as accurate as FP32
+                                  products (the dropped B B term is 2^-22 relative) */
 } gsp2_precision;
 
 /* Sparse matrix in CSR form.  All four arrays are device pointers. */
@@ -307,6 +311,44 @@ gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info);
 
 /* Release the plan and its device memory (waits for its stream).  NULL is a no-op. */
 void gsp2_plan_destroy(gsp2_plan plan);
+
+/* Graph G_tau of a plan (the threshold of P_prev), as the directed adjacency
+ * the GPU built: row v lists the columns u != v with |P_prev[v,u]| > tau, in
+ * stored order.  adj_ptr: host, n+1 int64; adj_col: host, nnz_graph int32,
+ * nullable (pass NULL first to size it from adj_ptr[n]).  Errors: GSP2_E_INVALID. */
+gsp2_status gsp2_plan_graph(gsp2_plan plan, int64_t *adj_ptr, int32_t *adj_col);
+
+/* Options of gsp2_partition_anneal.  Zero-initialised means defaults. */
+typedef struct {
+    int32_t sweeps;            /* passes over all vertices; 0 = 40 */
+    int32_t pad_;
+    double t0;                 /* starting temperature in units of 3 (C / n_parts)^(2/3), the
+                                  change of C when a part of mean cost grows by one vertex;
+                                  0 = 2; negative = no uphill moves */
+    double cooling;            /* temperature factor per sweep, in (0, 1]; 0 = 0.85 */
+    uint64_t seed;             /* seed of the move generator */
+    int32_t reserved[4];
+} gsp2_anneal_options;
+
+/*
+ * Host-only (no GPU needed): refine a partition to lower the cost of eq. (4),
+ * C = sum_k (c_k + h_k)^3, by simulated annealing, the alternative to METIS
+ * that the paper's graph-theory section evaluates.  Single-vertex moves of
+ * boundary vertices to a neighbouring part, the exact change of C from the
+ * neighbour counts, Metropolis acceptance with a geometric temperature
+ * schedule; no part is emptied (n_parts stays fixed).  The best partition
+ * seen is written back.  Deterministic for a given seed.
+ *  adj_ptr, adj_col  host CSR of the graph (the union of both orientations
+ *                    is used; self loops are ignored), as gsp2_plan_graph gives.
+ *  part              host, n int32 ids in [0, n_parts), every part non-empty;
+ *                    in: the starting partition, out: the refined one.
+ *  opt               nullable (defaults).
+ *  cost_before, cost_after  nullable: C of the partition given and returned.
+ * Errors: GSP2_E_INVALID.
+ */
+gsp2_status gsp2_partition_anneal(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, int32_t n_parts,
+                                  int32_t *part, const gsp2_anneal_options *opt, int64_t *cost_before,
+                                  int64_t *cost_after);
 
 /*
  * Host-only planning step (no GPU needed): core and one-hop halo of every

@@ -73,11 +73,10 @@ void upload(T *dst, const std::vector<T> &src, hipStream_t s, const char *what) 
     check_hip(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s), what);
 }
 
-// Core and one-hop halo of every part (host).  adj: directed CSR; the union
-// of both orientations is the undirected graph; self loops ignored.
-void plan_core_halo(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, const int32_t *part,
-                    int32_t n_parts, std::vector<int64_t> &sub_ptr, std::vector<int32_t> &sub_idx,
-                    std::vector<int32_t> &core_count) {
+// Checks of a host graph (directed CSR) and a partition of its vertices;
+// returns the core count of every part.
+std::vector<int32_t> check_graph_and_parts(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col,
+                                           const int32_t *part, int32_t n_parts) {
     if (n < 1) fail(GSP2_E_INVALID, "n must be >= 1");
     if (n_parts < 1) fail(GSP2_E_INVALID, "n_parts must be >= 1");
     if (!adj_ptr || !part) fail(GSP2_E_INVALID, "null pointer");
@@ -88,7 +87,7 @@ void plan_core_halo(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, c
         if (adj_ptr[v + 1] < adj_ptr[v]) fail(GSP2_E_INVALID, "adjacency row pointer not monotone");
     for (int64_t e = 0; e < nnz; ++e)
         if (adj_col[e] < 0 || adj_col[e] >= n) fail(GSP2_E_INVALID, "adjacency column out of range");
-    core_count.assign(n_parts, 0);
+    std::vector<int32_t> core_count(n_parts, 0);
     for (int32_t v = 0; v < n; ++v) {
         if (part[v] < 0 || part[v] >= n_parts)
             fail(GSP2_E_INVALID, "part id out of range at vertex " + std::to_string(v));
@@ -96,6 +95,16 @@ void plan_core_halo(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, c
     }
     for (int32_t k = 0; k < n_parts; ++k)
         if (core_count[k] == 0) fail(GSP2_E_INVALID, "part " + std::to_string(k) + " is empty");
+    return core_count;
+}
+
+// Core and one-hop halo of every part (host).  adj: directed CSR; the union
+// of both orientations is the undirected graph; self loops ignored.
+void plan_core_halo(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, const int32_t *part,
+                    int32_t n_parts, std::vector<int64_t> &sub_ptr, std::vector<int32_t> &sub_idx,
+                    std::vector<int32_t> &core_count) {
+    core_count = check_graph_and_parts(n, adj_ptr, adj_col, part, n_parts);
+    const int64_t nnz = adj_ptr[n];
     // cores, ascending
     std::vector<int64_t> core_ptr(n_parts + 1, 0);
     for (int32_t k = 0; k < n_parts; ++k) core_ptr[k + 1] = core_ptr[k] + core_count[k];
@@ -170,6 +179,8 @@ struct gsp2_plan_s {
     int64_t nnz_graph = 0;
     double plan_ms = 0.0;
     std::vector<int32_t> part;
+    std::vector<int64_t> adj_ptr;         // G_tau as built (directed, host)
+    std::vector<int32_t> adj_col;
     std::vector<int64_t> sub_ptr;
     std::vector<int32_t> sub_idx, core_count;
     std::vector<PartDesc> desc;
@@ -386,8 +397,8 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             }
         }
         plan->nnz_graph = (int64_t)adj_col.size();
-        std::vector<int64_t>().swap(adj_ptr);
-        std::vector<int32_t>().swap(adj_col);
+        plan->adj_ptr.swap(adj_ptr);
+        plan->adj_col.swap(adj_col);
 
         // descriptors, LPT tile list, gather chunks, P pattern
         const int T = kTile;
@@ -650,6 +661,33 @@ gsp2_status gsp2_plan_part_index(gsp2_plan plan, int32_t k, int32_t *idx) {
     });
 }
 
+gsp2_status gsp2_plan_graph(gsp2_plan plan, int64_t *adj_ptr, int32_t *adj_col) {
+    return guarded([&] {
+        if (!plan) fail(GSP2_E_INVALID, "null plan");
+        if (!adj_ptr) fail(GSP2_E_INVALID, "null adj_ptr");
+        std::copy(plan->adj_ptr.begin(), plan->adj_ptr.end(), adj_ptr);
+        if (adj_col) std::copy(plan->adj_col.begin(), plan->adj_col.end(), adj_col);
+    });
+}
+
+gsp2_status gsp2_partition_anneal(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, int32_t n_parts,
+                                  int32_t *part, const gsp2_anneal_options *opt, int64_t *cost_before,
+                                  int64_t *cost_after) {
+    return guarded([&] {
+        check_graph_and_parts(n, adj_ptr, adj_col, part, n_parts);
+        const int32_t sweeps = (opt && opt->sweeps > 0) ? opt->sweeps : 40;
+        const double t0 = (opt && opt->t0 != 0.0) ? opt->t0 : 2.0;
+        const double cooling = (opt && opt->cooling != 0.0) ? opt->cooling : 0.85;
+        if (opt && opt->sweeps < 0) fail(GSP2_E_INVALID, "sweeps must be >= 0");
+        if (!(cooling > 0.0 && cooling <= 1.0)) fail(GSP2_E_INVALID, "cooling must be in (0, 1]");
+        if (!std::isfinite(t0)) fail(GSP2_E_INVALID, "t0 must be finite");
+        const AnnealResult r = anneal_partition(n, adj_ptr, adj_col, n_parts, part, sweeps, std::max(t0, 0.0),
+                                                cooling, opt ? opt->seed : 0);
+        if (cost_before) *cost_before = r.cost_before;
+        if (cost_after) *cost_after = r.cost_after;
+    });
+}
+
 gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream) {
     return guarded([&] {
         if (!plan) fail(GSP2_E_INVALID, "null plan");
@@ -733,7 +771,8 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         rp.trace_tol = o.trace_tol;
         rp.mode = o.alpha_mode;
         rp.stop_rule = o.stop_rule ? 1 : 0;
-        if (o.precision != GSP2_PREC_FP32 && o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16)
+        if (o.precision != GSP2_PREC_FP32 && o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16 &&
+            o.precision != GSP2_PREC_FP16X3)
             fail(GSP2_E_INVALID, "bad precision");
         if (o.refine < 0 || o.refine > 8) fail(GSP2_E_INVALID, "refine must be in 0..8");
         rp.precision = o.precision;
@@ -753,8 +792,10 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         plan->wait_sys_staging();
         std::memset(plan->h_sys, 0, sizeof(SysParams) * (size_t)n_sys);
         // the stop rule's floor max(1, n u), u the unit roundoff of the product operands
-        const double u = o.precision == GSP2_PREC_FP16 ? std::ldexp(1.0, -11)
-                         : o.precision == GSP2_PREC_BF16 ? std::ldexp(1.0, -8) : std::ldexp(1.0, -24);
+        const double u = o.precision == GSP2_PREC_FP16     ? std::ldexp(1.0, -11)
+                         : o.precision == GSP2_PREC_BF16   ? std::ldexp(1.0, -8)
+                         : o.precision == GSP2_PREC_FP16X3 ? std::ldexp(1.0, -22)
+                                                           : std::ldexp(1.0, -24);
         if (o.alpha_mode == GSP2_ALPHA_REPLAY) {
             if (!(o.trace_tol >= 0.0)) fail(GSP2_E_INVALID, "trace_tol must be >= 0");
         } else if (o.alpha_mode == GSP2_ALPHA_TRACE) {
@@ -792,6 +833,10 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
             // 16-bit operand copies of both X buffers, allocated on the first mixed-precision run
             plan->dp.shadow[0] = plan->alloc<uint16_t>(plan->arena_floats, "16-bit X copy 0");
             plan->dp.shadow[1] = plan->alloc<uint16_t>(plan->arena_floats, "16-bit X copy 1");
+        }
+        if (rp.precision == GSP2_PREC_FP16X3 && !plan->dp.shadow_lo[0]) {
+            plan->dp.shadow_lo[0] = plan->alloc<uint16_t>(plan->arena_floats, "FP16 low parts 0");
+            plan->dp.shadow_lo[1] = plan->alloc<uint16_t>(plan->arena_floats, "FP16 low parts 1");
         }
         GraphKey k;
         k.h_ptr = H->row_ptr; k.h_col = H->col; k.h_val = H->val; k.h_nnz = H->nnz; k.h_dtype = H->dtype;

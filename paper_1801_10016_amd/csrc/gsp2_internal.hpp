@@ -120,6 +120,7 @@ struct DevicePlan {
     int32_t n_sys;              // systems (1 unless batched)
     float *buf[2];
     void *shadow[2];            // 16-bit operand copies of the two X buffers (mixed precision)
+    void *shadow_lo[2];         // scaled FP16 low parts of the two X buffers (split FP16 products)
     const PartDesc *parts;
     const TileDesc *tiles;
     const RowChunk *chunks;
@@ -210,5 +211,13 @@ hipError_t launch_backward(const DevicePlan &dp, const gsp2_csr &H, const RunPar
                            int n, const float *dLdP, double *dLdH, const BackwardBuffers &bb, hipStream_t s);
 // Workgroups of the persistent product kernel that the device keeps resident.
 hipError_t persistent_grid(int precision, int *grid);
+
+// Simulated-annealing refinement of a partition for eq. (4) (partition.cpp).
+struct AnnealResult {
+    int64_t cost_before, cost_after;
+    int64_t moves;
+};
+AnnealResult anneal_partition(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, int32_t n_parts,
+                              int32_t *part, int32_t sweeps, double t0, double cooling, uint64_t seed);
 
 }  // namespace gsp2

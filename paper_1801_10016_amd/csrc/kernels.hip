@@ -226,7 +226,17 @@ __device__ __forceinline__ uint2 pack4_bf16(float4 v) {
     return x.u;
 }
 __device__ __forceinline__ uint2 pack4(float4 v, int precision) {
-    return precision == GSP2_PREC_FP16 ? pack4_fp16(v) : pack4_bf16(v);
+    return precision == GSP2_PREC_BF16 ? pack4_bf16(v) : pack4_fp16(v);
+}
+// Low parts of split FP16 operands: L = fp16(2^11 (x - fp16(x))), so that
+// x = fp16(x) + 2^-11 L to about 2^-22 relative (the scaling keeps L normal).
+__device__ __forceinline__ uint2 pack4_fp16_lo(float4 v) {
+    union { _Float16 h[4]; uint2 u; } x;
+    x.h[0] = (_Float16)((v.x - (float)(_Float16)v.x) * 0x1p11f);
+    x.h[1] = (_Float16)((v.y - (float)(_Float16)v.y) * 0x1p11f);
+    x.h[2] = (_Float16)((v.z - (float)(_Float16)v.z) * 0x1p11f);
+    x.h[3] = (_Float16)((v.w - (float)(_Float16)v.w) * 0x1p11f);
+    return x.u;
 }
 
 template <typename T>
@@ -237,6 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
                                                       const RowChunk *__restrict__ chunks,
                                                       const int32_t *__restrict__ idx_arena,
                                                       float *__restrict__ X, uint16_t *__restrict__ Xs,
+                                                      uint16_t *__restrict__ Xlo,
                                                       const RunState *__restrict__ st_all,
                                                       double *__restrict__ x0_partials) {
     __shared__ int32_t idx_s[kGatherLdsIdx];
@@ -291,6 +302,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
                 const int prec = st->precision;
                 uint2 *dsh = reinterpret_cast<uint2 *>(Xs + pd.x_off + (int64_t)r * ld + c0);
                 for (int i = threadIdx.x; i < cw / 4; i += kBlock) dsh[i] = pack4(src[i], prec);
+            }
+            if (Xlo) {
+                uint2 *dlo = reinterpret_cast<uint2 *>(Xlo + pd.x_off + (int64_t)r * ld + c0);
+                for (int i = threadIdx.x; i < cw / 4; i += kBlock) dlo[i] = pack4_fp16_lo(src[i]);
             }
             __syncthreads();
         }
@@ -490,11 +505,12 @@ __device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16
 // ---------------------------------------------------------------------------
 constexpr int kLdsWords = 2 * 2 * kTile * kLdsRow;  // [buffer][A/B][row * 9 + word]
 
-template <typename Op>
+template <typename Op, bool kSplit = false>
 __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, int cur, float alpha,
                                          float *__restrict__ buf0, float *__restrict__ buf1,
                                          Op *__restrict__ sh0, Op *__restrict__ sh1,
-                                         double *__restrict__ diag_partials, uint4 *__restrict__ lds_base) {
+                                         double *__restrict__ diag_partials, uint4 *__restrict__ lds_base,
+                                         Op *__restrict__ lo0 = nullptr, Op *__restrict__ lo1 = nullptr) {
     constexpr bool kF32 = sizeof(Op) == 4;
     constexpr int kK = OpFmt<Op>::kK;
     auto lds = [&](int b, int ab) { return lds_base + (b * 2 + ab) * kTile * kLdsRow; };
@@ -502,6 +518,9 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     float *__restrict__ Xn = (cur ? buf0 : buf1) + pd.x_off;
     const Op *__restrict__ Xop = kF32 ? reinterpret_cast<const Op *>(X) : (cur ? sh1 : sh0) + pd.x_off;
     Op *__restrict__ Xnop = kF32 ? nullptr : (cur ? sh0 : sh1) + pd.x_off;
+    // split operands: the scaled low parts of X and of the next iterate
+    const Op *__restrict__ Xlo = kSplit ? (cur ? lo1 : lo0) + pd.x_off : nullptr;
+    Op *__restrict__ Xnlo = kSplit ? (cur ? lo0 : lo1) + pd.x_off : nullptr;
     const int ld = pd.s_pad;
     const int I0 = td.ti * kTile, J0 = td.tj * kTile;
     const bool diag = td.ti == td.tj;
@@ -509,8 +528,10 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     const int tid = threadIdx.x;
     // global -> LDS: 8 threads per 128-byte row segment, 32 rows per pass
     const int lr = tid >> 3, lw = tid & 7;
-    const char *Ag = reinterpret_cast<const char *>(Xop + (int64_t)(I0 + lr) * ld) + lw * 16;
-    const char *Bg = reinterpret_cast<const char *>(Xop + (int64_t)(J0 + lr) * ld) + lw * 16;
+    const char *AgH = reinterpret_cast<const char *>(Xop + (int64_t)(I0 + lr) * ld) + lw * 16;
+    const char *BgH = reinterpret_cast<const char *>(Xop + (int64_t)(J0 + lr) * ld) + lw * 16;
+    const char *AgL = kSplit ? reinterpret_cast<const char *>(Xlo + (int64_t)(I0 + lr) * ld) + lw * 16 : nullptr;
+    const char *BgL = kSplit ? reinterpret_cast<const char *>(Xlo + (int64_t)(J0 + lr) * ld) + lw * 16 : nullptr;
     const int64_t pass_bytes = (int64_t)32 * ld * sizeof(Op);
 
     const int lane = tid & 63, wave = tid >> 6;
@@ -525,39 +546,72 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 #pragma unroll
             for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
 
+    // K chunks.  Plain: the nk chunks of X[I,:] X[J,:].  Split (X = H + 2^-11 L):
+    // nk chunks of H[I,:] L[J,:], nk of L[I,:] H[J,:], the accumulator scaled by
+    // 2^-11 (exact), then nk of H[I,:] H[J,:].  Where both panels of a chunk are
+    // the same rows (a diagonal tile's plain or H H chunks) only A is staged.
+    const int nk = ld / kK;
+    const int nc = kSplit ? 3 * nk : nk;
     uint4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
-#define GSP2_LOAD_CHUNK(kb)                                                                        \
+#define GSP2_CHUNK_SRC(c, Ap, Bp, kb, same)                                                        \
     do {                                                                                           \
-        pa0 = *reinterpret_cast<const uint4 *>(Ag + (kb));                                         \
-        pa1 = *reinterpret_cast<const uint4 *>(Ag + pass_bytes + (kb));                            \
-        pa2 = *reinterpret_cast<const uint4 *>(Ag + 2 * pass_bytes + (kb));                        \
-        pa3 = *reinterpret_cast<const uint4 *>(Ag + 3 * pass_bytes + (kb));                        \
-        if (!diag) {                                                                               \
-            pb0 = *reinterpret_cast<const uint4 *>(Bg + (kb));                                     \
-            pb1 = *reinterpret_cast<const uint4 *>(Bg + pass_bytes + (kb));                        \
-            pb2 = *reinterpret_cast<const uint4 *>(Bg + 2 * pass_bytes + (kb));                    \
-            pb3 = *reinterpret_cast<const uint4 *>(Bg + 3 * pass_bytes + (kb));                    \
+        if constexpr (kSplit) {                                                                    \
+            const int seg_ = (c) / nk;                                                             \
+            Ap = seg_ == 1 ? AgL : AgH;                                                            \
+            Bp = seg_ == 0 ? BgL : BgH;                                                            \
+            kb = (int64_t)((c) - seg_ * nk) * 128;                                                 \
+            same = diag && seg_ == 2;                                                              \
+        } else {                                                                                   \
+            Ap = AgH; Bp = BgH; kb = (int64_t)(c) * 128; same = diag;                              \
         }                                                                                          \
     } while (0)
-#define GSP2_STORE_CHUNK(b)                                                                        \
+#define GSP2_LOAD_CHUNK(Ap, Bp, kb, same)                                                          \
+    do {                                                                                           \
+        pa0 = *reinterpret_cast<const uint4 *>(Ap + (kb));                                         \
+        pa1 = *reinterpret_cast<const uint4 *>(Ap + pass_bytes + (kb));                            \
+        pa2 = *reinterpret_cast<const uint4 *>(Ap + 2 * pass_bytes + (kb));                        \
+        pa3 = *reinterpret_cast<const uint4 *>(Ap + 3 * pass_bytes + (kb));                        \
+        if (!(same)) {                                                                             \
+            pb0 = *reinterpret_cast<const uint4 *>(Bp + (kb));                                     \
+            pb1 = *reinterpret_cast<const uint4 *>(Bp + pass_bytes + (kb));                        \
+            pb2 = *reinterpret_cast<const uint4 *>(Bp + 2 * pass_bytes + (kb));                    \
+            pb3 = *reinterpret_cast<const uint4 *>(Bp + 3 * pass_bytes + (kb));                    \
+        }                                                                                          \
+    } while (0)
+#define GSP2_STORE_CHUNK(b, same)                                                                  \
     do {                                                                                           \
         uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;                                                \
         As_[0] = pa0; As_[32 * kLdsRow] = pa1; As_[64 * kLdsRow] = pa2; As_[96 * kLdsRow] = pa3;   \
-        if (!diag) {                                                                               \
+        if (!(same)) {                                                                             \
             uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                            \
             Bs_[0] = pb0; Bs_[32 * kLdsRow] = pb1; Bs_[64 * kLdsRow] = pb2; Bs_[96 * kLdsRow] = pb3; \
         }                                                                                          \
     } while (0)
 
-    const int nk = ld / kK;
-    GSP2_LOAD_CHUNK(0);
-    GSP2_STORE_CHUNK(0);
+    const char *Ap;
+    const char *Bp;
+    int64_t kb;
+    bool same_cur, same_next;
+    GSP2_CHUNK_SRC(0, Ap, Bp, kb, same_cur);
+    GSP2_LOAD_CHUNK(Ap, Bp, kb, same_cur);
+    GSP2_STORE_CHUNK(0, same_cur);
     __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
+    for (int kc = 0; kc < nc; ++kc) {
         const int buf = kc & 1;
-        if (kc + 1 < nk) GSP2_LOAD_CHUNK((int64_t)(kc + 1) * 128);
+        if (kc + 1 < nc) {
+            GSP2_CHUNK_SRC(kc + 1, Ap, Bp, kb, same_next);
+            GSP2_LOAD_CHUNK(Ap, Bp, kb, same_next);
+        }
+        if constexpr (kSplit) {
+            if (kc == 2 * nk) {                 // cross terms done: scale them by 2^-11
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
+            }
+        }
         const uint4 *Asb = lds(buf, 0);
-        const uint4 *Bsb = diag ? lds(buf, 0) : lds(buf, 1);
+        const uint4 *Bsb = same_cur ? lds(buf, 0) : lds(buf, 1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             // FP32: word kh*4+q of the row (k = 16 kh + 4 q + e); 16-bit: word 2q+kh (k = 16 q + 8 kh + e)
@@ -573,9 +627,13 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 #pragma unroll
                 for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
         }
-        if (kc + 1 < nk) GSP2_STORE_CHUNK(buf ^ 1);
+        if (kc + 1 < nc) {
+            GSP2_STORE_CHUNK(buf ^ 1, same_next);
+            same_cur = same_next;
+        }
         __syncthreads();
     }
+#undef GSP2_CHUNK_SRC
 #undef GSP2_LOAD_CHUNK
 #undef GSP2_STORE_CHUNK
 
@@ -599,7 +657,12 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
                     const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
                     xn[e] = v;
                     Xn[(int64_t)rg * ld + cg] = v;
-                    if constexpr (!kF32) Xnop[(int64_t)rg * ld + cg] = static_cast<Op>(v);
+                    if constexpr (!kF32) {
+                        const Op h = static_cast<Op>(v);
+                        Xnop[(int64_t)rg * ld + cg] = h;
+                        if constexpr (kSplit)
+                            Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
+                    }
                     if (diag && rg == cg && rg < pd.c) {
                         tY += static_cast<double>(y);
                         tX += static_cast<double>(v);
@@ -609,10 +672,16 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
                     const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
                     *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
                     if constexpr (!kF32) {
-                        union { Op h[4]; uint2 u; } pk;
-                        pk.h[0] = static_cast<Op>(v4.x); pk.h[1] = static_cast<Op>(v4.y);
-                        pk.h[2] = static_cast<Op>(v4.z); pk.h[3] = static_cast<Op>(v4.w);
+                        union { Op h[4]; uint2 u; } pk, pl;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
                         *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
+                        if constexpr (kSplit) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
+                            *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
+                        }
                     }
                 }
             }
@@ -627,20 +696,22 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     }
 }
 
-template <typename Op>
+template <typename Op, bool kSplit = false>
 __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restrict__ tiles,
                                                         const PartDesc *__restrict__ parts,
                                                         float *__restrict__ buf0, float *__restrict__ buf1,
                                                         Op *__restrict__ sh0, Op *__restrict__ sh1,
                                                         const RunState *__restrict__ st_all,
-                                                        double *__restrict__ diag_partials, int phase) {
+                                                        double *__restrict__ diag_partials, int phase,
+                                                        Op *__restrict__ lo0, Op *__restrict__ lo1) {
     __shared__ uint4 lds[kLdsWords];
     const TileDesc td = tiles[blockIdx.x];
     if (td.part < 0) return;                    // padding of a short XCD list
     const PartDesc pd = parts[td.part];
     const RunState *st = st_all + pd.sys;       // each system runs, stops and branches on its own
     if (st->done || st->phase != phase) return;
-    sp2_tile<Op>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, diag_partials, lds);
+    sp2_tile<Op, kSplit>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, diag_partials,
+                         lds, lo0, lo1);
 }
 
 // a7 between per-product launches: reduce the product's trace partials in a
@@ -1082,9 +1153,11 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.row_bounds);
     record(rec, k_run_init, sys, blk, dp.row_bounds, dp.sys_rows, dp.sys_row_ptr, rp, dp.sys_params, dp.state);
     const bool mixed = rp.precision != GSP2_PREC_FP32;
+    const bool split = rp.precision == GSP2_PREC_FP16X3;
     uint16_t *sh0 = mixed ? static_cast<uint16_t *>(dp.shadow[0]) : nullptr;
+    uint16_t *lo0 = split ? static_cast<uint16_t *>(dp.shadow_lo[0]) : nullptr;
     record(rec, k_gather_x0<T>, dim3(dp.n_chunks), blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx,
-           dp.buf[0], sh0, dp.state, dp.x0_partials);
+           dp.buf[0], sh0, lo0, dp.state, dp.x0_partials);
     record(rec, k_run_start, sys, blk, dp.x0_partials, dp.sys_chunk_ptr, dp.state);
     if (ev) rec.add_event(ev->setup_end);
     const dim3 grid(dp.n_tiles);
@@ -1107,19 +1180,23 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
         if (ev) rec.add_event(ev->persist_end);
         record(rec, k_persist_check, dim3(1), blk, dp.persist, dp.state);
     }
+    _Float16 *h16[2] = {static_cast<_Float16 *>(dp.shadow[0]), static_cast<_Float16 *>(dp.shadow[1])};
+    _Float16 *l16[2] = {static_cast<_Float16 *>(dp.shadow_lo[0]), static_cast<_Float16 *>(dp.shadow_lo[1])};
+    __bf16 *b16[2] = {static_cast<__bf16 *>(dp.shadow[0]), static_cast<__bf16 *>(dp.shadow[1])};
     for (int it = 0; it < (rp.persistent ? 0 : rp.n_steps); ++it) {
         if (ev) rec.add_event(ev->step[2 * it]);
         if (rp.precision == GSP2_PREC_FP16)
-            record(rec, k_sp2_step<_Float16>, grid, blk, dp.tiles, dp.parts, b0, b1,
-                   static_cast<_Float16 *>(dp.shadow[0]), static_cast<_Float16 *>(dp.shadow[1]), dp.state,
-                   dp.diag_partials, 0);
+            record(rec, k_sp2_step<_Float16>, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1], dp.state,
+                   dp.diag_partials, 0, (_Float16 *)nullptr, (_Float16 *)nullptr);
+        else if (rp.precision == GSP2_PREC_FP16X3)
+            record(rec, k_sp2_step<_Float16, true>, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1],
+                   dp.state, dp.diag_partials, 0, l16[0], l16[1]);
         else if (rp.precision == GSP2_PREC_BF16)
-            record(rec, k_sp2_step<__bf16>, grid, blk, dp.tiles, dp.parts, b0, b1,
-                   static_cast<__bf16 *>(dp.shadow[0]), static_cast<__bf16 *>(dp.shadow[1]), dp.state,
-                   dp.diag_partials, 0);
+            record(rec, k_sp2_step<__bf16>, grid, blk, dp.tiles, dp.parts, b0, b1, b16[0], b16[1], dp.state,
+                   dp.diag_partials, 0, (__bf16 *)nullptr, (__bf16 *)nullptr);
         else
             record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr,
-                   (float *)nullptr, dp.state, dp.diag_partials, 0);
+                   (float *)nullptr, dp.state, dp.diag_partials, 0, (float *)nullptr, (float *)nullptr);
         if (ev) rec.add_event(ev->step[2 * it + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 0);
     }
@@ -1127,7 +1204,7 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
         const int slot = rp.n_steps + r;
         if (ev) rec.add_event(ev->step[2 * slot]);
         record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr, (float *)nullptr,
-               dp.state, dp.diag_partials, 1);
+               dp.state, dp.diag_partials, 1, (float *)nullptr, (float *)nullptr);
         if (ev) rec.add_event(ev->step[2 * slot + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 1);
     }
@@ -1150,7 +1227,7 @@ hipError_t backward_typed(const DevicePlan &dp, const gsp2_csr &H, const RunPara
     record(rec, k_run_init, dim3(dp.n_sys), blk, dp.row_bounds, dp.sys_rows, dp.sys_row_ptr, rp, dp.sys_params,
            dp.state);
     record(rec, k_gather_x0<T>, chunks, blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx, bb.ckpt[0],
-           (uint16_t *)nullptr, dp.state, dp.x0_partials);
+           (uint16_t *)nullptr, (uint16_t *)nullptr, dp.state, dp.x0_partials);
     const int k = bb.seg;
     const int nseg = n > 0 ? (n + k - 1) / k : 1;
     // forward replay, keeping X_{seg k}

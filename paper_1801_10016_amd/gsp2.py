@@ -18,8 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libgsp2.so")
 GSP2_OK, GSP2_E_INVALID, GSP2_E_HIP, GSP2_E_OOM, GSP2_E_NOT_CONVERGED, GSP2_E_WRONG_TRACE, GSP2_E_UNSUPPORTED = range(7)
 GSP2_F32, GSP2_F64 = 0, 1
 GSP2_ALPHA_TRACE, GSP2_ALPHA_REPLAY = 0, 1
-GSP2_PREC_FP32, GSP2_PREC_FP16, GSP2_PREC_BF16 = 0, 1, 2
-PRECISIONS = {"fp32": GSP2_PREC_FP32, "fp16": GSP2_PREC_FP16, "bf16": GSP2_PREC_BF16}
+GSP2_PREC_FP32, GSP2_PREC_FP16, GSP2_PREC_BF16, GSP2_PREC_FP16X3 = 0, 1, 2, 3
+PRECISIONS = {"fp32": GSP2_PREC_FP32, "fp16": GSP2_PREC_FP16, "bf16": GSP2_PREC_BF16,
+              "fp16x3": GSP2_PREC_FP16X3}
 GSP2_MAX_ITER = 100
 
 STATUS_NAMES = {0: "GSP2_OK", 1: "GSP2_E_INVALID", 2: "GSP2_E_HIP", 3: "GSP2_E_OOM",
@@ -66,6 +67,11 @@ class gsp2_timing(C.Structure):
                 ("product_ms", C.c_float * GSP2_MAX_ITER)]
 
 
+class gsp2_anneal_options(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("pad_", C.c_int32), ("t0", C.c_double), ("cooling", C.c_double),
+                ("seed", C.c_uint64), ("reserved", C.c_int32 * 4)]
+
+
 class gsp2_backward_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("n_alpha", C.c_int32), ("checkpoint_every", C.c_int32),
                 ("row_min", C.c_int32), ("row_max", C.c_int32), ("eps_min", C.c_double),
@@ -93,6 +99,10 @@ SIGNATURES = {
     "gsp2_plan_destroy": (None, [_PLAN]),
     "gsp2_backward": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.POINTER(C.c_int8), C.c_int32, C.c_void_p,
                                 C.c_void_p, C.POINTER(gsp2_backward_info)]),
+    "gsp2_plan_graph": (C.c_int, [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "gsp2_partition_anneal": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32,
+                                        C.POINTER(C.c_int32), C.POINTER(gsp2_anneal_options),
+                                        C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "gsp2_core_halo_host": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -256,6 +266,32 @@ def gsp2_plan_part_index(plan: Plan, k: int) -> np.ndarray:
     idx = np.empty(int(ss[k]), dtype=np.int32)
     _check(load().gsp2_plan_part_index(plan.handle, int(k), _i32(idx)))
     return idx
+
+
+def gsp2_plan_graph(plan: Plan):
+    """The plan's thresholded graph as host CSR arrays (adj_ptr int64, adj_col int32)."""
+    info, _, _ = gsp2_plan_query(plan)
+    adj_ptr = np.empty(info["n"] + 1, dtype=np.int64)
+    _check(load().gsp2_plan_graph(plan.handle, _i64(adj_ptr), None))
+    adj_col = np.empty(int(adj_ptr[-1]), dtype=np.int32)
+    _check(load().gsp2_plan_graph(plan.handle, _i64(adj_ptr), _i32(adj_col)))
+    return adj_ptr, adj_col
+
+
+def gsp2_partition_anneal(adj_ptr, adj_col, part, n_parts: int, sweeps: int = 0, t0: float = 0.0,
+                          cooling: float = 0.0, seed: int = 0):
+    """Simulated-annealing refinement of a partition for eq. (4) (host only).
+    Returns (refined part, cost before, cost after); zero options mean defaults."""
+    adj_ptr = np.ascontiguousarray(adj_ptr, dtype=np.int64)
+    adj_col = np.ascontiguousarray(adj_col, dtype=np.int32)
+    out = np.array(part, dtype=np.int32, copy=True)
+    if adj_ptr.size != out.size + 1:
+        raise ValueError("adj_ptr must have n+1 entries")
+    opt = gsp2_anneal_options(int(sweeps), 0, float(t0), float(cooling), int(seed))
+    before, after = C.c_int64(), C.c_int64()
+    _check(load().gsp2_partition_anneal(out.size, _i64(adj_ptr), _i32(adj_col), int(n_parts), _i32(out),
+                                        C.byref(opt), C.byref(before), C.byref(after)))
+    return out, before.value, after.value
 
 
 def gsp2_plan_set_stream(plan: Plan, stream=None):

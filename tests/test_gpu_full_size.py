@@ -154,6 +154,23 @@ def test_mixed_precision_error_vs_oracle(case, precision, bar):
             assert max(errs.values()) <= bar
 
 
+def test_split_fp16_full_size(case):
+    """Split FP16 products (three FP16 products per product) on the full
+    workload meet the FP32 bar against the FP64 oracle."""
+    gold = case["gold"]
+    run, vals = _run(case, alpha_seq=gold["alphas"], trace_tol=1e9, precision="fp16x3")
+    assert np.isfinite(vals).all() and run["precision"] == 3
+    errs = _sampled_errors(case, vals)
+    print("fp16x3: sampled-part rel_err " + ", ".join(f"{e:.2e}" for e in errs.values()) +
+          f"; Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}", flush=True)
+    assert max(errs.values()) <= TOL
+    # trace mode: the stop rule fires, as with FP32 products
+    run, vals = _run(case, precision="fp16x3")
+    print(f"fp16x3 trace mode: {run['n_products']} products, Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}",
+          flush=True)
+    assert run["status"] == 0 and abs(run["trace"] - gold["traces"][-1]) <= 1e-2
+
+
 @pytest.mark.skip(reason="persistent product launch switched off: its first GPU run did not return "
                          "within 120 s and the cause has not been established (see the design notes)")
 def test_persistent_launch_full_size(case):

@@ -180,6 +180,28 @@ def test_mixed_precision_trace_mode(precision):
     assert out[2] <= 1.05 * out[0]           # a purification pair cannot undo the subspace error, nor add to it
 
 
+@pytest.mark.parametrize("n_mol,seed,n_parts,tau", [(64, 0, 8, 1e-5), (200, 1, 6, 1e-4)])
+def test_split_fp16_products_meet_the_fp32_bar(n_mol, seed, n_parts, tau):
+    # three FP16 products with the operand split X = A + 2^-11 B: the FP32 bar applies
+    P, run, ref = _check_parity(pins.water(n_mol, seed), tau, n_parts, precision="fp16x3")
+    assert run["precision"] == 3
+
+
+def test_split_fp16_one_product():
+    # one product isolates the operand split: its error is that of FP32 products
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(100, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 3, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, alpha_seq=[-1])
+    errs = {}
+    for prec in ("fp32", "fp16x3"):
+        P, run, _, _, _ = run_gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, alpha_seq=[-1], trace_tol=1e9, precision=prec)
+        errs[prec] = rel_fro(P, ref.csc())
+    print(f"one product: fp32 {errs['fp32']:.2e}, split fp16 {errs['fp16x3']:.2e}", flush=True)
+    assert errs["fp16x3"] <= 4 * 2.0 ** -22
+
+
 def test_refinement_products_do_not_drift():
     # 24 molecules, 3 parts: after the FP16 stop the trace sits above n_occ, so
     # branches taken by the trace rule would square towards one side only;
@@ -224,3 +246,37 @@ def test_persistent_request_is_refused():
     with pytest.raises(g.Gsp2Error) as e:
         run_gsp2(s.H, s.H, 1e-5, part, 1, s.n_occ, persistent=True)
     assert e.value.status == 6          # GSP2_E_UNSUPPORTED
+
+
+def test_plan_graph_is_the_threshold_graph():
+    # the graph the GPU built, exported from the plan, is the oracle's G_tau
+    import paper_1801_10016_amd as g
+    s = pins.water(64, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 8, seed=0)
+    with g.gsp2_plan_create(g.csr_to_device(sp.csr_matrix(Pp)), 1e-3, part, 8) as plan:
+        adj_ptr, adj_col = g.gsp2_plan_graph(plan)
+        info, _, _ = g.gsp2_plan_query(plan)
+    A = sp.csr_matrix((np.ones(adj_col.size), adj_col, adj_ptr), shape=(s.n, s.n))
+    ref = oracle.threshold_graph(Pp, 1e-3)
+    assert info["nnz_graph"] == adj_col.size
+    assert ((A + A.T) != 0).toarray().tolist() == (ref != 0).toarray().tolist()
+
+
+def test_annealed_partition_runs_and_matches_its_cost():
+    # f4: the plan's graph, refined by simulated annealing for eq. (4), feeds a
+    # new plan: its sum of s^3 is the annealer's cost, and P matches the oracle
+    import paper_1801_10016_amd as g
+    s = pins.water(200, 1)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 6, seed=0)
+    Pd = g.csr_to_device(sp.csr_matrix(Pp))
+    with g.gsp2_plan_create(Pd, 1e-4, part, 6) as plan:
+        adj_ptr, adj_col = g.gsp2_plan_graph(plan)
+        before = g.gsp2_plan_query(plan)[0]["sum_s3"]
+    new, c0, c1 = g.gsp2_partition_anneal(adj_ptr, adj_col, part, 6, seed=3)
+    print(f"annealed: C {c0} -> {c1} ({c1 / c0:.3f})", flush=True)
+    assert c0 == before and c1 <= c0
+    with g.gsp2_plan_create(Pd, 1e-4, new, 6) as plan:
+        assert g.gsp2_plan_query(plan)[0]["sum_s3"] == c1
+    _check_parity(s, 1e-4, 6, part=new)

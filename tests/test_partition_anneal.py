@@ -1,0 +1,116 @@
+"""gsp2_partition_anneal (host, no GPU): simulated-annealing refinement of a
+partition for the cost of eq. (4), C = sum_k (c_k + h_k)^3.
+
+Pins: the cost the library reports for the partition it was given and for
+the one it returns equals the oracle's eq. (4) cost of the same partitions
+(exact integers); on graphs small enough to enumerate every partition, the
+annealer reaches the brute-force optimum; it never returns a worse
+partition, never empties a part, and is deterministic for a seed."""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import paper_1801_10016_amd as g
+from paper_1801_10016_amd import gsp2 as binding
+from synth.partition import uneven_spatial_partition
+from tests import _pins as pins
+
+
+def _csr(A):
+    A = sp.csr_matrix(A)
+    return A.indptr.astype(np.int64), A.indices.astype(np.int32)
+
+
+def _cost(A, part, n_parts):
+    cores, halos = oracle.core_halo(oracle.threshold_graph(A, 0.5), part, n_parts)
+    return oracle.ch_cost([len(c) + len(h) for c, h in zip(cores, halos)])
+
+
+def _brute_force(A, n, n_parts):
+    best = None
+    for labels in itertools.product(range(n_parts), repeat=n):
+        if len(set(labels)) < n_parts:
+            continue
+        c = _cost(A, np.array(labels), n_parts)
+        best = c if best is None else min(best, c)
+    return best
+
+
+def _fig2():
+    import json
+    import os
+    spec = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fig2_corehalo.json")))
+    names = spec["vertices"]
+    ix = {v: i for i, v in enumerate(names)}
+    A = np.zeros((6, 6))
+    for a, b in spec["edges"]:
+        A[ix[a], ix[b]] = A[ix[b], ix[a]] = 1.0
+    part_b = np.zeros(6, dtype=np.int32)
+    for k, members in enumerate(spec["partitions"]["b"]["parts"]):
+        for v in members:
+            part_b[ix[v]] = k
+    return A, part_b
+
+
+def test_fig2_reaches_the_optimum_from_the_worse_partition():
+    # the paper's Fig. 2: partition (b) costs 243; the better (a) costs 189
+    A, part_b = _fig2()
+    ptr, col = _csr(A)
+    out, before, after = g.gsp2_partition_anneal(ptr, col, part_b, 2, sweeps=50, seed=1)
+    assert before == 243 == _cost(A, part_b, 2)
+    assert after == _cost(A, out, 2) == _brute_force(A, 6, 2)
+    assert after <= 189
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_random_small_graphs_reach_the_brute_force_optimum(seed):
+    rng = np.random.default_rng(seed)
+    n, k = 8, 3
+    A = np.triu((rng.random((n, n)) < 0.35).astype(float), 1)
+    A = A + A.T
+    start = np.arange(n, dtype=np.int32) % k
+    ptr, col = _csr(A)
+    best = min(g.gsp2_partition_anneal(ptr, col, start, k, sweeps=200, seed=s)[2] for s in range(3))
+    assert best == _brute_force(A, n, k)
+
+
+def test_water_graph_costs_match_the_oracle():
+    s = pins.water(64, 0)
+    P = pins.cached(("dense", s.n_mol, s.seed, s.hop_a), lambda: oracle.dense_sp2(s.H, s.n_occ)[0])
+    adj = oracle.threshold_graph(P, 1e-3)
+    n_parts = 8
+    part = uneven_spatial_partition(s, n_parts, seed=0)
+    ptr, col = _csr(adj)
+    out, before, after = g.gsp2_partition_anneal(ptr, col, part, n_parts, seed=5)
+    assert before == _cost(adj, part, n_parts)
+    assert after == _cost(adj, out, n_parts)
+    assert after <= before
+    assert np.bincount(out, minlength=n_parts).min() >= 1
+    again = g.gsp2_partition_anneal(ptr, col, part, n_parts, seed=5)
+    assert np.array_equal(again[0], out) and again[2] == after
+    print(f"water 64, 8 parts, tau 1e-3: C {before} -> {after} ({after / before:.3f})")
+
+
+def test_greedy_refinement_never_worsens():
+    s = pins.water(32, 1)
+    P = pins.cached(("dense", s.n_mol, s.seed, s.hop_a), lambda: oracle.dense_sp2(s.H, s.n_occ)[0])
+    adj = oracle.threshold_graph(P, 1e-3)
+    part = uneven_spatial_partition(s, 4, seed=0)
+    ptr, col = _csr(adj)
+    out, before, after = g.gsp2_partition_anneal(ptr, col, part, 4, t0=-1.0, seed=2)
+    assert after <= before and after == _cost(adj, out, 4)
+
+
+def test_bad_arguments_are_refused():
+    A, part_b = _fig2()
+    ptr, col = _csr(A)
+    with pytest.raises(g.Gsp2Error) as e:
+        g.gsp2_partition_anneal(ptr, col, np.zeros(6, dtype=np.int32), 2)        # part 1 empty
+    assert e.value.status == binding.GSP2_E_INVALID and "empty" in str(e.value)
+    with pytest.raises(g.Gsp2Error):
+        g.gsp2_partition_anneal(ptr, col, part_b, 2, cooling=1.5)
+    with pytest.raises(g.Gsp2Error):
+        g.gsp2_partition_anneal(ptr, col, part_b, 2, sweeps=-1)
