@@ -184,7 +184,7 @@ struct gsp2_plan_s {
     std::vector<int64_t> sub_ptr;
     std::vector<int32_t> sub_idx, core_count;
     std::vector<PartDesc> desc;
-    std::vector<TileDesc> tiles;
+    std::vector<TileDesc> tiles, tiles_w;
     std::vector<RowChunk> chunks;
     std::vector<int32_t> perm;
     std::vector<int64_t> col_ptr;
@@ -472,6 +472,26 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         for (size_t q = 0; q < longest; ++q)
             for (int x = 0; x < kXcds; ++x)
                 plan->tiles.push_back(q < lists[x].size() ? lists[x][q] : TileDesc{-1, 0, 0, -1});
+        // The same order for the 256 x 256 tiles of the 16-bit products, in
+        // blocks of 4 x 4 (the same panels as 8 x 8 blocks of 128-tiles).  A
+        // diagonal 256-tile covers 128-tile diagonal slots 2t and 2t + 1.
+        constexpr int kTileBlockW = 4;
+        std::vector<std::vector<TileDesc>> lists_w(kXcds);
+        for (int x = 0; x < kXcds; ++x) {
+            for (int32_t k : xcd_parts[x]) {
+                const int nt = (plan->desc[k].s_pad + kTileWide - 1) / kTileWide;
+                for (int bi = 0; bi < nt; bi += kTileBlockW)
+                    for (int bj = bi; bj < nt; bj += kTileBlockW)
+                        for (int ti = bi; ti < std::min(bi + kTileBlockW, nt); ++ti)
+                            for (int tj = std::max(ti, bj); tj < std::min(bj + kTileBlockW, nt); ++tj)
+                                lists_w[x].push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + 2 * ti : -1});
+            }
+        }
+        longest = 0;
+        for (auto &l : lists_w) longest = std::max(longest, l.size());
+        for (size_t q = 0; q < longest; ++q)
+            for (int x = 0; x < kXcds; ++x)
+                plan->tiles_w.push_back(q < lists_w[x].size() ? lists_w[x][q] : TileDesc{-1, 0, 0, -1});
         plan->n_diag = slot;
         constexpr int kRowsPerChunk = 16;
         for (int32_t y = 0; y < n_sys; ++y) {
@@ -528,6 +548,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         dp.buf[1] = plan->alloc<float>(plan->arena_floats, "X buffer 1");
         auto *d_parts = plan->alloc<PartDesc>(n_parts, "part descriptors");
         auto *d_tiles = plan->alloc<TileDesc>(plan->tiles.size(), "tiles");
+        auto *d_tiles_w = plan->alloc<TileDesc>(plan->tiles_w.size(), "wide tiles");
         auto *d_chunks = plan->alloc<RowChunk>(plan->chunks.size(), "row chunks");
         auto *d_idx = plan->alloc<int32_t>(plan->sub_idx.size(), "index arena");
         auto *d_perm = plan->alloc<int32_t>(plan->perm.size(), "perm arena");
@@ -571,6 +592,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         dp.sys_diag_ptr = d_sys_diag_ptr;
         upload(d_parts, plan->desc, s, "upload parts");
         upload(d_tiles, plan->tiles, s, "upload tiles");
+        upload(d_tiles_w, plan->tiles_w, s, "upload wide tiles");
         upload(d_chunks, plan->chunks, s, "upload chunks");
         upload(d_idx, plan->sub_idx, s, "upload index");
         upload(d_perm, plan->perm, s, "upload perm");
@@ -580,6 +602,8 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         check_hip(hipMemsetAsync(dp.state, 0, sizeof(RunState) * (size_t)n_sys, s), "clear state");
         dp.parts = d_parts;
         dp.tiles = d_tiles;
+        dp.tiles_w = d_tiles_w;
+        dp.n_tiles_w = (int32_t)plan->tiles_w.size();
         dp.chunks = d_chunks;
         dp.idx = d_idx;
         dp.perm = d_perm;

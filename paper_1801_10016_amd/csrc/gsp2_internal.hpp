@@ -12,6 +12,7 @@ namespace gsp2 {
 // workgroup) and the K depth staged through LDS per pipeline step.
 constexpr int kTile = 128;
 constexpr int kKChunk = 32;
+constexpr int kTileWide = 256;      // product tile of 16-bit operands
 
 // XCDs of an MI355X: workgroup b of a launch runs on XCD b mod kXcds.
 constexpr int kXcds = 8;
@@ -123,6 +124,9 @@ struct DevicePlan {
     void *shadow_lo[2];         // scaled FP16 low parts of the two X buffers (split FP16 products)
     const PartDesc *parts;
     const TileDesc *tiles;
+    const TileDesc *tiles_w;    // 256 x 256 tiles of the 16-bit products (same layout rules)
+    int32_t n_tiles_w;
+    int32_t pad_w_;
     const RowChunk *chunks;
     const int32_t *idx;         // index arena (local order)
     const int32_t *perm;        // per part: sorted position -> local index

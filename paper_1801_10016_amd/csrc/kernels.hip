@@ -714,6 +714,239 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
                          lds, lo0, lo1);
 }
 
+// ---------------------------------------------------------------------------
+// a6 with 16-bit operands: 256 x 256 product tiles.
+//
+// At 16 bits a 128-wide tile moves too many operand bytes per matrix-core
+// flop: the 128-tile product is bound by L2 misses to HBM (the L2 serves
+// only about 58% of its panel reads, rocprofv3 TCC_HIT / TCC_MISS).  A
+// 256 x 256 tile halves the operand bytes per flop.  512 threads = 8 waves
+// in a 2 x 4 grid, each wave a 128 x 64 sub-tile as 4 x 2 blocks of 32 x 32
+// MFMA output, so 6 LDS fragment reads feed 8 MFMAs; two LDS buffers of
+// 2 x 256 rows x 144 B hold one workgroup per CU.  Tiles step by 256 over
+// the part; where s_pad is an odd multiple of 128, the last tile row and
+// column are half empty: those rows are neither loaded nor computed.  A
+// diagonal tile's trace partials go to the two 128-tile slots it covers, so
+// the control kernels are those of the 128-tile product.  Both operand
+// panels are staged for every chunk, diagonal tiles included.
+// ---------------------------------------------------------------------------
+constexpr int kTileW = 256;
+constexpr int kBlockW = 512;
+constexpr int kLdsWordsW = 2 * 2 * kTileW * kLdsRow;  // [buffer][A/B][row * 9 + word]: 147,456 bytes
+
+template <typename Op, bool kSplit>
+__device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc pd, int cur, float alpha,
+                                              float *__restrict__ buf0, float *__restrict__ buf1,
+                                              Op *__restrict__ sh0, Op *__restrict__ sh1, Op *__restrict__ lo0,
+                                              Op *__restrict__ lo1, double *__restrict__ diag_partials,
+                                              uint4 *__restrict__ lds_base) {
+    static_assert(sizeof(Op) == 2, "wide tiles are for 16-bit operands");
+    constexpr int kK = OpFmt<Op>::kK;
+    __shared__ double red[2][kBlockW / kWave];
+    auto lds = [&](int b, int ab) { return lds_base + (b * 2 + ab) * kTileW * kLdsRow; };
+    const float *__restrict__ X = (cur ? buf1 : buf0) + pd.x_off;
+    float *__restrict__ Xn = (cur ? buf0 : buf1) + pd.x_off;
+    const Op *__restrict__ Xop = (cur ? sh1 : sh0) + pd.x_off;
+    Op *__restrict__ Xnop = (cur ? sh0 : sh1) + pd.x_off;
+    const Op *__restrict__ Xlo = kSplit ? (cur ? lo1 : lo0) + pd.x_off : nullptr;
+    Op *__restrict__ Xnlo = kSplit ? (cur ? lo0 : lo1) + pd.x_off : nullptr;
+    const int ld = pd.s_pad;
+    const int I0 = td.ti * kTileW, J0 = td.tj * kTileW;
+    const bool diag = td.ti == td.tj;
+    const bool fullA = I0 + kTileW <= ld, fullB = J0 + kTileW <= ld;   // else 128 rows remain
+
+    const int tid = threadIdx.x;
+    // global -> LDS: 8 threads per 128-byte row segment, 64 rows per pass,
+    // passes 2 and 3 only where the panel has all 256 rows
+    const int lr = tid >> 3, lw = tid & 7;
+    const char *AgH = reinterpret_cast<const char *>(Xop + (int64_t)(I0 + lr) * ld) + lw * 16;
+    const char *BgH = reinterpret_cast<const char *>(Xop + (int64_t)(J0 + lr) * ld) + lw * 16;
+    const char *AgL = kSplit ? reinterpret_cast<const char *>(Xlo + (int64_t)(I0 + lr) * ld) + lw * 16 : nullptr;
+    const char *BgL = kSplit ? reinterpret_cast<const char *>(Xlo + (int64_t)(J0 + lr) * ld) + lw * 16 : nullptr;
+    const int64_t pass_bytes = (int64_t)64 * ld * sizeof(Op);
+
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 2, wc = wave & 3;        // rows wr*128.., columns wc*64..
+    const int l32 = lane & 31, kh = lane >> 5;
+    const bool active = (wr == 0 || fullA) && (wc < 2 || fullB);
+
+    v16f acc[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
+
+    // chunks as in sp2_tile: plain nk of X X; split nk of H L, nk of L H,
+    // the scale by 2^-11, nk of H H
+    const int nk = ld / kK;
+    const int nc = kSplit ? 3 * nk : nk;
+    uint4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
+#define GSP2W_SRC(c, Ap, Bp, kb)                                                                   \
+    do {                                                                                           \
+        if constexpr (kSplit) {                                                                    \
+            const int seg_ = (c) / nk;                                                             \
+            Ap = seg_ == 1 ? AgL : AgH;                                                            \
+            Bp = seg_ == 0 ? BgL : BgH;                                                            \
+            kb = (int64_t)((c) - seg_ * nk) * 128;                                                 \
+        } else {                                                                                   \
+            Ap = AgH; Bp = BgH; kb = (int64_t)(c) * 128;                                           \
+        }                                                                                          \
+    } while (0)
+#define GSP2W_LOAD(Ap, Bp, kb)                                                                     \
+    do {                                                                                           \
+        pa0 = *reinterpret_cast<const uint4 *>(Ap + (kb));                                         \
+        pa1 = *reinterpret_cast<const uint4 *>(Ap + pass_bytes + (kb));                            \
+        if (fullA) {                                                                               \
+            pa2 = *reinterpret_cast<const uint4 *>(Ap + 2 * pass_bytes + (kb));                    \
+            pa3 = *reinterpret_cast<const uint4 *>(Ap + 3 * pass_bytes + (kb));                    \
+        }                                                                                          \
+        pb0 = *reinterpret_cast<const uint4 *>(Bp + (kb));                                         \
+        pb1 = *reinterpret_cast<const uint4 *>(Bp + pass_bytes + (kb));                            \
+        if (fullB) {                                                                               \
+            pb2 = *reinterpret_cast<const uint4 *>(Bp + 2 * pass_bytes + (kb));                    \
+            pb3 = *reinterpret_cast<const uint4 *>(Bp + 3 * pass_bytes + (kb));                    \
+        }                                                                                          \
+    } while (0)
+#define GSP2W_STORE(b)                                                                             \
+    do {                                                                                           \
+        uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;                                                \
+        As_[0] = pa0; As_[64 * kLdsRow] = pa1;                                                     \
+        if (fullA) { As_[128 * kLdsRow] = pa2; As_[192 * kLdsRow] = pa3; }                         \
+        uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                                \
+        Bs_[0] = pb0; Bs_[64 * kLdsRow] = pb1;                                                     \
+        if (fullB) { Bs_[128 * kLdsRow] = pb2; Bs_[192 * kLdsRow] = pb3; }                         \
+    } while (0)
+
+    const char *Ap;
+    const char *Bp;
+    int64_t kb;
+    GSP2W_SRC(0, Ap, Bp, kb);
+    GSP2W_LOAD(Ap, Bp, kb);
+    GSP2W_STORE(0);
+    __syncthreads();
+    for (int kc = 0; kc < nc; ++kc) {
+        const int buf = kc & 1;
+        if (kc + 1 < nc) {
+            GSP2W_SRC(kc + 1, Ap, Bp, kb);
+            GSP2W_LOAD(Ap, Bp, kb);
+        }
+        if constexpr (kSplit) {
+            if (kc == 2 * nk) {                 // cross terms done: scale them by 2^-11
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
+            }
+        }
+        if (active) {
+            const uint4 *Asb = lds(buf, 0);
+            const uint4 *Bsb = lds(buf, 1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int w = 2 * q + kh;       // k = 16 q + 8 kh + e
+                uint4 fa[4], fb[2];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) fa[m] = Asb[(wr * 128 + m * 32 + l32) * kLdsRow + w];
+#pragma unroll
+                for (int nn = 0; nn < 2; ++nn) fb[nn] = Bsb[(wc * 64 + nn * 32 + l32) * kLdsRow + w];
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
+            }
+        }
+        if (kc + 1 < nc) GSP2W_STORE(buf ^ 1);
+        __syncthreads();
+    }
+#undef GSP2W_SRC
+#undef GSP2W_LOAD
+#undef GSP2W_STORE
+
+    // Epilogue: as in sp2_tile, over this wave's 4 x 2 blocks.
+    double tY = 0.0, tX = 0.0;
+    if (active) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int nn = 0; nn < 2; ++nn) {
+                const int cg = J0 + wc * 64 + nn * 32 + l32;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int rg0 = I0 + wr * 128 + m * 32 + g * 8 + kh * 4;
+                    float xn[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int rg = rg0 + e;
+                        const float y = acc[m][nn][4 * g + e];
+                        const float xo = X[(int64_t)rg * ld + cg];
+                        const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
+                        xn[e] = v;
+                        Xn[(int64_t)rg * ld + cg] = v;
+                        const Op h = static_cast<Op>(v);
+                        Xnop[(int64_t)rg * ld + cg] = h;
+                        if constexpr (kSplit)
+                            Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
+                        if (diag && rg == cg && rg < pd.c) {
+                            tY += static_cast<double>(y);
+                            tX += static_cast<double>(v);
+                        }
+                    }
+                    if (!diag) {
+                        const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
+                        *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
+                        union { Op h[4]; uint2 u; } pk, pl;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
+                        *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
+                        if constexpr (kSplit) {
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
+                            *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (diag) {
+        // wave (wr, wc) holds diagonal elements only in row half wr; one
+        // FP64 partial per 128-row half, summed in a fixed order
+        tY = wave_sum(tY);
+        tX = wave_sum(tX);
+        if (lane == 0) { red[0][wave] = tY; red[1][wave] = tX; }
+        __syncthreads();
+        if (tid == 0) {
+            for (int h = 0; h < (fullA ? 2 : 1); ++h) {
+                double y = 0.0, x = 0.0;
+                for (int w4 = 0; w4 < 4; ++w4) { y += red[0][h * 4 + w4]; x += red[1][h * 4 + w4]; }
+                diag_partials[2 * (td.diag_slot + h) + 0] = y;
+                diag_partials[2 * (td.diag_slot + h) + 1] = x;
+            }
+        }
+    }
+}
+
+template <typename Op, bool kSplit>
+__global__ __launch_bounds__(kBlockW, 1) void k_sp2_wide(const TileDesc *__restrict__ tiles,
+                                                         const PartDesc *__restrict__ parts,
+                                                         float *__restrict__ buf0, float *__restrict__ buf1,
+                                                         Op *__restrict__ sh0, Op *__restrict__ sh1,
+                                                         const RunState *__restrict__ st_all,
+                                                         double *__restrict__ diag_partials,
+                                                         Op *__restrict__ lo0, Op *__restrict__ lo1) {
+    __shared__ uint4 lds_w[kLdsWordsW];
+    const TileDesc td = tiles[blockIdx.x];
+    if (td.part < 0) return;
+    const PartDesc pd = parts[td.part];
+    const RunState *st = st_all + pd.sys;
+    if (st->done || st->phase != 0) return;
+    sp2_tile_wide<Op, kSplit>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, lo0, lo1,
+                              diag_partials, lds_w);
+}
+
 // a7 between per-product launches: reduce the product's trace partials in a
 // fixed order and take the decision.  One workgroup per system, over the
 // system's run of diagonal-tile slots.
@@ -1183,17 +1416,18 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     _Float16 *h16[2] = {static_cast<_Float16 *>(dp.shadow[0]), static_cast<_Float16 *>(dp.shadow[1])};
     _Float16 *l16[2] = {static_cast<_Float16 *>(dp.shadow_lo[0]), static_cast<_Float16 *>(dp.shadow_lo[1])};
     __bf16 *b16[2] = {static_cast<__bf16 *>(dp.shadow[0]), static_cast<__bf16 *>(dp.shadow[1])};
+    const dim3 grid_w(dp.n_tiles_w), blk_w(kBlockW);
     for (int it = 0; it < (rp.persistent ? 0 : rp.n_steps); ++it) {
         if (ev) rec.add_event(ev->step[2 * it]);
         if (rp.precision == GSP2_PREC_FP16)
-            record(rec, k_sp2_step<_Float16>, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1], dp.state,
-                   dp.diag_partials, 0, (_Float16 *)nullptr, (_Float16 *)nullptr);
+            record(rec, k_sp2_wide<_Float16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0], h16[1],
+                   dp.state, dp.diag_partials, (_Float16 *)nullptr, (_Float16 *)nullptr);
         else if (rp.precision == GSP2_PREC_FP16X3)
-            record(rec, k_sp2_step<_Float16, true>, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1],
-                   dp.state, dp.diag_partials, 0, l16[0], l16[1]);
+            record(rec, k_sp2_wide<_Float16, true>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0], h16[1],
+                   dp.state, dp.diag_partials, l16[0], l16[1]);
         else if (rp.precision == GSP2_PREC_BF16)
-            record(rec, k_sp2_step<__bf16>, grid, blk, dp.tiles, dp.parts, b0, b1, b16[0], b16[1], dp.state,
-                   dp.diag_partials, 0, (__bf16 *)nullptr, (__bf16 *)nullptr);
+            record(rec, k_sp2_wide<__bf16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, b16[0], b16[1],
+                   dp.state, dp.diag_partials, (__bf16 *)nullptr, (__bf16 *)nullptr);
         else
             record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr,
                    (float *)nullptr, dp.state, dp.diag_partials, 0, (float *)nullptr, (float *)nullptr);
