@@ -351,6 +351,27 @@ gsp2_status gsp2_partition_anneal(int32_t n, const int64_t *adj_ptr, const int32
                                   int64_t *cost_after);
 
 /*
+ * Host-only (no GPU needed): the graph of the locality construction that the
+ * paper's graph-theory section names as an alternative to thresholding an
+ * earlier P: beyond a localization radius, elements of P are taken as zero.
+ * Orbitals u != v are adjacent when their atoms lie closer than `radius`
+ * (minimum image in a cubic periodic box of edge `box`; open boundaries
+ * when box <= 0); orbitals of one atom are always adjacent.  The result
+ * seeds a plan where no earlier P exists (pass it as P_prev with unit values
+ * and any tau in [0, 1)), or feeds gsp2_partition_anneal.
+ *  orbital_atom  host, n_orb int32 atom ids in [0, n_atoms).
+ *  xyz           host, 3 n_atoms doubles (x, y, z of every atom).
+ *  radius        > 0 (same length unit as xyz and box).
+ *  adj_ptr       host, n_orb + 1 int64 (out).
+ *  adj_col       host, adj_ptr[n_orb] int32 (out), nullable: pass NULL first
+ *                to size it.  Every row lists its columns ascending; the
+ *                graph is symmetric and has no self loops.
+ * Errors: GSP2_E_INVALID.
+ */
+gsp2_status gsp2_locality_graph(int32_t n_orb, const int32_t *orbital_atom, int32_t n_atoms, const double *xyz,
+                                double radius, double box, int64_t *adj_ptr, int32_t *adj_col);
+
+/*
  * Host-only planning step (no GPU needed): core and one-hop halo of every
  * part of an undirected graph given by a directed adjacency (the union of
  * both orientations is used; self loops are ignored).

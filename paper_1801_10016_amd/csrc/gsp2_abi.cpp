@@ -712,6 +712,26 @@ gsp2_status gsp2_partition_anneal(int32_t n, const int64_t *adj_ptr, const int32
     });
 }
 
+gsp2_status gsp2_locality_graph(int32_t n_orb, const int32_t *orbital_atom, int32_t n_atoms, const double *xyz,
+                                double radius, double box, int64_t *adj_ptr, int32_t *adj_col) {
+    return guarded([&] {
+        if (n_orb < 1 || n_atoms < 1) fail(GSP2_E_INVALID, "need n_orb >= 1 and n_atoms >= 1");
+        if (!orbital_atom || !xyz || !adj_ptr) fail(GSP2_E_INVALID, "null pointer");
+        if (!(radius > 0.0) || !std::isfinite(radius)) fail(GSP2_E_INVALID, "radius must be finite and > 0");
+        if (!std::isfinite(box)) fail(GSP2_E_INVALID, "box must be finite");
+        for (int32_t u = 0; u < n_orb; ++u)
+            if (orbital_atom[u] < 0 || orbital_atom[u] >= n_atoms)
+                fail(GSP2_E_INVALID, "atom id out of range at orbital " + std::to_string(u));
+        for (int64_t i = 0; i < 3 * (int64_t)n_atoms; ++i)
+            if (!std::isfinite(xyz[i])) fail(GSP2_E_INVALID, "non-finite coordinate");
+        std::vector<int64_t> ptr;
+        std::vector<int32_t> col;
+        locality_graph(n_orb, orbital_atom, n_atoms, xyz, radius, box, ptr, col);
+        std::copy(ptr.begin(), ptr.end(), adj_ptr);
+        if (adj_col) std::copy(col.begin(), col.end(), adj_col);
+    });
+}
+
 gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream) {
     return guarded([&] {
         if (!plan) fail(GSP2_E_INVALID, "null plan");

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "gsp2.h"
 
 namespace gsp2 {
@@ -223,5 +225,10 @@ struct AnnealResult {
 };
 AnnealResult anneal_partition(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, int32_t n_parts,
                               int32_t *part, int32_t sweeps, double t0, double cooling, uint64_t seed);
+
+// Graph of the locality construction: orbitals adjacent when their atoms are
+// closer than `radius` (partition.cpp).
+void locality_graph(int32_t n_orb, const int32_t *orbital_atom, int32_t n_atoms, const double *xyz, double radius,
+                    double box, std::vector<int64_t> &adj_ptr, std::vector<int32_t> &adj_col);
 
 }  // namespace gsp2

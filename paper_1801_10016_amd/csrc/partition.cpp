@@ -161,3 +161,86 @@ AnnealResult anneal_partition(int32_t n, const int64_t *adj_ptr, const int32_t *
 }
 
 }  // namespace gsp2
+
+// ---------------------------------------------------------------------------
+// Locality construction of the graph (host).
+//
+// The paper's graph-theory section notes that sub-problems can also be built
+// from locality: beyond a localization radius the elements of P are taken as
+// zero.  Here orbitals u != v are adjacent when their atoms lie closer than
+// `radius` (minimum image in a cubic periodic box of edge `box`, or open
+// boundaries for box <= 0); orbitals of one atom are always adjacent.  Atom
+// pairs come from a cell list with cells no smaller than the radius (27
+// neighbouring cells; a direct double loop when the box holds fewer than
+// three cells per edge).
+// ---------------------------------------------------------------------------
+namespace gsp2 {
+
+void locality_graph(int32_t n_orb, const int32_t *orbital_atom, int32_t n_atoms, const double *xyz, double radius,
+                    double box, std::vector<int64_t> &adj_ptr, std::vector<int32_t> &adj_col) {
+    const bool periodic = box > 0.0;
+    const double r2 = radius * radius;
+    auto dist2 = [&](int32_t a, int32_t b) {
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            double x = xyz[3 * b + d] - xyz[3 * a + d];
+            if (periodic) x -= box * std::nearbyint(x / box);
+            s += x * x;
+        }
+        return s;
+    };
+    // atom neighbour lists (both orientations), strict distance < radius
+    std::vector<std::vector<int32_t>> anb(n_atoms);
+    const int nc = periodic ? (int)std::floor(box / radius) : 0;
+    if (periodic && nc >= 3) {
+        auto cell_of = [&](int32_t a, int d) {
+            double x = xyz[3 * a + d] - box * std::floor(xyz[3 * a + d] / box);   // wrap into [0, box)
+            int c = (int)(x / box * nc);
+            return c >= nc ? nc - 1 : c;
+        };
+        std::vector<std::vector<int32_t>> cells((size_t)nc * nc * nc);
+        std::vector<int> cx(n_atoms), cy(n_atoms), cz(n_atoms);
+        for (int32_t a = 0; a < n_atoms; ++a) {
+            cx[a] = cell_of(a, 0); cy[a] = cell_of(a, 1); cz[a] = cell_of(a, 2);
+            cells[((size_t)cx[a] * nc + cy[a]) * nc + cz[a]].push_back(a);
+        }
+        for (int32_t a = 0; a < n_atoms; ++a)
+            for (int dx = -1; dx <= 1; ++dx)
+                for (int dy = -1; dy <= 1; ++dy)
+                    for (int dz = -1; dz <= 1; ++dz) {
+                        const int x = (cx[a] + dx + nc) % nc, y = (cy[a] + dy + nc) % nc, z = (cz[a] + dz + nc) % nc;
+                        for (int32_t b : cells[((size_t)x * nc + y) * nc + z])
+                            if (b != a && dist2(a, b) < r2) anb[a].push_back(b);
+                    }
+    } else {
+        for (int32_t a = 0; a < n_atoms; ++a)
+            for (int32_t b = 0; b < n_atoms; ++b)
+                if (b != a && dist2(a, b) < r2) anb[a].push_back(b);
+    }
+    // orbitals of every atom
+    std::vector<int64_t> aptr(n_atoms + 1, 0);
+    for (int32_t u = 0; u < n_orb; ++u) aptr[orbital_atom[u] + 1]++;
+    for (int32_t a = 0; a < n_atoms; ++a) aptr[a + 1] += aptr[a];
+    std::vector<int32_t> aorb(n_orb);
+    {
+        std::vector<int64_t> fill(aptr.begin(), aptr.end() - 1);
+        for (int32_t u = 0; u < n_orb; ++u) aorb[fill[orbital_atom[u]]++] = u;
+    }
+    adj_ptr.assign(n_orb + 1, 0);
+    adj_col.clear();
+    std::vector<int32_t> row;
+    for (int32_t u = 0; u < n_orb; ++u) {
+        const int32_t a = orbital_atom[u];
+        row.clear();
+        for (int64_t i = aptr[a]; i < aptr[a + 1]; ++i)
+            if (aorb[i] != u) row.push_back(aorb[i]);
+        for (int32_t b : anb[a])
+            for (int64_t i = aptr[b]; i < aptr[b + 1]; ++i) row.push_back(aorb[i]);
+        std::sort(row.begin(), row.end());
+        row.erase(std::unique(row.begin(), row.end()), row.end());
+        adj_col.insert(adj_col.end(), row.begin(), row.end());
+        adj_ptr[u + 1] = (int64_t)adj_col.size();
+    }
+}
+
+}  // namespace gsp2

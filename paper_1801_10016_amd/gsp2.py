@@ -100,6 +100,8 @@ SIGNATURES = {
     "gsp2_backward": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.POINTER(C.c_int8), C.c_int32, C.c_void_p,
                                 C.c_void_p, C.POINTER(gsp2_backward_info)]),
     "gsp2_plan_graph": (C.c_int, [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "gsp2_locality_graph": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double),
+                                      C.c_double, C.c_double, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "gsp2_partition_anneal": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(gsp2_anneal_options),
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
@@ -275,6 +277,20 @@ def gsp2_plan_graph(plan: Plan):
     _check(load().gsp2_plan_graph(plan.handle, _i64(adj_ptr), None))
     adj_col = np.empty(int(adj_ptr[-1]), dtype=np.int32)
     _check(load().gsp2_plan_graph(plan.handle, _i64(adj_ptr), _i32(adj_col)))
+    return adj_ptr, adj_col
+
+
+def gsp2_locality_graph(orbital_atom, xyz, radius: float, box: float = 0.0):
+    """Host CSR arrays (adj_ptr int64, adj_col int32) of the locality graph:
+    orbitals adjacent when their atoms are closer than radius."""
+    oa = np.ascontiguousarray(orbital_atom, dtype=np.int32)
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    lib = load()
+    adj_ptr = np.empty(oa.size + 1, dtype=np.int64)
+    args = (oa.size, _i32(oa), xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), float(radius), float(box))
+    _check(lib.gsp2_locality_graph(*args, _i64(adj_ptr), None))
+    adj_col = np.empty(int(adj_ptr[-1]), dtype=np.int32)
+    _check(lib.gsp2_locality_graph(*args, _i64(adj_ptr), _i32(adj_col)))
     return adj_ptr, adj_col
 
 

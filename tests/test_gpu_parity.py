@@ -280,3 +280,84 @@ def test_annealed_partition_runs_and_matches_its_cost():
     with g.gsp2_plan_create(Pd, 1e-4, new, 6) as plan:
         assert g.gsp2_plan_query(plan)[0]["sum_s3"] == c1
     _check_parity(s, 1e-4, 6, part=new)
+
+
+@pytest.mark.parametrize("which", ["empty", "full"])
+def test_degenerate_occupations(which):
+    # N_occ = 0 gives P = 0, N_occ = N gives P = I on P's pattern (one branch
+    # repeated until the trace reaches N_occ, where a tie takes 2X - X^2,
+    # which leaves 0 and I in place); the oracle agrees
+    from tests._gpu import run_gsp2
+    s = pins.water(32, 1)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 4, seed=0)
+    n_occ = 0.0 if which == "empty" else float(s.n)
+    ref = oracle.gsp2(s.H, Pp, 1e-3, part, 4, n_occ)
+    P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-3, part, 4, n_occ)
+    print(f"{which}: {run['n_products']} products, branches {run['alpha']}, Tr P = {run['trace']:.3e}", flush=True)
+    assert run["status"] == 0
+    if which == "full":
+        assert set(run["alpha"]) == {1}
+    want = ref.csc().toarray()
+    assert np.abs(P.toarray() - want).max() <= 1e-5
+    assert abs(run["trace"] - n_occ) <= 1e-4 * max(1.0, n_occ)
+
+
+def test_one_core_vertex_per_part():
+    # every part is a single core orbital with its halo: many tiny blocks,
+    # each padded to one 128 tile
+    s = pins.water(12, 4)
+    part = np.arange(s.n, dtype=np.int32)
+    _check_parity(s, 1e-3, s.n, part=part)
+
+
+def test_largest_checked_single_block():
+    # one part of 3,000 orbitals: a 24 x 24 grid of 128-tiles in one block,
+    # against the oracle's dense SP2
+    s = pins.water(500, 0)
+    part = np.zeros(s.n, dtype=np.int32)
+    P, run, ref = _check_parity(s, 1e-5, 1, part=part)
+
+
+def test_dense_block_beyond_the_lds_index_list():
+    # a single part of 9,000 orbitals: the gather's vertex list no longer fits
+    # LDS (8,192 entries) and is read from global memory.  No oracle runs at
+    # this size: the result is checked by properties of the projector,
+    # computed in FP64 on the GPU: trace, idempotency, commutation with H
+    import torch
+    import paper_1801_10016_amd as g
+    s = pins.water(1500, 0)
+    n = s.n
+    part = np.zeros(n, dtype=np.int32)
+    Hd = g.csr_to_device(s.H)
+    with g.gsp2_plan_create(Hd, 0.0, part, 1) as plan:
+        assert g.gsp2_plan_query(plan)[0]["max_s"] == n > 8192
+        P_val = torch.empty(n * n, dtype=torch.float32, device="cuda")
+        run = g.gsp2_density(plan, Hd, s.n_occ, P_val)
+        torch.cuda.synchronize()
+    P = P_val.double().view(n, n).t()          # CSC of one part: column j holds all rows in order
+    H = torch.as_tensor(s.H.toarray(), device="cuda")
+    tr = float(torch.trace(P))
+    idem = float(torch.linalg.matrix_norm(P @ P - P) / torch.linalg.matrix_norm(P))
+    comm = float(torch.linalg.matrix_norm(H @ P - P @ H) / (torch.linalg.matrix_norm(H) * torch.linalg.matrix_norm(P)))
+    print(f"N={n}: {run['n_products']} products, Tr P - N_occ = {tr - s.n_occ:.2e}, "
+          f"|P^2 - P|/|P| = {idem:.2e}, |[H,P]|/(|H||P|) = {comm:.2e}", flush=True)
+    assert run["status"] == 0
+    assert abs(tr - s.n_occ) <= 1e-2
+    assert idem <= 1e-4 and comm <= 1e-5
+
+
+def test_non_finite_or_flat_h_is_rejected():
+    import paper_1801_10016_amd as g
+    from tests._gpu import run_gsp2
+    s = pins.water(16, 0)
+    part = np.zeros(s.n, dtype=np.int32)
+    bad = s.H.tocsr().copy()
+    bad.data[3] = np.nan
+    with pytest.raises(g.Gsp2Error) as e:
+        run_gsp2(bad, s.H, 1e-5, part, 1, s.n_occ)
+    assert e.value.status == 1 and "Gershgorin" in str(e.value)
+    flat = sp.identity(s.n, format="csr") * 2.0          # eps_max == eps_min
+    with pytest.raises(g.Gsp2Error) as e:
+        run_gsp2(flat, s.H, 1e-5, part, 1, s.n_occ)
+    assert e.value.status == 1

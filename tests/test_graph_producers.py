@@ -1,11 +1,18 @@
-"""gsp2_partition_anneal (host, no GPU): simulated-annealing refinement of a
+"""Producers of the graph and partition (host, no GPU).
+
+gsp2_partition_anneal: simulated-annealing refinement of a
 partition for the cost of eq. (4), C = sum_k (c_k + h_k)^3.
 
 Pins: the cost the library reports for the partition it was given and for
 the one it returns equals the oracle's eq. (4) cost of the same partitions
 (exact integers); on graphs small enough to enumerate every partition, the
 annealer reaches the brute-force optimum; it never returns a worse
-partition, never empties a part, and is deterministic for a seed."""
+partition, never empties a part, and is deterministic for a seed.
+
+gsp2_locality_graph: the graph of the locality construction, against its
+definition evaluated by brute force over all atom pairs, and against the
+threshold of the distance-based stand-in for a previous P (equal by
+construction of the stand-in's radius)."""
 import itertools
 
 import numpy as np
@@ -114,3 +121,55 @@ def test_bad_arguments_are_refused():
         g.gsp2_partition_anneal(ptr, col, part_b, 2, cooling=1.5)
     with pytest.raises(g.Gsp2Error):
         g.gsp2_partition_anneal(ptr, col, part_b, 2, sweeps=-1)
+
+
+# -- locality construction of the graph -----------------------------------------
+
+def _brute_locality(system, radius):
+    """Adjacency by definition: orbitals on atoms closer than radius (minimum image)."""
+    oa = system.orbital_atom()
+    X = system.atoms
+    d = X[:, None, :] - X[None, :, :]
+    d -= system.box * np.round(d / system.box)
+    close = np.sqrt((d ** 2).sum(-1)) < radius            # includes each atom with itself
+    A = close[np.ix_(oa, oa)]
+    np.fill_diagonal(A, False)
+    return A
+
+
+@pytest.mark.parametrize("n_mol,radius", [(8, 3.0), (32, 4.5), (64, 7.0)])
+def test_locality_graph_matches_brute_force(n_mol, radius):
+    s = pins.water(n_mol, 0)
+    ptr, col = g.gsp2_locality_graph(s.orbital_atom(), s.atoms, radius, s.box)
+    A = sp.csr_matrix((np.ones(col.size), col, ptr), shape=(s.n, s.n)).toarray() != 0
+    want = _brute_locality(s, radius)
+    assert np.array_equal(A, want)
+    assert np.array_equal(A, A.T)
+    for u in range(s.n):                                   # rows ascending, no self loops
+        row = col[ptr[u]:ptr[u + 1]]
+        assert np.all(np.diff(row) > 0) and u not in row
+
+
+def test_locality_graph_is_the_thresholded_distance_stand_in():
+    # the stand-in for a previous P is 1e-3 exp(-(r - R3) / XI) for atoms at
+    # distance r: above tau exactly inside the radius R3 + XI ln(1e-3 / tau)
+    from synth.locality import surrogate_prev_density, surrogate_radius
+    s = pins.water(200, 2)
+    tau = 1e-4
+    Q = surrogate_prev_density(s, q_floor=tau / 2)
+    ref = oracle.threshold_graph(Q, tau)
+    ptr, col = g.gsp2_locality_graph(s.orbital_atom(), s.atoms, surrogate_radius(tau), s.box)
+    A = sp.csr_matrix((np.ones(col.size), col, ptr), shape=(s.n, s.n))
+    assert ((A != 0) != (ref != 0)).nnz == 0
+
+
+def test_locality_graph_open_boundaries_and_errors():
+    xyz = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [5.0, 0.0, 0.0]])
+    oa = np.array([0, 0, 1, 2], dtype=np.int32)             # two orbitals on atom 0
+    ptr, col = g.gsp2_locality_graph(oa, xyz, 1.5)
+    rows = [col[ptr[u]:ptr[u + 1]].tolist() for u in range(4)]
+    assert rows == [[1, 2], [0, 2], [0, 1], []]
+    with pytest.raises(g.Gsp2Error):
+        g.gsp2_locality_graph(oa, xyz, 0.0)
+    with pytest.raises(g.Gsp2Error):
+        g.gsp2_locality_graph(np.array([0, 3], dtype=np.int32), xyz, 1.0)
