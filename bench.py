@@ -69,9 +69,10 @@ def parse():
     ap.add_argument("--compare-steps", type=int, default=3)
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM counter calibration)")
-    ap.add_argument("--workload", choices=["water3500", "batch16"], default="water3500",
+    ap.add_argument("--workload", choices=["water3500", "batch16", "backward1000"], default="water3500",
                     help="water3500: one system (the default line); batch16: 16 independent systems of "
-                    "500-8,000 molecules, each one MD step on, in one batched plan")
+                    "500-8,000 molecules, each one MD step on, in one batched plan; backward1000: forward "
+                    "and reverse mode on 1,000 molecules, 32 parts, tau = 1e-3")
     ap.add_argument("--refine", type=int, default=None,
                     help="FP32 refinement products after the stop (default: 0, or 2 for batch16)")
     ap.add_argument("--no-alone", action="store_true", help="batch16: skip timing each system in a plan of its own")
@@ -175,6 +176,73 @@ def syrk_flops(sizes) -> float:
     entries, 2 s flops each."""
     s = np.asarray(sizes, dtype=np.float64)
     return float(np.sum(s * s * (s + 1.0)))
+
+
+def bench_backward(args, g, torch):
+    """Forward density matrix and reverse-mode pass (dL/dH for L = Tr(P W),
+    W random on P's pattern) on 1,000 molecules, 32 parts, tau = 1e-3."""
+    from synth.partition import uneven_spatial_partition
+    from synth.water import make_water
+    n_mol, n_parts, tau = 1000, 32, 1e-3
+    system = make_water(n_mol, seed=0)
+    n, n_occ = system.n, system.n_occ
+    stream = torch.cuda.Stream()
+    Hd = g.csr_to_device(system.H)
+    Pprev, boot = dense_bootstrap(g, torch, Hd, n, n_occ, stream)
+    part = uneven_spatial_partition(system, n_parts, seed=0)
+    with torch.cuda.stream(stream):
+        plan = g.gsp2_plan_create(Pprev, tau, part, n_parts, stream=stream)
+    del Pprev
+    info, _, sub_sizes = g.gsp2_plan_query(plan)
+    P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    W = torch.randn(info["nnz_P"], dtype=torch.float32, device="cuda", generator=gen)
+    with torch.cuda.stream(stream):
+        run = g.gsp2_density(plan, Hd, n_occ, P_val)
+        alphas = run["alpha"]
+        n_prod = run["n_products"]
+        dH = None
+        for _ in range(args.warmup):
+            g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, want_info=False)
+            dH, binfo = g.gsp2_backward(plan, Hd, alphas, W, dH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, want_info=False)
+        torch.cuda.synchronize()
+        fwd_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dH, binfo = g.gsp2_backward(plan, Hd, alphas, W, dH)
+        torch.cuda.synchronize()
+        bwd_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # matrix-core work of the pass: the forward replay to the checkpoints, the
+    # recomputation inside each segment, and two products per reverse step
+    m = len(alphas)
+    k = binfo["checkpoint_every"]
+    nseg = max(1, -(-m // k))
+    replay = (nseg - 1) * k + sum(max(0, min(k, m - j * k) - 1) for j in range(nseg))
+    unit = syrk_flops(sub_sizes)
+    flops = (replay + 2 * m) * unit
+    out = {
+        "metric": "ms per reverse-mode pass dL/dH (and per forward P) at 1,000 molecules",
+        "value": round(bwd_ms, 3), "unit": "ms/backward", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(bwd_ms, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{n_mol} water molecules ({n} orbitals), {n_parts} uneven parts, tau={tau:g}, "
+                               "L = Tr(P W) with W random on P's pattern",
+                   "n_products": m, "checkpoint_every": k, "s_min": info["min_s"], "s_max": info["max_s"]},
+        "forward_ms": round(fwd_ms, 3), "backward_over_forward": round(bwd_ms / fwd_ms, 3),
+        "backward_tflops": round(flops / (bwd_ms * 1e-3) / 1e12, 2),
+        "backward_tflops_convention": ("(forward replay + segment recomputation + 2 per reverse step) products "
+                                       "x sum_k s_k^2 (s_k + 1), over the pass's wall time"),
+        "backward_workspace_gib": round(binfo["workspace_bytes"] / 2**30, 3),
+        "previous_P": f"regular SP2 of H on the GPU ({boot['n_products']} products)",
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    plan.close()
+    return 0
 
 
 def bench_batch(args, g, torch):
@@ -318,6 +386,8 @@ def main():
         return copy_probe(torch, args.copy_probe_gib)
     if args.workload == "batch16":
         return bench_batch(args, g, torch)
+    if args.workload == "backward1000":
+        return bench_backward(args, g, torch)
     stream = torch.cuda.Stream()
     t = time.perf_counter()
     system = make_water(args.n_mol, seed=args.seed)
