@@ -165,7 +165,13 @@ def cpu_baseline(system, part, n_parts, tau, n_products, sub_sizes, n_sample):
     s3_sample = float(sum(sizes[k] ** 3 for k in pick))
     s3_all = float(np.sum(np.asarray(sub_sizes, dtype=np.float64) ** 3))
     ms = dt * 1e3 * s3_all / s3_sample
-    return {"value": ms, "unit": "ms/P", "cores": int(threads), "kind": "oracle",
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((line.split(":", 1)[1].strip() for line in f if line.startswith("model name")), model)
+    except OSError:
+        pass
+    return {"value": ms, "unit": "ms/P", "cores": int(threads), "kind": "oracle", "cpu_model": model,
             "sample": (f"FP64 numpy/OpenBLAS SP2 products of {len(pick)} of {n_parts} parts "
                        f"(s = {', '.join(str(int(sizes[k])) for k in pick)}), {n_products} products each, "
                        f"{dt:.1f} s, scaled by sum_k s_k^3 of the timed workload")}
