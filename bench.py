@@ -95,14 +95,17 @@ def dense_bootstrap(g, torch, Hd, n, n_occ, stream):
     return g.DeviceCSR(n, col_ptr, row_idx, P), run
 
 
-def counter_traffic(precision):
+def counter_traffic(precision, workload):
     """HBM bytes per product launch from the committed rocprofv3 counter record,
-    or None when the kernel or planner sources changed since it was taken."""
+    or None when the record was taken on another workload (molecules, parts,
+    tau, sum of s^3) or the kernel or planner sources changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sp2_step_counters.json")
     try:
         rec = json.load(open(path))[precision]
     except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("match") != workload:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -549,9 +552,11 @@ def main():
         "batched_gemm_tflops": round(n_prod * gemm_flops / (sp2_med * 1e-3) / 1e12, 2),
         "batched_gemm_tflops_convention": "n_products * sum_k 2 s_k^3 / SP2-phase time (GEMM convention)",
         "roofline": {
-            "bound": "mfma", "kernel": "k_sp2_step",
+            "bound": "mfma", "kernel": "k_sp2_step" if args.precision == "fp32" else "k_sp2_wide",
             "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": counter_traffic(args.precision),
+            "frac": round(achieved / peak, 4), "traffic": counter_traffic(
+                args.precision, {"n_mol": args.n_mol, "n_parts": args.n_parts, "tau": args.tau,
+                                 "sum_s3": info["sum_s3"]}),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "flops_per_launch": MFMA_PRODUCTS[args.precision] * syrk_flops, "avg_launch_ms": round(avg_prod_ms, 4),
             "flops_convention": "symmetric product: sum_k s_k^2 (s_k + 1) per launch (one launch = one product)",
