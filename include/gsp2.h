@@ -63,6 +63,9 @@ typedef enum {
                                   FP16 products accumulated in FP32, about as accurate as FP32
                                   products (the dropped B B term is 2^-22 relative) */
 } gsp2_precision;
+/* The 16-bit modes need every part's padded size (s_k rounded up to 128) to
+ * be at most 46,336, so that a part's operand matrix is under 4 GiB; larger
+ * plans get GSP2_E_UNSUPPORTED from gsp2_density for those modes. */
 
 /* Sparse matrix in CSR form.  All four arrays are device pointers. */
 typedef struct {

@@ -818,6 +818,9 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         if (o.precision != GSP2_PREC_FP32 && o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16 &&
             o.precision != GSP2_PREC_FP16X3)
             fail(GSP2_E_INVALID, "bad precision");
+        if (o.precision != GSP2_PREC_FP32 && plan->dp.max_s_pad > kMaxWidePad)
+            fail(GSP2_E_UNSUPPORTED, "16-bit products need every padded sub-problem size <= " +
+                                         std::to_string(kMaxWidePad));
         if (o.refine < 0 || o.refine > 8) fail(GSP2_E_INVALID, "refine must be in 0..8");
         rp.precision = o.precision;
         rp.refine = o.refine;

@@ -15,6 +15,9 @@ namespace gsp2 {
 constexpr int kTile = 128;
 constexpr int kKChunk = 32;
 constexpr int kTileWide = 256;      // product tile of 16-bit operands
+// 16-bit products address a part's operand matrix as one buffer of under
+// 4 GiB: s_pad^2 * 2 bytes < 2^32
+constexpr int kMaxWidePad = 46336;
 
 // XCDs of an MI355X: workgroup b of a launch runs on XCD b mod kXcds.
 constexpr int kXcds = 8;
