@@ -902,31 +902,50 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 #undef GSP2W_LOAD
 #undef GSP2W_STORE
 
-    // Epilogue: as in sp2_tile, over this wave's 4 x 4 blocks.
+    // Epilogue: as in sp2_tile, over this wave's 4 x 4 blocks, one 32-row
+    // band m at a time.  X_old is only needed for X' = 2X - Y; each lane's
+    // four rows of one column are read as one float4 at the mirrored
+    // position (X is symmetric), all sixteen before any of the band's
+    // stores, so the wave waits on memory once per band rather than once per
+    // element group.  The mirrored writes leave the registers as float4
+    // columns; the direct writes go through this wave's own 16 KB of LDS
+    // (free after the last chunk's barrier), so that they too are 16-byte
+    // row pieces: 2 rows x 512 contiguous bytes per store instruction.
+    constexpr int kBandRow = 132;               // floats per LDS band row: 128 + 4 pad
+    float *band = reinterpret_cast<float *>(lds_base) + wave * 32 * kBandRow;
     double tY = 0.0, tX = 0.0;
     if (active) {
+        const bool upd = alpha > 0.0f;
+        float4 xo[4][4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
+            if (upd) {
+#pragma unroll
+                for (int nn = 0; nn < 4; ++nn) {
+                    const int cg = J0 + wc * 128 + nn * 32 + l32;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int rg0 = I0 + wr * 128 + m * 32 + g * 8 + kh * 4;
+                        xo[nn][g] = *reinterpret_cast<const float4 *>(X + (int64_t)cg * ld + rg0);
+                    }
+                }
+            }
 #pragma unroll
             for (int nn = 0; nn < 4; ++nn) {
                 const int cg = J0 + wc * 128 + nn * 32 + l32;
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int rg0 = I0 + wr * 128 + m * 32 + g * 8 + kh * 4;
+                    const float4 x4 = xo[nn][g];
+                    const float xov[4] = {x4.x, x4.y, x4.z, x4.w};
                     float xn[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const int rg = rg0 + e;
                         const float y = acc[m][nn][4 * g + e];
-                        const float xo = X[(int64_t)rg * ld + cg];
-                        const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
+                        const float v = upd ? (2.0f * xov[e] - y) : y;
                         xn[e] = v;
-                        Xn[(int64_t)rg * ld + cg] = v;
-                        const Op h = static_cast<Op>(v);
-                        Xnop[(int64_t)rg * ld + cg] = h;
-                        if constexpr (kSplit)
-                            Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
-                        if (diag && rg == cg && rg < pd.c) {
+                        band[(g * 8 + kh * 4 + e) * kBandRow + nn * 32 + l32] = v;
+                        if (diag && rg0 + e == cg && cg < pd.c) {
                             tY += static_cast<double>(y);
                             tX += static_cast<double>(v);
                         }
@@ -945,6 +964,27 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
                             *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
                         }
                     }
+                }
+            }
+            // the band's rows back from LDS: lane (r2, c4) takes row 2 i + r2,
+            // columns 4 c4 .. 4 c4 + 3 (the wave's own LDS, written above)
+            const int c4 = lane & 31, r2 = lane >> 5;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int r = 2 * i + r2;
+                const float4 v4 = *reinterpret_cast<const float4 *>(band + r * kBandRow + c4 * 4);
+                const int64_t o = (int64_t)(I0 + wr * 128 + m * 32 + r) * ld + J0 + wc * 128 + c4 * 4;
+                *reinterpret_cast<float4 *>(Xn + o) = v4;
+                const float xv[4] = {v4.x, v4.y, v4.z, v4.w};
+                union { Op h[4]; uint2 u; } pk, pl;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xv[e]);
+                *reinterpret_cast<uint2 *>(Xnop + o) = pk.u;
+                if constexpr (kSplit) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        pl.h[e] = static_cast<Op>((xv[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
+                    *reinterpret_cast<uint2 *>(Xnlo + o) = pl.u;
                 }
             }
         }
