@@ -727,7 +727,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restri
 // SIMD, each wave a 128 x 128 sub-tile as 4 x 4 blocks of 32 x 32 MFMA
 // output (256 accumulator registers): 8 LDS fragment reads feed 16 MFMAs.
 // Two LDS buffers of 2 x 256 rows x 144 B (147,456 bytes) hold one
-// workgroup per CU.  Tiles step by 256 over the part; where s_pad is an odd
+// workgroup per CU; operands arrive by buffer loads two chunks ahead, in
+// two register sets, and are stored into LDS between the MFMAs of the
+// chunk before.  Tiles step by 256 over the part; where s_pad is an odd
 // multiple of 128, the last tile row and column are half empty: those rows
 // are neither loaded nor computed.  A diagonal tile's trace partials go to
 // the two 128-tile slots it covers, so the control kernels are those of the
@@ -798,7 +800,7 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
     // the scale by 2^-11, nk of H H.  Both panels are staged for every
     // chunk, diagonal tiles included.
     const int nk = ld / kK;
-    uint4 pa[8], pb[8];
+    uint4 pa[2][8], pb[2][8];
 #define GSP2W_SRC(c, ra, rb, kb)                                                                   \
     do {                                                                                           \
         if constexpr (kSplit) {                                                                    \
@@ -812,79 +814,107 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
     } while (0)
     // every pass is loaded and stored, so no register keeps a value from an
     // earlier chunk; a half-empty panel repeats its first 128 rows in passes
-    // 4 to 7 (in bounds; those LDS rows are not read)
-#define GSP2W_LOAD(ra, rb, kb)                                                                     \
+    // 4 to 7 (in bounds; those LDS rows are not read).  Two register sets:
+    // chunk c + 2 is loaded while chunk c + 1 waits to be stored.
+#define GSP2W_LOAD(S, ra, rb, kb)                                                                  \
     do {                                                                                           \
         _Pragma("unroll") for (int p_ = 0; p_ < 8; ++p_) {                                         \
-            pa[p_] = __builtin_bit_cast(                                                           \
+            pa[S][p_] = __builtin_bit_cast(                                                        \
                 uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, offA, passA[p_] + (kb), 0));      \
-            pb[p_] = __builtin_bit_cast(                                                           \
+            pb[S][p_] = __builtin_bit_cast(                                                        \
                 uint4, __builtin_amdgcn_raw_buffer_load_b128(rb, offB, passB[p_] + (kb), 0));      \
         }                                                                                          \
     } while (0)
-#define GSP2W_STORE(b)                                                                             \
+#define GSP2W_STORE(b, S)                                                                          \
     do {                                                                                           \
         uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;                                                \
         uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                                \
         _Pragma("unroll") for (int p_ = 0; p_ < 8; ++p_) {                                         \
-            As_[p_ * 32 * kLdsRow] = pa[p_];                                                       \
-            Bs_[p_ * 32 * kLdsRow] = pb[p_];                                                       \
+            As_[p_ * 32 * kLdsRow] = pa[S][p_];                                                    \
+            Bs_[p_ * 32 * kLdsRow] = pb[S][p_];                                                    \
         }                                                                                          \
     } while (0)
 
-    // one pipelined pass over chunks [c0, c1): the next chunk's loads are in
-    // flight while the current one feeds the MFMAs
+    // the MFMAs of one chunk from LDS buffer buf, with the stores of the
+    // next chunk (register set sa, sb, loaded a chunk earlier) into the
+    // other buffer folded into its steps 1 and 2.  Every wave runs the MFMAs
+    // (a branch around them would make the accumulators flow through
+    // VGPRs); an inactive wave's results are discarded.  The fragments of
+    // step q + 1 are read while the MFMAs of step q run, one read (and in
+    // steps 1 and 2 one store) after each of its first eight MFMAs; a
+    // scheduling barrier per step keeps the compiler from moving memory
+    // operations across steps.
+    auto compute = [&](int buf, const uint4 (&sa)[8], const uint4 (&sb)[8]) {
+        const uint4 *Asb = lds(buf, 0);
+        const uint4 *Bsb = lds(buf, 1);
+        uint4 *As_ = lds(buf ^ 1, 0) + lr * kLdsRow + lw;
+        uint4 *Bs_ = lds(buf ^ 1, 1) + lr * kLdsRow + lw;
+        uint4 fa[2][4], fb[2][4];
+        auto frags = [&](int q, uint4 *fa_, uint4 *fb_) {
+            const int w = 2 * q + kh;           // k = 16 q + 8 kh + e
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                fa_[m] = Asb[(wr * 128 + m * 32 + l32) * kLdsRow + w];
+                fb_[m] = Bsb[(wc * 128 + m * 32 + l32) * kLdsRow + w];
+            }
+        };
+        frags(0, fa[0], fb[0]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (q + 1 < 4) frags(q + 1, fa[(q + 1) & 1], fb[(q + 1) & 1]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int nn = 0; nn < 4; ++nn)
+                    acc[m][nn] = mfma_chunk_q(fa[q & 1][m], fb[q & 1][nn], acc[m][nn], Op{});
+            const bool st = q == 1 || q == 2;
+            if (st) {
+                const int p0 = (q - 1) * 4;     // passes 0-3 in step 1, 4-7 in step 2
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    As_[(p0 + p) * 32 * kLdsRow] = sa[p0 + p];
+                    Bs_[(p0 + p) * 32 * kLdsRow] = sb[p0 + p];
+                }
+            }
+            if (q + 1 < 4) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // one MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);       // one LDS read
+                    if (st) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    // one pass over chunks [c0, c1): chunk c computes from LDS buffer
+    // (c - c0) & 1 while chunk c + 1 waits in registers to be stored into
+    // the other buffer and chunk c + 2 is being loaded.  Chunk counts are
+    // even (s_pad is a multiple of 128, a chunk 64 columns), so the loop
+    // takes chunks in pairs and every MFMA block is unconditional.  The last
+    // pair stores its final chunk a second time into the buffer it already
+    // occupies, which no wave reads during that step.
     auto run = [&](int c0, int c1) {
         __amdgpu_buffer_rsrc_t ra, rb;
         uint32_t kb;
         GSP2W_SRC(c0, ra, rb, kb);
-        GSP2W_LOAD(ra, rb, kb);
-        GSP2W_STORE(0);
+        GSP2W_LOAD(0, ra, rb, kb);
+        GSP2W_STORE(0, 0);
+        GSP2W_SRC(c0 + 1, ra, rb, kb);
+        GSP2W_LOAD(1, ra, rb, kb);
         __syncthreads();
-        for (int kc = c0; kc < c1; ++kc) {
-            const int buf = (kc - c0) & 1;
-            if (kc + 1 < c1) {
-                GSP2W_SRC(kc + 1, ra, rb, kb);
-                GSP2W_LOAD(ra, rb, kb);
-            }
-            // every wave runs the MFMAs (a branch around them would make the
-            // accumulators flow through VGPRs); an inactive wave's results
-            // are discarded
-            const uint4 *Asb = lds(buf, 0);
-            const uint4 *Bsb = lds(buf, 1);
-            // the fragments of step q + 1 are read while the MFMAs of step q
-            // run, one read after each of its first eight MFMAs; a scheduling
-            // barrier per step keeps the compiler from moving reads across
-            // steps
-            uint4 fa[2][4], fb[2][4];
-            auto frags = [&](int q, uint4 *fa_, uint4 *fb_) {
-                const int w = 2 * q + kh;       // k = 16 q + 8 kh + e
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    fa_[m] = Asb[(wr * 128 + m * 32 + l32) * kLdsRow + w];
-                    fb_[m] = Bsb[(wc * 128 + m * 32 + l32) * kLdsRow + w];
-                }
-            };
-            frags(0, fa[0], fb[0]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                if (q + 1 < 4) frags(q + 1, fa[(q + 1) & 1], fb[(q + 1) & 1]);
-#pragma unroll
-                for (int m = 0; m < 4; ++m)
-#pragma unroll
-                    for (int nn = 0; nn < 4; ++nn)
-                        acc[m][nn] = mfma_chunk_q(fa[q & 1][m], fb[q & 1][nn], acc[m][nn], Op{});
-                if (q + 1 < 4) {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) {
-                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
-                        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
-                    }
-                    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            if (kc + 1 < c1) GSP2W_STORE(buf ^ 1);
+        for (int kc = c0; kc < c1; kc += 2) {
+            // past the end the last chunk is loaded again, so that every
+            // load is unconditional and the waits before the stores count
+            // exactly the loads issued after them
+            GSP2W_SRC(min(kc + 2, c1 - 1), ra, rb, kb);
+            GSP2W_LOAD(0, ra, rb, kb);
+            compute(0, pa[1], pb[1]);
+            __syncthreads();
+            GSP2W_SRC(min(kc + 3, c1 - 1), ra, rb, kb);
+            GSP2W_LOAD(1, ra, rb, kb);
+            compute(1, pa[0], pb[0]);
             __syncthreads();
         }
     };
