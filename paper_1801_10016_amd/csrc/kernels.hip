@@ -843,25 +843,32 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
     // step q + 1 are read while the MFMAs of step q run, one read (and in
     // steps 1 and 2 one store) after each of its first eight MFMAs; a
     // scheduling barrier per step keeps the compiler from moving memory
-    // operations across steps.
+    // operations across steps.  The workgroup barrier sits before step 3:
+    // by then every wave has stored its part of the next chunk and read the
+    // last fragments of this one, so step 3's MFMAs cover the reads of the
+    // next chunk's step-0 fragments.
+    uint4 fa[2][4], fb[2][4];
+    auto frags = [&](int b, int q, uint4 *fa_, uint4 *fb_) {
+        const uint4 *Asb = lds(b, 0);
+        const uint4 *Bsb = lds(b, 1);
+        const int w = 2 * q + kh;               // k = 16 q + 8 kh + e
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            fa_[m] = Asb[(wr * 128 + m * 32 + l32) * kLdsRow + w];
+            fb_[m] = Bsb[(wc * 128 + m * 32 + l32) * kLdsRow + w];
+        }
+    };
     auto compute = [&](int buf, const uint4 (&sa)[8], const uint4 (&sb)[8]) {
-        const uint4 *Asb = lds(buf, 0);
-        const uint4 *Bsb = lds(buf, 1);
         uint4 *As_ = lds(buf ^ 1, 0) + lr * kLdsRow + lw;
         uint4 *Bs_ = lds(buf ^ 1, 1) + lr * kLdsRow + lw;
-        uint4 fa[2][4], fb[2][4];
-        auto frags = [&](int q, uint4 *fa_, uint4 *fb_) {
-            const int w = 2 * q + kh;           // k = 16 q + 8 kh + e
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                fa_[m] = Asb[(wr * 128 + m * 32 + l32) * kLdsRow + w];
-                fb_[m] = Bsb[(wc * 128 + m * 32 + l32) * kLdsRow + w];
-            }
-        };
-        frags(0, fa[0], fb[0]);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (q + 1 < 4) frags(q + 1, fa[(q + 1) & 1], fb[(q + 1) & 1]);
+            if (q + 1 < 4) {
+                frags(buf, q + 1, fa[(q + 1) & 1], fb[(q + 1) & 1]);
+            } else {
+                __syncthreads();
+                frags(buf ^ 1, 0, fa[0], fb[0]);
+            }
 #pragma unroll
             for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -876,15 +883,13 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
                     Bs_[(p0 + p) * 32 * kLdsRow] = sb[p0 + p];
                 }
             }
-            if (q + 1 < 4) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // one MFMA
-                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);       // one LDS read
-                    if (st) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write
-                }
-                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+            for (int i = 0; i < 8; ++i) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);       // one LDS read
+                if (st) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write
             }
+            __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
             __builtin_amdgcn_sched_barrier(0);
         }
     };
@@ -894,16 +899,20 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
     // even (s_pad is a multiple of 128, a chunk 64 columns), so the loop
     // takes chunks in pairs and every MFMA block is unconditional.  The last
     // pair stores its final chunk a second time into the buffer it already
-    // occupies, which no wave reads during that step.
+    // occupies, which no wave reads during that step, and its last step
+    // reads fragments that are not used.  The barriers at entry and exit
+    // keep LDS reuse (a second pass, the epilogue) clear of these reads.
     auto run = [&](int c0, int c1) {
         __amdgpu_buffer_rsrc_t ra, rb;
         uint32_t kb;
+        __syncthreads();
         GSP2W_SRC(c0, ra, rb, kb);
         GSP2W_LOAD(0, ra, rb, kb);
         GSP2W_STORE(0, 0);
         GSP2W_SRC(c0 + 1, ra, rb, kb);
         GSP2W_LOAD(1, ra, rb, kb);
         __syncthreads();
+        frags(0, 0, fa[0], fb[0]);
         for (int kc = c0; kc < c1; kc += 2) {
             // past the end the last chunk is loaded again, so that every
             // load is unconditional and the waits before the stores count
@@ -911,12 +920,11 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
             GSP2W_SRC(min(kc + 2, c1 - 1), ra, rb, kb);
             GSP2W_LOAD(0, ra, rb, kb);
             compute(0, pa[1], pb[1]);
-            __syncthreads();
             GSP2W_SRC(min(kc + 3, c1 - 1), ra, rb, kb);
             GSP2W_LOAD(1, ra, rb, kb);
             compute(1, pa[0], pb[0]);
-            __syncthreads();
         }
+        __syncthreads();
     };
     if constexpr (kSplit) {
         run(0, 2 * nk);                         // cross terms H L and L H
