@@ -837,11 +837,11 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 
     // the MFMAs of one chunk from LDS buffer buf, with the stores of the
     // next chunk (register set sa, sb, loaded a chunk earlier) into the
-    // other buffer folded into its steps 1 and 2.  Every wave runs the MFMAs
+    // other buffer folded into its steps 0 to 2.  Every wave runs the MFMAs
     // (a branch around them would make the accumulators flow through
     // VGPRs); an inactive wave's results are discarded.  The fragments of
     // step q + 1 are read while the MFMAs of step q run, one read (and in
-    // steps 1 and 2 one store) after each of its first eight MFMAs; a
+    // steps 0 to 2 up to one store) after each of its first eight MFMAs; a
     // scheduling barrier per step keeps the compiler from moving memory
     // operations across steps.  The workgroup barrier sits before step 3:
     // by then every wave has stored its part of the next chunk and read the
@@ -874,20 +874,18 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 #pragma unroll
                 for (int nn = 0; nn < 4; ++nn)
                     acc[m][nn] = mfma_chunk_q(fa[q & 1][m], fb[q & 1][nn], acc[m][nn], Op{});
-            const bool st = q == 1 || q == 2;
-            if (st) {
-                const int p0 = (q - 1) * 4;     // passes 0-3 in step 1, 4-7 in step 2
+            // passes 0-2 in step 0, 3-5 in step 1, 6-7 in step 2
+            const int p0 = 3 * q, np = q < 2 ? 3 : (q == 2 ? 2 : 0);
 #pragma unroll
-                for (int p = 0; p < 4; ++p) {
-                    As_[(p0 + p) * 32 * kLdsRow] = sa[p0 + p];
-                    Bs_[(p0 + p) * 32 * kLdsRow] = sb[p0 + p];
-                }
+            for (int p = 0; p < np; ++p) {
+                As_[(p0 + p) * 32 * kLdsRow] = sa[p0 + p];
+                Bs_[(p0 + p) * 32 * kLdsRow] = sb[p0 + p];
             }
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);       // one MFMA
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);       // one LDS read
-                if (st) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);   // one LDS write
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);                 // one MFMA
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);                 // one LDS read
+                if (i < 2 * np) __builtin_amdgcn_sched_group_barrier(0x200, 1, 0); // one LDS write
             }
             __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
             __builtin_amdgcn_sched_barrier(0);
