@@ -198,12 +198,22 @@ __global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// a5: gather + X0 (eq. (1)).  One workgroup per chunk of rows of one part;
-// every row of the padded block (s_pad wide) is written exactly once, built
-// in LDS so the HBM writes are whole coalesced rows.
+// a5: gather + X0 (eq. (1)).  One workgroup per chunk of rows of one part,
+// each wave building one row at a time in its own LDS segment, so that the
+// four waves work on four rows without workgroup barriers; every row of the
+// padded block (s_pad wide) is written exactly once, as whole coalesced
+// rows.
 // ---------------------------------------------------------------------------
 constexpr int kGatherLdsIdx = 8192;    // vertex list held in LDS up to this size
-constexpr int kGatherChunk = 8192;     // row segment built in LDS per pass
+constexpr int kGatherChunk = 2048;     // row segment built in LDS per wave and pass
+
+// Orders a wave's LDS accesses: writes by any lane before the call are seen
+// by reads of any lane after it.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ int find_sorted(const int32_t *a, int n, int32_t key) {
     int lo = 0, hi = n;
@@ -251,7 +261,8 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
                                                       const RunState *__restrict__ st_all,
                                                       double *__restrict__ x0_partials) {
     __shared__ int32_t idx_s[kGatherLdsIdx];
-    __shared__ float row_s[kGatherChunk];
+    __shared__ float4 row_s4[kBlock / kWave][kGatherChunk / 4];
+    __shared__ double tr_s[kBlock / kWave];
     const RowChunk ch = chunks[blockIdx.x];
     const PartDesc pd = parts[ch.part];
     const RunState *st = st_all + pd.sys;
@@ -267,19 +278,23 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
     const double inv = 1.0 / (emax - emin);
     const int ld = pd.s_pad;
     float *Xp = X + pd.x_off;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    float4 *row4 = row_s4[wave];
+    float *row_s = reinterpret_cast<float *>(row4);
+    const int prec = st->precision;
     double tr = 0.0;
-    for (int r = ch.r0; r < ch.r1; ++r) {
+    for (int r = ch.r0 + wave; r < ch.r1; r += kBlock / kWave) {
         const bool real = r < pd.s;
         const int64_t g = real ? idx[r] : -1;
         const int64_t hb = real ? row_ptr[g] : 0, he = real ? row_ptr[g + 1] : 0;
         for (int c0 = 0; c0 < ld; c0 += kGatherChunk) {
-            const int cw = min(kGatherChunk, ld - c0);
-            for (int i = threadIdx.x; i < cw; i += kBlock) row_s[i] = 0.0f;
-            __syncthreads();
-            if (real && threadIdx.x == 0 && r >= c0 && r < c0 + cw)
+            const int cw = min(kGatherChunk, ld - c0);   // a multiple of 128
+            for (int i = lane; i < cw / 4; i += kWave) row4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            wave_lds_sync();
+            if (real && lane == 0 && r >= c0 && r < c0 + cw)
                 row_s[r - c0] = static_cast<float>(emax * inv);       // H_gg = 0 if not stored
-            __syncthreads();
-            for (int64_t e = hb + threadIdx.x; e < he; e += kBlock) {
+            wave_lds_sync();
+            for (int64_t e = hb + lane; e < he; e += kWave) {
                 const int32_t cg = col[e];
                 int q = find_sorted(idx, pd.c, cg);
                 if (q < 0) {
@@ -292,25 +307,29 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
                     row_s[q - c0] = static_cast<float>(x);
                 }
             }
-            __syncthreads();
-            if (real && r < pd.c && threadIdx.x == 0 && r >= c0 && r < c0 + cw)
+            wave_lds_sync();
+            if (real && r < pd.c && lane == 0 && r >= c0 && r < c0 + cw)
                 tr += static_cast<double>(row_s[r - c0]);
             float4 *dst = reinterpret_cast<float4 *>(Xp + (int64_t)r * ld + c0);
-            const float4 *src = reinterpret_cast<const float4 *>(row_s);
-            for (int i = threadIdx.x; i < cw / 4; i += kBlock) dst[i] = src[i];
-            if (Xs) {
-                const int prec = st->precision;
-                uint2 *dsh = reinterpret_cast<uint2 *>(Xs + pd.x_off + (int64_t)r * ld + c0);
-                for (int i = threadIdx.x; i < cw / 4; i += kBlock) dsh[i] = pack4(src[i], prec);
+            uint2 *dsh = Xs ? reinterpret_cast<uint2 *>(Xs + pd.x_off + (int64_t)r * ld + c0) : nullptr;
+            uint2 *dlo = Xlo ? reinterpret_cast<uint2 *>(Xlo + pd.x_off + (int64_t)r * ld + c0) : nullptr;
+            for (int i = lane; i < cw / 4; i += kWave) {
+                const float4 v = row4[i];
+                dst[i] = v;
+                if (dsh) dsh[i] = pack4(v, prec);
+                if (dlo) dlo[i] = pack4_fp16_lo(v);
             }
-            if (Xlo) {
-                uint2 *dlo = reinterpret_cast<uint2 *>(Xlo + pd.x_off + (int64_t)r * ld + c0);
-                for (int i = threadIdx.x; i < cw / 4; i += kBlock) dlo[i] = pack4_fp16_lo(src[i]);
-            }
-            __syncthreads();
+            wave_lds_sync();                             // reads done before the next zeroing
         }
     }
-    if (threadIdx.x == 0) x0_partials[blockIdx.x] = tr;
+    // one partial per workgroup, the waves' sums added in a fixed order
+    if (lane == 0) tr_s[wave] = tr;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += tr_s[w];
+        x0_partials[blockIdx.x] = t;
+    }
 }
 
 // ---------------------------------------------------------------------------
