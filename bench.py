@@ -564,6 +564,13 @@ def main():
         "phase_ms": {"setup": round(statistics.median(setup), 3), "sp2": round(sp2_med, 3),
                      "scatter": round(statistics.median(scatter), 3),
                      "event_total_median": round(statistics.median(totals), 3)},
+        # the analogue of the paper's linear-algebra-only time against the whole step
+        "time_split": {"products_ms": round(sum(product_ms) / args.steps, 3),
+                       "other_ms": round(statistics.median(totals) - sum(product_ms) / args.steps, 3),
+                       "products_share": round(sum(product_ms) / args.steps / statistics.median(totals), 4),
+                       "convention": "event time of the product launches (matrix products with their fused "
+                                     "update and trace partials) against the rest of one P: Gershgorin, gather, "
+                                     "branch decisions, scatter and launch gaps"},
         "precision_compare": compare,
         "plan_ms": round(plan_s * 1e3, 1),
         "plan_info": {k: info[k] for k in ("nnz_graph", "nnz_P", "sum_s", "workspace_bytes")},
