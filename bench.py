@@ -354,7 +354,7 @@ def bench_batch(args, g, torch):
         "aggregate_tflops": round(total_flops / (float(np.sum(per_launch)) * 1e-3) / 1e12, 2),
         "aggregate_tflops_convention": "symmetric-product flops of every system in every launch it took part in "
                                        "/ summed product-kernel time",
-        "roofline": {"bound": "mfma", "kernel": f"k_sp2_step<{precision}>", "achieved": round(main_tf, 2),
+        "roofline": {"bound": "mfma", "kernel": "k_sp2_step<fp32>" if precision == "fp32" else f"k_sp2_wide<{precision}>", "achieved": round(main_tf, 2),
                      "peak": peak_main, "unit": "TFLOP/s", "frac": round(main_tf / peak_main, 4), "traffic": None,
                      "refine_kernel_tflops": round(ref_flops / (ref_ms * 1e-3) / 1e12, 2) if ref_ms > 0 else None},
         "event_total_ms_median": round(statistics.median(totals), 3),
