@@ -493,7 +493,6 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             for (int x = 0; x < kXcds; ++x)
                 plan->tiles_w.push_back(q < lists_w[x].size() ? lists_w[x][q] : TileDesc{-1, 0, 0, -1});
         plan->n_diag = slot;
-        constexpr int kRowsPerChunk = 16;
         for (int32_t y = 0; y < n_sys; ++y) {
             for (int32_t k : sys_parts[y])
                 for (int r0 = 0; r0 < plan->desc[k].s_pad; r0 += kRowsPerChunk)

@@ -18,6 +18,9 @@ constexpr int kTileWide = 256;      // product tile of 16-bit operands
 // 16-bit products address a part's operand matrix as one buffer of under
 // 4 GiB: s_pad^2 * 2 bytes < 2^32
 constexpr int kMaxWidePad = 46336;
+// rows per gather chunk (one workgroup each); also the row block of the
+// fixup after 16-bit products.  Divides 128, so chunks never straddle s_pad.
+constexpr int kRowsPerChunk = 16;
 
 // XCDs of an MI355X: workgroup b of a launch runs on XCD b mod kXcds.
 constexpr int kXcds = 8;

@@ -959,13 +959,19 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 
     // Epilogue: as in sp2_tile, over this wave's 4 x 4 blocks, one 32-row
     // band m at a time.  X_old is only needed for X' = 2X - Y; each lane's
-    // four rows of one column are read as one float4 at the mirrored
-    // position (X is symmetric), all sixteen before any of the band's
-    // stores, so the wave waits on memory once per band rather than once per
-    // element group.  The mirrored writes leave the registers as float4
-    // columns; the direct writes go through this wave's own 16 KB of LDS
-    // (free after the last chunk's barrier), so that they too are 16-byte
-    // row pieces: 2 rows x 512 contiguous bytes per store instruction.
+    // four rows of one column are read at the mirrored position (X is
+    // symmetric), all sixteen reads before any of the band's stores, so the
+    // wave waits on memory once per band rather than once per element group.
+    // The mirrored writes leave the registers as float4 columns; the direct
+    // writes go through this wave's own 16 KB of LDS (free after the last
+    // chunk's barrier), so that they too are 16-byte row pieces: 2 rows x
+    // 512 contiguous bytes per store instruction.
+    //
+    // The FP32 master is not written in full during the 16-bit products:
+    // plain operands write it on the diagonal tiles and at the mirrored
+    // (lower) positions only, which is all the next product reads; split
+    // operands do not write it at all and read X_old as hi + 2^-11 lo.  The
+    // fixup after the last product completes it (k_wide_fixup).
     constexpr int kBandRow = 132;               // floats per LDS band row: 128 + 4 pad
     float *band = reinterpret_cast<float *>(lds_base) + wave * 32 * kBandRow;
     double tY = 0.0, tX = 0.0;
@@ -981,7 +987,18 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const int rg0 = I0 + wr * 128 + m * 32 + g * 8 + kh * 4;
-                        xo[nn][g] = *reinterpret_cast<const float4 *>(X + (int64_t)cg * ld + rg0);
+                        if constexpr (kSplit) {
+                            union { uint2 u; Op h[4]; } hi, lo;
+                            hi.u = *reinterpret_cast<const uint2 *>(Xop + (int64_t)cg * ld + rg0);
+                            lo.u = *reinterpret_cast<const uint2 *>(Xlo + (int64_t)cg * ld + rg0);
+                            xo[nn][g] = make_float4(
+                                static_cast<float>(hi.h[0]) + static_cast<float>(lo.h[0]) * 0x1p-11f,
+                                static_cast<float>(hi.h[1]) + static_cast<float>(lo.h[1]) * 0x1p-11f,
+                                static_cast<float>(hi.h[2]) + static_cast<float>(lo.h[2]) * 0x1p-11f,
+                                static_cast<float>(hi.h[3]) + static_cast<float>(lo.h[3]) * 0x1p-11f);
+                        } else {
+                            xo[nn][g] = *reinterpret_cast<const float4 *>(X + (int64_t)cg * ld + rg0);
+                        }
                     }
                 }
             }
@@ -1006,8 +1023,10 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
                         }
                     }
                     if (!diag) {
-                        const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
-                        *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
+                        if constexpr (!kSplit) {
+                            const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
+                            *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
+                        }
                         union { Op h[4]; uint2 u; } pk, pl;
 #pragma unroll
                         for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
@@ -1029,7 +1048,7 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
                 const int r = 2 * i + r2;
                 const float4 v4 = *reinterpret_cast<const float4 *>(band + r * kBandRow + c4 * 4);
                 const int64_t o = (int64_t)(I0 + wr * 128 + m * 32 + r) * ld + J0 + wc * 128 + c4 * 4;
-                *reinterpret_cast<float4 *>(Xn + o) = v4;
+                if (!kSplit && diag) *reinterpret_cast<float4 *>(Xn + o) = v4;
                 const float xv[4] = {v4.x, v4.y, v4.z, v4.w};
                 union { Op h[4]; uint2 u; } pk, pl;
 #pragma unroll
@@ -1078,6 +1097,61 @@ __global__ __launch_bounds__(kBlockW, 1) void k_sp2_wide(const TileDesc *__restr
     if (st->done || st->phase != 0) return;
     sp2_tile_wide<Op, kSplit>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, lo0, lo1,
                               diag_partials, lds_w);
+}
+
+// After the last 16-bit product of the main phase: complete the FP32 master
+// of each system's result buffer (the one refinement starts from, or the
+// scatter reads).  One workgroup per chunk of 16 rows of one part.  Plain
+// 16-bit products left the upper triangle outside the diagonal tiles stale:
+// row r takes X[r][c] = X[c][r] for c > r, each thread one column c, reading
+// the 16 rows' values of row c as 64 contiguous bytes.  Split products left
+// FP32 X unwritten: X = hi + 2^-11 lo, in the operand copies' rounding.
+template <typename Op, bool kSplit>
+__global__ __launch_bounds__(kBlock) void k_wide_fixup(const PartDesc *__restrict__ parts,
+                                                       const RowChunk *__restrict__ chunks,
+                                                       float *__restrict__ buf0, float *__restrict__ buf1,
+                                                       const Op *__restrict__ hi0, const Op *__restrict__ hi1,
+                                                       const Op *__restrict__ lo0, const Op *__restrict__ lo1,
+                                                       const RunState *__restrict__ st_all) {
+    const RowChunk ch = chunks[blockIdx.x];
+    const PartDesc pd = parts[ch.part];
+    const RunState *st = st_all + pd.sys;
+    if (st->status == GSP2_E_INVALID || st->status == GSP2_E_HIP) return;
+    const int b = st->phase == 1 ? st->cur : st->result_buf;
+    float *X = (b ? buf1 : buf0) + pd.x_off;
+    const int ld = pd.s_pad;
+    if constexpr (kSplit) {
+        const Op *H = (b ? hi1 : hi0) + pd.x_off;
+        const Op *L = (b ? lo1 : lo0) + pd.x_off;
+        for (int r = ch.r0; r < ch.r1; ++r) {
+            const uint2 *h4 = reinterpret_cast<const uint2 *>(H + (int64_t)r * ld);
+            const uint2 *l4 = reinterpret_cast<const uint2 *>(L + (int64_t)r * ld);
+            float4 *x4 = reinterpret_cast<float4 *>(X + (int64_t)r * ld);
+            for (int i = threadIdx.x; i < ld / 4; i += kBlock) {
+                union { uint2 u; Op h[4]; } a, c;
+                a.u = h4[i];
+                c.u = l4[i];
+                x4[i] = make_float4(static_cast<float>(a.h[0]) + static_cast<float>(c.h[0]) * 0x1p-11f,
+                                    static_cast<float>(a.h[1]) + static_cast<float>(c.h[1]) * 0x1p-11f,
+                                    static_cast<float>(a.h[2]) + static_cast<float>(c.h[2]) * 0x1p-11f,
+                                    static_cast<float>(a.h[3]) + static_cast<float>(c.h[3]) * 0x1p-11f);
+            }
+        }
+    } else {
+        constexpr int kRows = kRowsPerChunk;    // r0 is a multiple of it
+        for (int c = ch.r0 + 1 + threadIdx.x; c < ld; c += kBlock) {
+            const float4 *src = reinterpret_cast<const float4 *>(X + (int64_t)c * ld + ch.r0);
+            float v[kRows];
+#pragma unroll
+            for (int q = 0; q < kRows / 4; ++q) {
+                const float4 t = src[q];
+                v[4 * q] = t.x; v[4 * q + 1] = t.y; v[4 * q + 2] = t.z; v[4 * q + 3] = t.w;
+            }
+#pragma unroll
+            for (int i = 0; i < kRows; ++i)
+                if (ch.r0 + i < ch.r1 && c > ch.r0 + i) X[(int64_t)(ch.r0 + i) * ld + c] = v[i];
+        }
+    }
 }
 
 // a7 between per-product launches: reduce the product's trace partials in a
@@ -1566,6 +1640,20 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
                    (float *)nullptr, dp.state, dp.diag_partials, 0, (float *)nullptr, (float *)nullptr);
         if (ev) rec.add_event(ev->step[2 * it + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 0);
+    }
+    if (!rp.persistent && rp.n_steps > 0) {
+        if (rp.precision == GSP2_PREC_FP16)
+            record(rec, k_wide_fixup<_Float16, false>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
+                   (const _Float16 *)nullptr, (const _Float16 *)nullptr, (const _Float16 *)nullptr,
+                   (const _Float16 *)nullptr, dp.state);
+        else if (rp.precision == GSP2_PREC_BF16)
+            record(rec, k_wide_fixup<__bf16, false>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
+                   (const __bf16 *)nullptr, (const __bf16 *)nullptr, (const __bf16 *)nullptr,
+                   (const __bf16 *)nullptr, dp.state);
+        else if (rp.precision == GSP2_PREC_FP16X3)
+            record(rec, k_wide_fixup<_Float16, true>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
+                   (const _Float16 *)h16[0], (const _Float16 *)h16[1], (const _Float16 *)l16[0],
+                   (const _Float16 *)l16[1], dp.state);
     }
     for (int r = 0; r < rp.refine; ++r) {
         const int slot = rp.n_steps + r;

@@ -164,6 +164,28 @@ def test_mixed_precision_one_product(precision):
     assert err <= 4 * unit
 
 
+@pytest.mark.parametrize("precision", ["fp16", "bf16", "fp16x3"])
+def test_16bit_one_update_product(precision):
+    # one X' = 2X - X^2 product: the 16-bit epilogue reads X_old at the
+    # mirrored position and applies the update; the parts' padded sizes are
+    # 5, 5 and 4 times 128, so 256-wide tiles with a half-empty last row and
+    # column are exercised next to full ones
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(100, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 3, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, alpha_seq=[1])
+    P, run, _, index, _ = run_gsp2(s.H, Pp, 1e-3, part, 3, s.n_occ, alpha_seq=[1], trace_tol=1e9,
+                                   precision=precision)
+    pads = sorted(-(-len(ix) // 128) for ix in index)
+    assert any(p % 2 for p in pads) and any(p % 2 == 0 for p in pads), pads
+    err = rel_fro(P, ref.csc())
+    print(f"{precision} one update product: rel_err={err:.2e}, s_pad/128 = {pads}", flush=True)
+    unit = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8, "fp16x3": 2.0 ** -22}[precision]
+    assert run["alpha"][:1] == [1]
+    assert err <= 4 * unit
+
+
 @pytest.mark.parametrize("precision", ["fp16", "bf16"])
 def test_mixed_precision_trace_mode(precision):
     from tests._gpu import rel_fro, run_gsp2
