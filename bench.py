@@ -376,7 +376,7 @@ def main():
     args.precision = args.precision or ("fp16" if batch else "fp32")
     args.refine = (2 if batch else 0) if args.refine is None else args.refine
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}); "
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
               "run with --gpus 1", file=sys.stderr)
         return 2
     import torch

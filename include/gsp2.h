@@ -42,7 +42,7 @@ typedef enum {
     GSP2_E_NOT_CONVERGED = 4,  /* the stop rule did not fire within max_iter products,
                                   or the iteration left the finite range */
     GSP2_E_WRONG_TRACE = 5,    /* a replayed branch sequence missed n_occ by more than trace_tol */
-    GSP2_E_UNSUPPORTED = 6     /* option not available in this build */
+    GSP2_E_UNSUPPORTED = 6     /* option not available in this library */
 } gsp2_status;
 
 typedef enum { GSP2_F32 = 0, GSP2_F64 = 1 } gsp2_dtype;
@@ -125,7 +125,7 @@ typedef struct {
     int32_t persistent;        /* must be 0 (one launch per product, all in one HIP graph).
                                   1 would put all products before the stop in one persistent
                                   launch with a grid barrier per product; that path is switched
-                                  off in this build and returns GSP2_E_UNSUPPORTED. */
+                                  off in this library and returns GSP2_E_UNSUPPORTED. */
     /* Batched plans only (n_systems > 1); NULL otherwise. */
     const double *n_occ_system;      /* host, n_systems: occupation of every system (required;
                                         replaces the n_occ argument of gsp2_density) */
