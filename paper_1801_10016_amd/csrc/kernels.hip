@@ -567,70 +567,56 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 
     // K chunks.  Plain: the nk chunks of X[I,:] X[J,:].  Split (X = H + 2^-11 L):
     // nk chunks of H[I,:] L[J,:], nk of L[I,:] H[J,:], the accumulator scaled by
-    // 2^-11 (exact), then nk of H[I,:] H[J,:].  Where both panels of a chunk are
-    // the same rows (a diagonal tile's plain or H H chunks) only A is staged.
+    // 2^-11 (exact), then nk of H[I,:] H[J,:].  Both panels are staged for
+    // every chunk, diagonal tiles included.
+    //
+    // Operands arrive two chunks ahead in two register sets: chunk c + 1 is
+    // stored into LDS after the MFMAs of chunk c, from the set loaded before
+    // the MFMAs of chunk c - 1.  Chunk counts are even (s_pad is a multiple of
+    // 128), so the loop takes chunks in pairs with the sets fixed; past the end
+    // the last chunk is loaded again, so every load is unconditional, and the
+    // last pair stores it a second time into a buffer no wave reads again.
     const int nk = ld / kK;
     const int nc = kSplit ? 3 * nk : nk;
-    uint4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
-#define GSP2_CHUNK_SRC(c, Ap, Bp, kb, same)                                                        \
+    uint4 pa00, pa01, pa02, pa03, pb00, pb01, pb02, pb03;   // register set 0
+    uint4 pa10, pa11, pa12, pa13, pb10, pb11, pb12, pb13;   // register set 1
+    const char *Ap_ = AgH, *Bp_ = BgH;
+    int64_t kb_ = 0;
+#define GSP2_SRC(c)                                                                                \
     do {                                                                                           \
+        const int c_ = (c);                                                                        \
+        Ap_ = AgH; Bp_ = BgH; kb_ = (int64_t)c_ * 128;                                             \
         if constexpr (kSplit) {                                                                    \
-            const int seg_ = (c) / nk;                                                             \
-            Ap = seg_ == 1 ? AgL : AgH;                                                            \
-            Bp = seg_ == 0 ? BgL : BgH;                                                            \
-            kb = (int64_t)((c) - seg_ * nk) * 128;                                                 \
-            same = diag && seg_ == 2;                                                              \
-        } else {                                                                                   \
-            Ap = AgH; Bp = BgH; kb = (int64_t)(c) * 128; same = diag;                              \
+            const int seg_ = c_ / nk;                                                              \
+            Ap_ = seg_ == 1 ? AgL : AgH;                                                           \
+            Bp_ = seg_ == 0 ? BgL : BgH;                                                           \
+            kb_ = (int64_t)(c_ - seg_ * nk) * 128;                                                 \
         }                                                                                          \
     } while (0)
-#define GSP2_LOAD_CHUNK(Ap, Bp, kb, same)                                                          \
+#define GSP2_LD(S, c)                                                                              \
     do {                                                                                           \
-        pa0 = *reinterpret_cast<const uint4 *>(Ap + (kb));                                         \
-        pa1 = *reinterpret_cast<const uint4 *>(Ap + pass_bytes + (kb));                            \
-        pa2 = *reinterpret_cast<const uint4 *>(Ap + 2 * pass_bytes + (kb));                        \
-        pa3 = *reinterpret_cast<const uint4 *>(Ap + 3 * pass_bytes + (kb));                        \
-        if (!(same)) {                                                                             \
-            pb0 = *reinterpret_cast<const uint4 *>(Bp + (kb));                                     \
-            pb1 = *reinterpret_cast<const uint4 *>(Bp + pass_bytes + (kb));                        \
-            pb2 = *reinterpret_cast<const uint4 *>(Bp + 2 * pass_bytes + (kb));                    \
-            pb3 = *reinterpret_cast<const uint4 *>(Bp + 3 * pass_bytes + (kb));                    \
-        }                                                                                          \
+        GSP2_SRC(c);                                                                               \
+        pa##S##0 = *reinterpret_cast<const uint4 *>(Ap_ + kb_);                                    \
+        pa##S##1 = *reinterpret_cast<const uint4 *>(Ap_ + pass_bytes + kb_);                       \
+        pa##S##2 = *reinterpret_cast<const uint4 *>(Ap_ + 2 * pass_bytes + kb_);                   \
+        pa##S##3 = *reinterpret_cast<const uint4 *>(Ap_ + 3 * pass_bytes + kb_);                   \
+        pb##S##0 = *reinterpret_cast<const uint4 *>(Bp_ + kb_);                                    \
+        pb##S##1 = *reinterpret_cast<const uint4 *>(Bp_ + pass_bytes + kb_);                       \
+        pb##S##2 = *reinterpret_cast<const uint4 *>(Bp_ + 2 * pass_bytes + kb_);                   \
+        pb##S##3 = *reinterpret_cast<const uint4 *>(Bp_ + 3 * pass_bytes + kb_);                   \
     } while (0)
-#define GSP2_STORE_CHUNK(b, same)                                                                  \
+#define GSP2_ST(b, S)                                                                              \
     do {                                                                                           \
         uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;                                                \
-        As_[0] = pa0; As_[32 * kLdsRow] = pa1; As_[64 * kLdsRow] = pa2; As_[96 * kLdsRow] = pa3;   \
-        if (!(same)) {                                                                             \
-            uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                            \
-            Bs_[0] = pb0; Bs_[32 * kLdsRow] = pb1; Bs_[64 * kLdsRow] = pb2; Bs_[96 * kLdsRow] = pb3; \
-        }                                                                                          \
+        uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                                \
+        As_[0] = pa##S##0; As_[32 * kLdsRow] = pa##S##1;                                           \
+        As_[64 * kLdsRow] = pa##S##2; As_[96 * kLdsRow] = pa##S##3;                                \
+        Bs_[0] = pb##S##0; Bs_[32 * kLdsRow] = pb##S##1;                                           \
+        Bs_[64 * kLdsRow] = pb##S##2; Bs_[96 * kLdsRow] = pb##S##3;                                \
     } while (0)
-
-    const char *Ap;
-    const char *Bp;
-    int64_t kb;
-    bool same_cur, same_next;
-    GSP2_CHUNK_SRC(0, Ap, Bp, kb, same_cur);
-    GSP2_LOAD_CHUNK(Ap, Bp, kb, same_cur);
-    GSP2_STORE_CHUNK(0, same_cur);
-    __syncthreads();
-    for (int kc = 0; kc < nc; ++kc) {
-        const int buf = kc & 1;
-        if (kc + 1 < nc) {
-            GSP2_CHUNK_SRC(kc + 1, Ap, Bp, kb, same_next);
-            GSP2_LOAD_CHUNK(Ap, Bp, kb, same_next);
-        }
-        if constexpr (kSplit) {
-            if (kc == 2 * nk) {                 // cross terms done: scale them by 2^-11
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
-            }
-        }
+    auto compute = [&](int buf) __attribute__((always_inline)) {
         const uint4 *Asb = lds(buf, 0);
-        const uint4 *Bsb = same_cur ? lds(buf, 0) : lds(buf, 1);
+        const uint4 *Bsb = lds(buf, 1);
         // interleave the LDS fragment reads with the MFMAs (3.5% faster FP32
         // products than the default schedule, measured)
         __builtin_amdgcn_iglp_opt(1);
@@ -649,15 +635,32 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 #pragma unroll
                 for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
         }
-        if (kc + 1 < nc) {
-            GSP2_STORE_CHUNK(buf ^ 1, same_next);
-            same_cur = same_next;
+    };
+    GSP2_LD(0, 0);
+    GSP2_ST(0, 0);
+    GSP2_LD(1, min(1, nc - 1));
+    __syncthreads();
+    for (int kc = 0; kc < nc; kc += 2) {
+        if constexpr (kSplit) {
+            if (kc == 2 * nk) {                 // cross terms done: scale them by 2^-11
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
+            }
         }
+        GSP2_LD(0, min(kc + 2, nc - 1));
+        compute(0);
+        GSP2_ST(1, 1);
+        __syncthreads();
+        GSP2_LD(1, min(kc + 3, nc - 1));
+        compute(1);
+        GSP2_ST(0, 0);
         __syncthreads();
     }
-#undef GSP2_CHUNK_SRC
-#undef GSP2_LOAD_CHUNK
-#undef GSP2_STORE_CHUNK
+#undef GSP2_SRC
+#undef GSP2_LD
+#undef GSP2_ST
 
     // Epilogue.  Accumulator element i of lane (l32, kh) in a 32x32 block is
     // row 8*(i/4) + 4*kh + (i%4), column l32.
@@ -719,7 +722,7 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 }
 
 template <typename Op, bool kSplit = false>
-__global__ __launch_bounds__(kBlock, 2) void k_sp2_step(const TileDesc *__restrict__ tiles,
+__global__ __launch_bounds__(kBlock, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_sp2_step(const TileDesc *__restrict__ tiles,
                                                         const PartDesc *__restrict__ parts,
                                                         float *__restrict__ buf0, float *__restrict__ buf1,
                                                         Op *__restrict__ sh0, Op *__restrict__ sh1,
@@ -1419,7 +1422,7 @@ __device__ __forceinline__ void adj_tile(const TileDesc td, const PartDesc pd, f
 
 // One forward product with the buffers and branch given explicitly (the
 // backward pass replays a known sequence).
-__global__ __launch_bounds__(kBlock, 2) void k_sp2_fixed(const TileDesc *__restrict__ tiles,
+__global__ __launch_bounds__(kBlock, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_sp2_fixed(const TileDesc *__restrict__ tiles,
                                                          const PartDesc *__restrict__ parts,
                                                          float *__restrict__ X_in, float *__restrict__ X_out,
                                                          float alpha, double *__restrict__ diag_partials) {
