@@ -516,8 +516,8 @@ __device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16
 // partial sums of Y and X' over the part's core diagonal.
 //
 // 256 threads = 4 waves in a 2x2 grid, each wave a 64x64 sub-tile as 2x2
-// blocks of 32x32 MFMA output.  Operands are staged through LDS in K chunks
-// with a register prefetch of the next chunk and two LDS buffers.  Within a
+// blocks of 32x32 MFMA output.  Operands are staged through LDS in K chunks,
+// two LDS buffers and two register sets deep.  Within a
 // chunk, lane half h of an MFMA operand takes the k values of its half of
 // every 16-byte group, for A and B alike, so each lane reads whole 16-byte
 // LDS words.
