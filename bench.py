@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--compare-precisions", default="fp16,bf16,fp16x3",
                     help="after the FP32 timing, also time these operand precisions (empty: none)")
     ap.add_argument("--compare-steps", type=int, default=3)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the 16-bit tile autotuner (gsp2_plan_tune) and use 256 x 256 tiles")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM counter calibration)")
     ap.add_argument("--workload", choices=["water3500", "batch16", "backward1000"], default="water3500",
@@ -95,17 +97,18 @@ def dense_bootstrap(g, torch, Hd, n, n_occ, stream):
     return g.DeviceCSR(n, col_ptr, row_idx, P), run
 
 
-def counter_traffic(precision, workload):
+def counter_traffic(precision, workload, kernel=None):
     """HBM bytes per product launch from the committed rocprofv3 counter record,
     or None when the record was taken on another workload (molecules, parts,
-    tau, sum of s^3) or the kernel or planner sources changed since."""
+    tau, sum of s^3) or product kernel, or the kernel or planner sources
+    changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sp2_step_counters.json")
     try:
         rec = json.load(open(path))[precision]
     except (OSError, KeyError, ValueError):
         return None
-    if rec.get("match") != workload:
+    if rec.get("match") != workload or (kernel is not None and rec.get("kernel") != kernel):
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -275,6 +278,12 @@ def bench_batch(args, g, torch):
         f"workspace {info['workspace_bytes'] / 2**30:.1f} GiB, {plan_s:.1f} s")
     P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
     sys_flops = [syrk_flops(sub_sizes[b.part_offs[i]:b.part_offs[i + 1]]) for i in range(len(b.steps))]
+    tuning = None
+    if precision != "fp32" and not args.no_tune:
+        with torch.cuda.stream(stream):
+            tuning = g.gsp2_plan_tune(plan, Hd, 0.0, precision, n_products=6)
+        log(f"tile autotuner: {tuning}")
+    tile16 = tuning["tile16"] if tuning else 256
     with torch.cuda.stream(stream):
         first = g.gsp2_density(plan, Hd, b.n_occ, P_val, max_iter=args.max_iter, precision=precision, refine=refine)
     n_main = [r["n_products"] - r["n_refine"] for r in first]
@@ -321,7 +330,8 @@ def bench_batch(args, g, torch):
         for i, st in enumerate(b.steps):
             Hs = g.csr_to_device(st.system.H)
             with torch.cuda.stream(stream):
-                with g.gsp2_plan_create(g.csr_to_device(st.P_prev), b.tau, st.part, st.n_parts, stream=stream) as p1:
+                with g.gsp2_plan_create(g.csr_to_device(st.P_prev), b.tau, st.part, st.n_parts, stream=stream,
+                                        tile16=tile16 if precision != "fp32" else 0) as p1:
                     Pv = torch.empty(p1.nnz_P, dtype=torch.float32, device="cuda")
                     k1 = dict(kw, max_iter=n_main[i])
                     g.gsp2_density(p1, Hs, st.system.n_occ, Pv, **k1)
@@ -354,12 +364,15 @@ def bench_batch(args, g, torch):
         "aggregate_tflops": round(total_flops / (float(np.sum(per_launch)) * 1e-3) / 1e12, 2),
         "aggregate_tflops_convention": "symmetric-product flops of every system in every launch it took part in "
                                        "/ summed product-kernel time",
-        "roofline": {"bound": "mfma", "kernel": "k_sp2_step<fp32>" if precision == "fp32" else f"k_sp2_wide<{precision}>", "achieved": round(main_tf, 2),
+        "roofline": {"bound": "mfma",
+                     "kernel": (f"k_sp2_wide<{precision}>" if precision != "fp32" and tile16 == 256
+                                else f"k_sp2_step<{precision}>"), "achieved": round(main_tf, 2),
                      "peak": peak_main, "unit": "TFLOP/s", "frac": round(main_tf / peak_main, 4), "traffic": None,
                      "refine_kernel_tflops": round(ref_flops / (ref_ms * 1e-3) / 1e12, 2) if ref_ms > 0 else None},
         "event_total_ms_median": round(statistics.median(totals), 3),
         "main_launches": max_main, "main_launch_ms": round(main_ms, 3), "refine_launch_ms": round(ref_ms, 3),
         "alone_total_ms": round(sum(alone_ms), 3) if alone_ms else None,
+        "tile16_tuning": tuning,
         "per_system": per_system,
         "plan_ms": round(plan_s * 1e3, 1),
         "workspace_gib": round(info["workspace_bytes"] / 2**30, 2),
@@ -440,6 +453,14 @@ def main():
         f"tiles/product = {info['n_tiles']}, workspace = {info['workspace_bytes'] / 2**30:.2f} GiB, {plan_s:.1f} s")
     P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
 
+    # 16-bit products: the tile autotuner picks the tile edge on this plan
+    # first (outside every timed region)
+    tuning = None
+    if args.precision != "fp32" and not args.no_tune:
+        with torch.cuda.stream(stream):
+            tuning = g.gsp2_plan_tune(plan, Hd, n_occ, args.precision, n_products=6)
+        log(f"tile autotuner: {tuning}")
+
     # the first run finds where the stop rule fires; later runs form exactly
     # that many products (the same stop fires at the same product), so no
     # empty launches follow the stop
@@ -484,6 +505,8 @@ def main():
 
     s = np.asarray(sub_sizes, dtype=np.float64)
     syrk_flops = float(np.sum(s * s * (s + 1.0)))        # distinct entries s(s+1)/2, 2s flops each
+    product_kernel = ("k_sp2_wide" if args.precision != "fp32" and (tuning or {}).get("tile16", 256) == 256
+                      else "k_sp2_step")
     gemm_flops = float(np.sum(2.0 * s ** 3))
     avg_prod_ms = statistics.fmean(product_ms)
     achieved = MFMA_PRODUCTS[args.precision] * syrk_flops / (avg_prod_ms * 1e-3) / 1e12
@@ -496,7 +519,10 @@ def main():
     P_ref = P_val.double()
     for prec in [p for p in args.compare_precisions.split(",") if p]:
         P_mp = torch.empty_like(P_val)
+        tune_rec = None
         with torch.cuda.stream(stream):
+            if not args.no_tune:
+                tune_rec = g.gsp2_plan_tune(plan, Hd, n_occ, prec, n_products=6)
             r0 = g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=args.max_iter, precision=prec)
             n_mp = r0["n_products"]
             g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=n_mp, precision=prec)      # builds the graph
@@ -516,7 +542,8 @@ def main():
                          "tflops": round(syrk_flops / (avg * 1e-3) / 1e12, 2),
                          "mfma_products_per_product": MFMA_PRODUCTS[prec],
                          "frac_of_peak": round(hw / (avg * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[prec], 4),
-                         "rel_diff_vs_fp32_P": diff, "trace_minus_nocc": r0["trace"] - n_occ}
+                         "rel_diff_vs_fp32_P": diff, "trace_minus_nocc": r0["trace"] - n_occ,
+                         "tile16_tuning": tune_rec}
         log(f"{prec}: {ms:.1f} ms/P, {n_mp} products, |P - P_fp32|/|P_fp32| = {diff:.2e}")
         del P_mp
         torch.cuda.empty_cache()
@@ -552,11 +579,11 @@ def main():
         "batched_gemm_tflops": round(n_prod * gemm_flops / (sp2_med * 1e-3) / 1e12, 2),
         "batched_gemm_tflops_convention": "n_products * sum_k 2 s_k^3 / SP2-phase time (GEMM convention)",
         "roofline": {
-            "bound": "mfma", "kernel": "k_sp2_step" if args.precision == "fp32" else "k_sp2_wide",
+            "bound": "mfma", "kernel": product_kernel,
             "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": counter_traffic(
                 args.precision, {"n_mol": args.n_mol, "n_parts": args.n_parts, "tau": args.tau,
-                                 "sum_s3": info["sum_s3"]}),
+                                 "sum_s3": info["sum_s3"]}, product_kernel),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "flops_per_launch": MFMA_PRODUCTS[args.precision] * syrk_flops, "avg_launch_ms": round(avg_prod_ms, 4),
             "flops_convention": "symmetric product: sum_k s_k^2 (s_k + 1) per launch (one launch = one product)",
@@ -572,6 +599,7 @@ def main():
                                      "update and trace partials) against the rest of one P: Gershgorin, gather, "
                                      "branch decisions, scatter and launch gaps"},
         "precision_compare": compare,
+        "tile16_tuning": tuning,
         "plan_ms": round(plan_s * 1e3, 1),
         "plan_info": {k: info[k] for k in ("nnz_graph", "nnz_P", "sum_s", "workspace_bytes")},
         "previous_P_s": round(boot_s, 2),

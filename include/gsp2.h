@@ -81,12 +81,15 @@ typedef struct gsp2_plan_s *gsp2_plan;   /* opaque, library-owned */
 
 /* Plan options.  Zero-initialised means defaults. */
 typedef struct {
-    int32_t tile;              /* macro-tile edge of the SP2 product: 0 = automatic, or 128 */
+    int32_t tile;              /* macro-tile edge of the FP32 product: 0 = automatic, or 128 */
     int32_t n_systems;         /* independent systems batched in the plan: 0 or 1 = one */
     const int32_t *part_system;/* host, n_parts ids in [0, n_systems), every system used by at
                                   least one part: the system of every part.  Ignored (may be
                                   NULL) when n_systems <= 1. */
-    int32_t reserved[4];
+    int32_t tile16;            /* macro-tile edge of the 16-bit products: 0 = automatic (the
+                                  edge gsp2_plan_tune chose for the precision, else 256), 128
+                                  or 256 (fixed; gsp2_plan_tune does not override it) */
+    int32_t reserved[3];
 } gsp2_plan_options;
 
 /* Summary of a plan, filled by gsp2_plan_query. */
@@ -320,6 +323,39 @@ void gsp2_plan_destroy(gsp2_plan plan);
  * stored order.  adj_ptr: host, n+1 int64; adj_col: host, nnz_graph int32,
  * nullable (pass NULL first to size it from adj_ptr[n]).  Errors: GSP2_E_INVALID. */
 gsp2_status gsp2_plan_graph(gsp2_plan plan, int64_t *adj_ptr, int32_t *adj_col);
+
+/* Result of gsp2_plan_tune. */
+typedef struct {
+    int32_t precision;         /* the 16-bit gsp2_precision tuned */
+    int32_t tile16;            /* the macro-tile edge chosen: 128 or 256 */
+    double ms_128;             /* mean product time over the timed products, 128 x 128 tiles */
+    double ms_256;             /* the same with 256 x 256 tiles */
+    int32_t n_products;        /* products timed per candidate */
+    int32_t pad_;
+} gsp2_tune_info;
+
+/* Autotuner of the 16-bit product tile (the paper's products are dense
+ * matrix-matrix sub-problems, Methods, eq. (4); their tiling is this
+ * library's choice).  Times n_products products of the plan's own
+ * sub-problems, built from H, with each candidate macro-tile edge (128 x 128
+ * tiles, several workgroups per CU; 256 x 256 tiles, one workgroup per CU)
+ * and keeps the edge with the lower mean product time for `precision`:
+ * gsp2_density then uses it for that precision unless the plan was created
+ * with a fixed tile16.  The products replay alternating branches (X^2,
+ * 2X - X^2, ...), so every product carries the same work as in a run; the
+ * trace check of those runs is not applied.  Runs on the plan's stream and
+ * waits for it.
+ *
+ *  H           device CSR as for gsp2_density.
+ *  n_occ       as for gsp2_density (batched plans: ignored).
+ *  precision   GSP2_PREC_FP16, GSP2_PREC_BF16 or GSP2_PREC_FP16X3.
+ *  n_products  2..GSP2_MAX_ITER products per candidate (after one untimed run).
+ *  info        nullable; filled with the timings and the choice.
+ * Returns GSP2_E_INVALID for other precisions or a bad n_products; the
+ * plan's previous choice is kept on any error.  The library allocates and
+ * frees a P-sized scratch output of its own. */
+gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int32_t precision,
+                           int32_t n_products, gsp2_tune_info *info);
 
 /* Options of gsp2_partition_anneal.  Zero-initialised means defaults. */
 typedef struct {

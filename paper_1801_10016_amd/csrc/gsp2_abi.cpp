@@ -169,6 +169,8 @@ struct GraphKey {
 
 struct gsp2_plan_s {
     int32_t n = 0, n_parts = 0, tile = kTile;
+    int32_t tile16_fixed = 0;             // plan option: 0 = tuned or default
+    int32_t tile16_tuned[4] = {0, 0, 0, 0};   // gsp2_plan_tune's choice per precision, 0 = none
     int32_t n_sys = 1;
     std::vector<int32_t> part_system;     // system of every part
     std::vector<int32_t> sys_size;        // vertices of every system
@@ -318,6 +320,8 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         if (!(tau >= 0.0) || !std::isfinite(tau)) fail(GSP2_E_INVALID, "tau must be finite and >= 0");
         if (n_parts < 1 || n_parts > P_prev->n) fail(GSP2_E_INVALID, "need 1 <= n_parts <= n");
         if (opt && opt->tile != 0 && opt->tile != kTile) fail(GSP2_E_UNSUPPORTED, "tile must be 0 or 128");
+        if (opt && opt->tile16 != 0 && opt->tile16 != kTile && opt->tile16 != kTileWide)
+            fail(GSP2_E_INVALID, "tile16 must be 0, 128 or 256");
         const int32_t n_sys = (opt && opt->n_systems > 1) ? opt->n_systems : 1;
         if (opt && opt->n_systems < 0) fail(GSP2_E_INVALID, "n_systems must be >= 0");
         if (n_sys > n_parts) fail(GSP2_E_INVALID, "more systems than parts");
@@ -326,6 +330,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         plan->n = P_prev->n;
         plan->n_parts = n_parts;
         plan->n_sys = n_sys;
+        plan->tile16_fixed = opt ? opt->tile16 : 0;
         plan->stream = static_cast<hipStream_t>(stream);
         hipStream_t s = plan->stream;
         const int32_t n = plan->n;
@@ -684,6 +689,59 @@ gsp2_status gsp2_plan_part_index(gsp2_plan plan, int32_t k, int32_t *idx) {
     });
 }
 
+gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int32_t precision,
+                           int32_t n_products, gsp2_tune_info *info) {
+    float *scratch = nullptr;
+    const gsp2_status st = guarded([&] {
+        if (!plan || !H) fail(GSP2_E_INVALID, "null argument");
+        if (precision != GSP2_PREC_FP16 && precision != GSP2_PREC_BF16 && precision != GSP2_PREC_FP16X3)
+            fail(GSP2_E_INVALID, "gsp2_plan_tune takes a 16-bit precision");
+        if (n_products < 2 || n_products > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_products out of range");
+        int64_t nnz_p = 0;
+        for (const auto &d : plan->desc) nnz_p += (int64_t)d.c * d.s;
+        check_hip(hipMalloc(&scratch, sizeof(float) * (size_t)std::max<int64_t>(nnz_p, 1)), "tuner scratch output");
+        std::vector<int8_t> seq(n_products);
+        for (int i = 0; i < n_products; ++i) seq[i] = (i % 2) ? 1 : -1;
+        std::vector<double> occ(plan->n_sys, n_occ);
+        gsp2_run_options o;
+        gsp2_run_options_default(&o);
+        o.max_iter = n_products;
+        o.alpha_mode = GSP2_ALPHA_REPLAY;
+        o.alpha_seq = seq.data();
+        o.n_alpha = n_products;
+        o.timing = 1;
+        o.precision = precision;
+        if (plan->n_sys > 1) o.n_occ_system = occ.data();
+        const int32_t saved_fixed = plan->tile16_fixed;
+        double ms[2] = {0.0, 0.0};
+        const int32_t edge[2] = {kTile, kTileWide};
+        for (int c = 0; c < 2; ++c) {
+            plan->tile16_fixed = edge[c];
+            gsp2_status r = GSP2_OK;
+            for (int rep = 0; rep < 2 && r == GSP2_OK; ++rep)    // the first run builds the graph
+                r = gsp2_density(plan, H, n_occ, &o, scratch, nullptr);
+            gsp2_timing t;
+            if (r == GSP2_OK) r = gsp2_run_timing(plan, &t);
+            plan->tile16_fixed = saved_fixed;
+            if (r != GSP2_OK) fail(r, std::string("tuning run: ") + g_last_error);
+            double sum = 0.0;
+            for (int i = 0; i < t.n_products; ++i) sum += t.product_ms[i];
+            ms[c] = t.n_products > 0 ? sum / t.n_products : 0.0;
+        }
+        plan->tile16_tuned[precision] = ms[0] < ms[1] ? kTile : kTileWide;
+        if (info) {
+            info->precision = precision;
+            info->tile16 = plan->tile16_tuned[precision];
+            info->ms_128 = ms[0];
+            info->ms_256 = ms[1];
+            info->n_products = n_products;
+            info->pad_ = 0;
+        }
+    });
+    if (scratch) hipFree(scratch);
+    return st;
+}
+
 gsp2_status gsp2_plan_graph(gsp2_plan plan, int64_t *adj_ptr, int32_t *adj_col) {
     return guarded([&] {
         if (!plan) fail(GSP2_E_INVALID, "null plan");
@@ -824,6 +882,10 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         rp.precision = o.precision;
         rp.refine = o.refine;
         rp.persistent = o.persistent ? 1 : 0;
+        rp.tile16 = 0;
+        if (rp.precision != GSP2_PREC_FP32)
+            rp.tile16 = plan->tile16_fixed ? plan->tile16_fixed
+                        : plan->tile16_tuned[rp.precision] ? plan->tile16_tuned[rp.precision] : kTileWide;
         if (rp.persistent)
             fail(GSP2_E_UNSUPPORTED,
                  "the persistent product launch is switched off: its first GPU run did not return and the "

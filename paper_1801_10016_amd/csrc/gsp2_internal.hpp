@@ -104,6 +104,8 @@ struct RunParams {
     int32_t precision;          // gsp2_precision of the main phase
     int32_t refine;             // FP32 products after the main phase
     int32_t persistent;         // 1: main-phase products in one persistent launch
+    int32_t tile16;             // 16-bit products: 256 (k_sp2_wide) or 128 (k_sp2_step) tiles
+    int32_t pad_;
 };
 
 // Per-call parameters of one system, uploaded to the device before each run.

@@ -1622,9 +1622,20 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     _Float16 *l16[2] = {static_cast<_Float16 *>(dp.shadow_lo[0]), static_cast<_Float16 *>(dp.shadow_lo[1])};
     __bf16 *b16[2] = {static_cast<__bf16 *>(dp.shadow[0]), static_cast<__bf16 *>(dp.shadow[1])};
     const dim3 grid_w(dp.n_tiles_w), blk_w(kBlockW);
+    // 16-bit products on 128 x 128 tiles (the tile autotuner's other candidate)
+    const bool narrow16 = mixed && rp.tile16 == kTile;
     for (int it = 0; it < (rp.persistent ? 0 : rp.n_steps); ++it) {
         if (ev) rec.add_event(ev->step[2 * it]);
-        if (rp.precision == GSP2_PREC_FP16)
+        if (narrow16 && rp.precision == GSP2_PREC_FP16)
+            record(rec, k_sp2_step<_Float16, false>, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1],
+                   dp.state, dp.diag_partials, 0, (_Float16 *)nullptr, (_Float16 *)nullptr);
+        else if (narrow16 && rp.precision == GSP2_PREC_FP16X3)
+            record(rec, k_sp2_step<_Float16, true>, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1],
+                   dp.state, dp.diag_partials, 0, l16[0], l16[1]);
+        else if (narrow16 && rp.precision == GSP2_PREC_BF16)
+            record(rec, k_sp2_step<__bf16, false>, grid, blk, dp.tiles, dp.parts, b0, b1, b16[0], b16[1],
+                   dp.state, dp.diag_partials, 0, (__bf16 *)nullptr, (__bf16 *)nullptr);
+        else if (rp.precision == GSP2_PREC_FP16)
             record(rec, k_sp2_wide<_Float16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0], h16[1],
                    dp.state, dp.diag_partials, (_Float16 *)nullptr, (_Float16 *)nullptr);
         else if (rp.precision == GSP2_PREC_FP16X3)
@@ -1639,7 +1650,7 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
         if (ev) rec.add_event(ev->step[2 * it + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 0);
     }
-    if (!rp.persistent && rp.n_steps > 0) {
+    if (!rp.persistent && rp.n_steps > 0 && !narrow16) {
         if (rp.precision == GSP2_PREC_FP16)
             record(rec, k_wide_fixup<_Float16, false>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
                    (const _Float16 *)nullptr, (const _Float16 *)nullptr, (const _Float16 *)nullptr,

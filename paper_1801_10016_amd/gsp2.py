@@ -34,7 +34,12 @@ class gsp2_csr(C.Structure):
 
 class gsp2_plan_options(C.Structure):
     _fields_ = [("tile", C.c_int32), ("n_systems", C.c_int32), ("part_system", C.POINTER(C.c_int32)),
-                ("reserved", C.c_int32 * 4)]
+                ("tile16", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class gsp2_tune_info(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("tile16", C.c_int32), ("ms_128", C.c_double),
+                ("ms_256", C.c_double), ("n_products", C.c_int32), ("pad_", C.c_int32)]
 
 
 class gsp2_plan_info(C.Structure):
@@ -100,6 +105,8 @@ SIGNATURES = {
     "gsp2_backward": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.POINTER(C.c_int8), C.c_int32, C.c_void_p,
                                 C.c_void_p, C.POINTER(gsp2_backward_info)]),
     "gsp2_plan_graph": (C.c_int, [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
+    "gsp2_plan_tune": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.c_double, C.c_int32, C.c_int32,
+                                 C.POINTER(gsp2_tune_info)]),
     "gsp2_locality_graph": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double),
                                       C.c_double, C.c_double, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "gsp2_partition_anneal": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32,
@@ -219,13 +226,15 @@ class Plan:
 
 
 def gsp2_plan_create(P_prev: DeviceCSR, tau: float, part, n_parts: int, tile: int = 0, stream=None,
-                     part_system=None) -> Plan:
-    """part_system (n_parts ids) batches independent systems in one plan."""
+                     part_system=None, tile16: int = 0) -> Plan:
+    """part_system (n_parts ids) batches independent systems in one plan;
+    tile16 fixes the 16-bit product tile edge (0: tuned, else 256)."""
     part = np.ascontiguousarray(part, dtype=np.int32)
     if part.shape != (P_prev.n,):
         raise ValueError("part must have one entry per vertex")
     c = P_prev.as_c()
     opt = gsp2_plan_options(tile)
+    opt.tile16 = int(tile16)
     keep = None
     if part_system is not None:
         keep = np.ascontiguousarray(part_system, dtype=np.int32)
@@ -268,6 +277,18 @@ def gsp2_plan_part_index(plan: Plan, k: int) -> np.ndarray:
     idx = np.empty(int(ss[k]), dtype=np.int32)
     _check(load().gsp2_plan_part_index(plan.handle, int(k), _i32(idx)))
     return idx
+
+
+def gsp2_plan_tune(plan: Plan, H: DeviceCSR, n_occ, precision: str, n_products: int = 8) -> dict:
+    """Time both 16-bit product tile edges on the plan's sub-problems and keep
+    the faster for `precision` (gsp2_plan_tune in gsp2.h).  Returns the
+    timings and the choice; json.dump of it is the tuning record."""
+    info = gsp2_tune_info()
+    c = H.as_c()
+    _check(load().gsp2_plan_tune(plan.handle, C.byref(c), float(n_occ), PRECISIONS[precision], int(n_products),
+                                 C.byref(info)))
+    return {"precision": precision, "tile16": info.tile16, "ms_per_product_128": info.ms_128,
+            "ms_per_product_256": info.ms_256, "n_products": info.n_products}
 
 
 def gsp2_plan_graph(plan: Plan):

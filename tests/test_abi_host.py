@@ -126,7 +126,7 @@ def test_binding_structs_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = [binding.gsp2_csr, binding.gsp2_plan_options, binding.gsp2_plan_info, binding.gsp2_run_options,
-               binding.gsp2_run_info, binding.gsp2_timing, binding.gsp2_backward_info]
+               binding.gsp2_run_info, binding.gsp2_timing, binding.gsp2_backward_info, binding.gsp2_tune_info]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsp2.h"', "int main(void) {"]
     for cls in structs:
         name = cls.__name__
@@ -147,7 +147,7 @@ def test_binding_structs_match_the_header(tmp_path):
             assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, (name, f)
 
 
-def _plan_create_host(part, n_parts, n_systems, part_system):
+def _plan_create_host(part, n_parts, n_systems, part_system, tile16=0):
     """gsp2_plan_create with host arrays: only its argument checks, which run
     before any HIP call, are reached when the arguments are invalid."""
     import ctypes as C
@@ -160,6 +160,7 @@ def _plan_create_host(part, n_parts, n_systems, part_system):
         keep = np.ascontiguousarray(part_system, dtype=np.int32)
         opt.part_system = keep.ctypes.data_as(C.POINTER(C.c_int32))
     opt.n_systems = n_systems
+    opt.tile16 = tile16
     out = C.c_void_p()
     part = np.ascontiguousarray(part, dtype=np.int32)
     st = g.load().gsp2_plan_create(C.byref(c), 1e-3, part.ctypes.data_as(C.POINTER(C.c_int32)), n_parts,
@@ -178,6 +179,21 @@ def test_batched_plan_arguments_are_checked(n_systems, part_system, message):
     part = np.array([0, 0, 1, 1], dtype=np.int32)
     st, msg, handle = _plan_create_host(part, 2, n_systems, part_system)
     assert st == binding.GSP2_E_INVALID and message in msg and handle is None
+
+
+@pytest.mark.parametrize("tile16", [64, 512, -1])
+def test_tile16_option_is_checked(tile16):
+    part = np.array([0, 0, 1, 1], dtype=np.int32)
+    st, msg, handle = _plan_create_host(part, 2, 0, None, tile16)
+    assert st == binding.GSP2_E_INVALID and "tile16" in msg and handle is None
+
+
+def test_tune_rejects_bad_arguments_before_any_gpu_call():
+    import ctypes as C
+    c = binding.gsp2_csr(4, 0, None, None, None, binding.GSP2_F64)
+    lib = g.load()
+    assert lib.gsp2_plan_tune(None, C.byref(c), 1.0, binding.GSP2_PREC_FP16, 8, None) == binding.GSP2_E_INVALID
+    assert "null" in lib.gsp2_last_error().decode()
 
 
 def test_run_option_defaults_leave_batch_fields_empty():

@@ -17,3 +17,6 @@ def test_counter_traffic_only_for_the_recorded_workload():
         assert bench.counter_traffic(prec, other) is None
         assert bench.counter_traffic(prec, dict(r["match"], sum_s3=r["match"]["sum_s3"] + 1)) is None
     assert bench.counter_traffic("no-such-precision", {}) is None
+    for prec, r in rec.items():
+        other = "k_sp2_step" if r["kernel"] == "k_sp2_wide" else "k_sp2_wide"
+        assert bench.counter_traffic(prec, dict(r["match"]), other) is None

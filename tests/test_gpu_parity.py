@@ -205,6 +205,41 @@ def test_mixed_precision_trace_mode(precision):
     assert out[2] <= 1.05 * out[0]           # a purification pair cannot undo the subspace error, nor add to it
 
 
+@pytest.mark.parametrize("precision", ["fp16", "bf16", "fp16x3"])
+def test_16bit_products_on_128_tiles(precision):
+    # the tile autotuner's other candidate: 16-bit products on 128 x 128
+    # tiles meet the same bars as on 256 x 256 tiles, against the oracle
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(200, 1)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 6, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ)
+    bar = {"fp16": MIXED_TOL["fp16"], "bf16": MIXED_TOL["bf16"], "fp16x3": 1e-5}[precision]
+    errs = {}
+    for tile16 in (128, 256):
+        P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, tile16=tile16)
+        assert run["status"] == 0 and np.isfinite(vals).all(), run
+        errs[tile16] = rel_fro(P, ref.csc())
+    print(f"{precision}: rel_err 128 tiles {errs[128]:.2e}, 256 tiles {errs[256]:.2e}", flush=True)
+    assert errs[128] <= bar and errs[256] <= bar
+
+
+def test_tile_autotuner_choice_is_used():
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(200, 1)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 6, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ)
+    P, run, _, _, _ = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision="fp16", tune="fp16")
+    rec = run["tune"]
+    print(f"tuner: {rec}", flush=True)
+    assert rec["tile16"] in (128, 256) and rec["n_products"] == 4
+    assert rec["ms_per_product_128"] > 0 and rec["ms_per_product_256"] > 0
+    faster = 128 if rec["ms_per_product_128"] < rec["ms_per_product_256"] else 256
+    assert rec["tile16"] == faster
+    assert run["status"] == 0 and rel_fro(P, ref.csc()) <= MIXED_TOL["fp16"]
+
+
 @pytest.mark.parametrize("n_mol,seed,n_parts,tau", [(64, 0, 8, 1e-5), (200, 1, 6, 1e-4)])
 def test_split_fp16_products_meet_the_fp32_bar(n_mol, seed, n_parts, tau):
     # three FP16 products with the operand split X = A + 2^-11 B: the FP32 bar applies
