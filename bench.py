@@ -507,6 +507,11 @@ def main():
     syrk_flops = float(np.sum(s * s * (s + 1.0)))        # distinct entries s(s+1)/2, 2s flops each
     product_kernel = ("k_sp2_wide" if args.precision != "fp32" and (tuning or {}).get("tile16", 256) == 256
                       else "k_sp2_step")
+    # the matrix-core rate measured on this GPU at its clock, beside the published peak
+    with torch.cuda.stream(stream):
+        probe = {p: g.gsp2_probe_mfma(p, stream=stream)
+                 for p in {args.precision, *[q for q in args.compare_precisions.split(",") if q]}}
+    log("measured MFMA rate: " + ", ".join(f"{p} {v:.1f} TFLOP/s" for p, v in sorted(probe.items())))
     gemm_flops = float(np.sum(2.0 * s ** 3))
     avg_prod_ms = statistics.fmean(product_ms)
     achieved = MFMA_PRODUCTS[args.precision] * syrk_flops / (avg_prod_ms * 1e-3) / 1e12
@@ -542,6 +547,7 @@ def main():
                          "tflops": round(syrk_flops / (avg * 1e-3) / 1e12, 2),
                          "mfma_products_per_product": MFMA_PRODUCTS[prec],
                          "frac_of_peak": round(hw / (avg * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[prec], 4),
+                         "frac_of_measured_peak": round(hw / (avg * 1e-3) / 1e12 / probe[prec], 4),
                          "rel_diff_vs_fp32_P": diff, "trace_minus_nocc": r0["trace"] - n_occ,
                          "tile16_tuning": tune_rec}
         log(f"{prec}: {ms:.1f} ms/P, {n_mp} products, |P - P_fp32|/|P_fp32| = {diff:.2e}")
@@ -581,7 +587,9 @@ def main():
         "roofline": {
             "bound": "mfma", "kernel": product_kernel,
             "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": counter_traffic(
+            "frac": round(achieved / peak, 4),
+            "measured_peak": round(probe[args.precision], 1),
+            "frac_of_measured_peak": round(achieved / probe[args.precision], 4), "traffic": counter_traffic(
                 args.precision, {"n_mol": args.n_mol, "n_parts": args.n_parts, "tau": args.tau,
                                  "sum_s3": info["sum_s3"]}, product_kernel),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",

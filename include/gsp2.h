@@ -324,6 +324,15 @@ void gsp2_plan_destroy(gsp2_plan plan);
  * nullable (pass NULL first to size it from adj_ptr[n]).  Errors: GSP2_E_INVALID. */
 gsp2_status gsp2_plan_graph(gsp2_plan plan, int64_t *adj_ptr, int32_t *adj_col);
 
+/* Matrix-core rate probe.  Runs back-to-back MFMAs of the product kernels'
+ * shape and operand format (`precision`: FP32, FP16 or BF16 operands; split
+ * FP16 runs FP16 MFMAs) on every CU, two waves per SIMD, for about 30 ms on
+ * `stream` (nullable: the null stream), and returns the rate reached in
+ * TFLOP/s: the measured counterpart of the published peak, at the clock the
+ * GPU runs at.  Allocates and frees a small device buffer; waits for the
+ * stream. */
+gsp2_status gsp2_probe_mfma(int32_t precision, void *stream, double *tflops);
+
 /* Result of gsp2_plan_tune. */
 typedef struct {
     int32_t precision;         /* the 16-bit gsp2_precision tuned */

@@ -689,6 +689,39 @@ gsp2_status gsp2_plan_part_index(gsp2_plan plan, int32_t k, int32_t *idx) {
     });
 }
 
+gsp2_status gsp2_probe_mfma(int32_t precision, void *stream, double *tflops) {
+    float *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const gsp2_status st = guarded([&] {
+        if (!tflops) fail(GSP2_E_INVALID, "null tflops");
+        if (precision < GSP2_PREC_FP32 || precision > GSP2_PREC_FP16X3) fail(GSP2_E_INVALID, "bad precision");
+        int dev = 0, cus = 0;
+        check_hip(hipGetDevice(&dev), "device");
+        check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+        const int blocks = 2 * std::max(cus, 1);                // two 4-wave workgroups per CU
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        check_hip(hipMalloc(&out, sizeof(float) * (size_t)blocks * kProbeThreads), "probe output");
+        check_hip(hipEventCreate(&e0), "event");
+        check_hip(hipEventCreate(&e1), "event");
+        // about 30 ms at the published peak: 16-bit MFMAs run 16 times as
+        // many flops per cycle as FP32 ones and twice as many per call
+        const int n_iter = precision == GSP2_PREC_FP32 ? 12000 : 96000;
+        int64_t flops = 0;
+        check_hip(probe_mfma(precision, n_iter / 16, blocks, out, s, &flops), "probe warm-up");
+        check_hip(hipEventRecord(e0, s), "event");
+        check_hip(probe_mfma(precision, n_iter, blocks, out, s, &flops), "probe");
+        check_hip(hipEventRecord(e1, s), "event");
+        check_hip(hipEventSynchronize(e1), "probe");
+        float ms = 0.0f;
+        check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        *tflops = ms > 0.0f ? (double)flops / (ms * 1e-3) / 1e12 : 0.0;
+    });
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    if (out) hipFree(out);
+    return st;
+}
+
 gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int32_t precision,
                            int32_t n_products, gsp2_tune_info *info) {
     float *scratch = nullptr;

@@ -223,6 +223,10 @@ hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunPara
 // Reverse pass for a known branch sequence: dL/dH on H's stored entries.
 hipError_t launch_backward(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, const int8_t *alphas,
                            int n, const float *dLdP, double *dLdH, const BackwardBuffers &bb, hipStream_t s);
+// Matrix-core rate probe: n_blocks workgroups of kProbeThreads threads of
+// back-to-back MFMAs; *flops receives the matrix-core flops the launch performs.
+constexpr int kProbeThreads = 256;
+hipError_t probe_mfma(int precision, int n_iter, int n_blocks, float *out, hipStream_t s, int64_t *flops);
 // Workgroups of the persistent product kernel that the device keeps resident.
 hipError_t persistent_grid(int precision, int *grid);
 

@@ -1778,6 +1778,62 @@ hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *o
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core rate probe: back-to-back MFMAs of the product kernels' shape
+// (32 x 32 output blocks) on eight independent accumulators per wave, so
+// the matrix pipe never waits on a result; two waves per SIMD on every CU.
+// What the products reach is stated against this measured rate as well as
+// against the published peak.  The sums go to `out` so no MFMA is removed.
+// ---------------------------------------------------------------------------
+constexpr int kProbeAcc = 8;
+
+static_assert(kProbeThreads == kBlock, "probe workgroups are kBlock threads");
+
+template <typename Op>
+__global__ __launch_bounds__(kBlock) void k_mfma_probe(int n_iter, float *__restrict__ out) {
+    v16f acc[kProbeAcc];
+#pragma unroll
+    for (int j = 0; j < kProbeAcc; ++j)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[j][i] = 0.0f;
+    const float x = 1e-3f * static_cast<float>(threadIdx.x & 7);
+    uint4 a, b;
+    {
+        union { Op h[16 / sizeof(Op)]; uint4 u; } ua, ub;
+#pragma unroll
+        for (int e = 0; e < static_cast<int>(16 / sizeof(Op)); ++e) {
+            ua.h[e] = static_cast<Op>(x + 1e-4f * e);
+            ub.h[e] = static_cast<Op>(x - 1e-4f * e);
+        }
+        a = ua.u;
+        b = ub.u;
+    }
+    for (int it = 0; it < n_iter; ++it) {
+#pragma unroll
+        for (int j = 0; j < kProbeAcc; ++j) acc[j] = mfma_chunk_q(a, b, acc[j], Op{});
+    }
+    float t = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kProbeAcc; ++j)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) t += acc[j][i];
+    out[blockIdx.x * kBlock + threadIdx.x] = t;
+}
+
+hipError_t probe_mfma(int precision, int n_iter, int n_blocks, float *out, hipStream_t s, int64_t *flops) {
+    // flops of one mfma_chunk_q call: four 32x32x2 FP32 MFMAs (k = 8 in all),
+    // or one 32x32x16 16-bit MFMA
+    const int64_t per_call = 2LL * 32 * 32 * (precision == GSP2_PREC_FP32 ? 8 : 16);
+    *flops = per_call * kProbeAcc * (int64_t)n_iter * n_blocks * (kBlock / kWave);
+    if (precision == GSP2_PREC_FP32)
+        hipLaunchKernelGGL(k_mfma_probe<float>, dim3(n_blocks), dim3(kBlock), 0, s, n_iter, out);
+    else if (precision == GSP2_PREC_BF16)
+        hipLaunchKernelGGL(k_mfma_probe<__bf16>, dim3(n_blocks), dim3(kBlock), 0, s, n_iter, out);
+    else
+        hipLaunchKernelGGL(k_mfma_probe<_Float16>, dim3(n_blocks), dim3(kBlock), 0, s, n_iter, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, float *P_val,
                           Recorder &rec, const RunEvents *ev) {
     if (H.dtype == GSP2_F64) return density_typed<double>(dp, H, rp, P_val, rec, ev);

@@ -107,6 +107,7 @@ SIGNATURES = {
     "gsp2_plan_graph": (C.c_int, [_PLAN, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "gsp2_plan_tune": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.c_double, C.c_int32, C.c_int32,
                                  C.POINTER(gsp2_tune_info)]),
+    "gsp2_probe_mfma": (C.c_int, [C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
     "gsp2_locality_graph": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_double),
                                       C.c_double, C.c_double, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]),
     "gsp2_partition_anneal": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32,
@@ -277,6 +278,14 @@ def gsp2_plan_part_index(plan: Plan, k: int) -> np.ndarray:
     idx = np.empty(int(ss[k]), dtype=np.int32)
     _check(load().gsp2_plan_part_index(plan.handle, int(k), _i32(idx)))
     return idx
+
+
+def gsp2_probe_mfma(precision: str, stream=None) -> float:
+    """Matrix-core rate (TFLOP/s) of back-to-back MFMAs of the product
+    kernels' shape for `precision`, measured on this GPU (gsp2_probe_mfma)."""
+    out = C.c_double()
+    _check(load().gsp2_probe_mfma(PRECISIONS[precision], C.c_void_p(_stream_handle(stream)), C.byref(out)))
+    return out.value
 
 
 def gsp2_plan_tune(plan: Plan, H: DeviceCSR, n_occ, precision: str, n_products: int = 8) -> dict:

@@ -196,6 +196,15 @@ def test_tune_rejects_bad_arguments_before_any_gpu_call():
     assert "null" in lib.gsp2_last_error().decode()
 
 
+def test_probe_rejects_bad_arguments_before_any_gpu_call():
+    import ctypes as C
+    lib = g.load()
+    out = C.c_double()
+    assert lib.gsp2_probe_mfma(99, None, C.byref(out)) == binding.GSP2_E_INVALID
+    assert "precision" in lib.gsp2_last_error().decode()
+    assert lib.gsp2_probe_mfma(binding.GSP2_PREC_FP32, None, None) == binding.GSP2_E_INVALID
+
+
 def test_run_option_defaults_leave_batch_fields_empty():
     o = g.gsp2_run_options_default()
     assert not o.n_occ_system and not o.alpha_seq_system and not o.n_alpha_system

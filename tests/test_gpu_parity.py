@@ -224,6 +224,16 @@ def test_16bit_products_on_128_tiles(precision):
     assert errs[128] <= bar and errs[256] <= bar
 
 
+@pytest.mark.parametrize("precision,published", [("fp32", 157.3), ("fp16", 2500.0), ("bf16", 2500.0)])
+def test_mfma_probe_rate_is_plausible(precision, published):
+    # back-to-back MFMAs reach most of the published dense peak, and not more
+    # than the peak at the top clock allows
+    import paper_1801_10016_amd as g
+    rate = g.gsp2_probe_mfma(precision)
+    print(f"{precision}: measured {rate:.1f} TFLOP/s of {published}", flush=True)
+    assert 0.6 * published < rate < 1.05 * published
+
+
 def test_tile_autotuner_choice_is_used():
     from tests._gpu import rel_fro, run_gsp2
     s = pins.water(200, 1)
