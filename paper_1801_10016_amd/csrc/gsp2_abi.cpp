@@ -716,9 +716,9 @@ gsp2_status gsp2_probe_mfma(int32_t precision, void *stream, double *tflops) {
         check_hip(hipEventElapsedTime(&ms, e0, e1), "elapsed");
         *tflops = ms > 0.0f ? (double)flops / (ms * 1e-3) / 1e12 : 0.0;
     });
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    if (out) hipFree(out);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (out) (void)hipFree(out);             // waits for the probe launches
     return st;
 }
 
@@ -771,7 +771,7 @@ gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int3
             info->pad_ = 0;
         }
     });
-    if (scratch) hipFree(scratch);
+    if (scratch) (void)hipFree(scratch);     // waits for the tuning runs
     return st;
 }
 
