@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--compare-precisions", default="fp16,bf16,fp16x3",
                     help="after the FP32 timing, also time these operand precisions (empty: none)")
     ap.add_argument("--compare-steps", type=int, default=3)
+    ap.add_argument("--no-library-compare", action="store_true",
+                    help="skip timing the same sub-matrix products with torch.matmul (rocBLAS / hipBLASLt)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the 16-bit tile autotuner (gsp2_plan_tune) and use 256 x 256 tiles")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -115,6 +117,43 @@ def counter_traffic(precision, workload, kernel=None):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
+def library_products(torch, stream, sizes, gemm_flops, ours_ms, reps=3):
+    """The products of one SP2 product step done by the vendor GEMM instead:
+    torch.matmul (rocBLAS / hipBLASLt) of every sub-matrix with itself, the
+    full s_k x s_k result, without the fused update, trace partials or
+    symmetry.  Random operands of the same sizes; median of `reps` timed
+    passes over all parts, after one untimed pass.  A comparison only: no
+    result of it is used."""
+    dtypes = {"fp32": torch.float32, "fp16": torch.float16, "bf16": torch.bfloat16}
+    out = {"what": "torch.matmul of each s_k x s_k sub-matrix with itself (full product, no update), "
+                   "all parts of one product step, event-timed on the bench stream"}
+    for prec, dt in dtypes.items():
+        gen = torch.Generator(device="cuda").manual_seed(0)
+        with torch.cuda.stream(stream):
+            A = [torch.randn(s, s, device="cuda", dtype=dt, generator=gen) / s for s in sizes]
+            Y = [torch.empty(s, s, device="cuda", dtype=dt) for s in sizes]
+            for a, y in zip(A, Y):
+                torch.matmul(a, a, out=y)
+            times = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for a, y in zip(A, Y):
+                    torch.matmul(a, a, out=y)
+                e1.record(stream)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+        ms = statistics.median(times)
+        rec = {"ms_per_product": round(ms, 3), "full_gemm_tflops": round(gemm_flops / (ms * 1e-3) / 1e12, 1)}
+        if prec in ours_ms:
+            rec["product_kernel_ms"] = round(ours_ms[prec], 4)
+            rec["library_over_kernel"] = round(ms / ours_ms[prec], 3)
+        out[prec] = rec
+        del A, Y
+        torch.cuda.empty_cache()
+    return out
 
 
 def threshold_on_host(Pprev, tau):
@@ -554,6 +593,13 @@ def main():
         del P_mp
         torch.cuda.empty_cache()
 
+    library = None
+    if not args.no_library_compare:
+        ours = {args.precision: avg_prod_ms, **{p: c["product_kernel_ms"] for p, c in compare.items()}}
+        library = library_products(torch, stream, [int(v) for v in sub_sizes], gemm_flops, ours)
+        log("library products: " + ", ".join(f"{p} {v['ms_per_product']:.2f} ms" for p, v in library.items()
+                                             if isinstance(v, dict)))
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline: timing the FP64 oracle on a sample of parts")
@@ -611,6 +657,7 @@ def main():
         "plan_ms": round(plan_s * 1e3, 1),
         "plan_info": {k: info[k] for k in ("nnz_graph", "nnz_P", "sum_s", "workspace_bytes")},
         "previous_P_s": round(boot_s, 2),
+        "library_products": library,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
