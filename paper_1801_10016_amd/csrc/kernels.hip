@@ -879,7 +879,8 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
             fb_[m] = Bsb[(wc * 128 + m * 32 + l32) * kLdsRow + w];
         }
     };
-    auto compute = [&](int buf, const uint4 (&sa)[8], const uint4 (&sb)[8]) {
+    auto compute = [&](int buf, uint4 (&sa)[8], uint4 (&sb)[8], __amdgpu_buffer_rsrc_t ra,
+                       __amdgpu_buffer_rsrc_t rb, uint32_t kb) {
         uint4 *As_ = lds(buf ^ 1, 0) + lr * kLdsRow + lw;
         uint4 *Bs_ = lds(buf ^ 1, 1) + lr * kLdsRow + lw;
 #pragma unroll
@@ -895,12 +896,17 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 #pragma unroll
                 for (int nn = 0; nn < 4; ++nn)
                     acc[m][nn] = mfma_chunk_q(fa[q & 1][m], fb[q & 1][nn], acc[m][nn], Op{});
-            // passes 0-2 in step 0, 3-5 in step 1, 6-7 in step 2
+            // passes 0-2 in step 0, 3-5 in step 1, 6-7 in step 2; each
+            // register is loaded again (chunk c + 3) as soon as it is stored
             const int p0 = 3 * q, np = q < 2 ? 3 : (q == 2 ? 2 : 0);
 #pragma unroll
             for (int p = 0; p < np; ++p) {
                 As_[(p0 + p) * 32 * kLdsRow] = sa[p0 + p];
                 Bs_[(p0 + p) * 32 * kLdsRow] = sb[p0 + p];
+                sa[p0 + p] = __builtin_bit_cast(
+                    uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, offA, passA[p0 + p] + kb, 0));
+                sb[p0 + p] = __builtin_bit_cast(
+                    uint4, __builtin_amdgcn_raw_buffer_load_b128(rb, offB, passB[p0 + p] + kb, 0));
             }
             // the compiler's MFMA / LDS interleave for one wave per SIMD (3% faster
             // than placing one LDS access after each of the first MFMAs, measured)
@@ -926,18 +932,18 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
         GSP2W_STORE(0, 0);
         GSP2W_SRC(c0 + 1, ra, rb, kb);
         GSP2W_LOAD(1, ra, rb, kb);
+        GSP2W_SRC(min(c0 + 2, c1 - 1), ra, rb, kb);
+        GSP2W_LOAD(0, ra, rb, kb);
         __syncthreads();
         frags(0, 0, fa[0], fb[0]);
         for (int kc = c0; kc < c1; kc += 2) {
             // past the end the last chunk is loaded again, so that every
             // load is unconditional and the waits before the stores count
             // exactly the loads issued after them
-            GSP2W_SRC(min(kc + 2, c1 - 1), ra, rb, kb);
-            GSP2W_LOAD(0, ra, rb, kb);
-            compute(0, pa[1], pb[1]);
             GSP2W_SRC(min(kc + 3, c1 - 1), ra, rb, kb);
-            GSP2W_LOAD(1, ra, rb, kb);
-            compute(1, pa[0], pb[0]);
+            compute(0, pa[1], pb[1], ra, rb, kb);
+            GSP2W_SRC(min(kc + 4, c1 - 1), ra, rb, kb);
+            compute(1, pa[0], pb[0], ra, rb, kb);
         }
         __syncthreads();
     };
