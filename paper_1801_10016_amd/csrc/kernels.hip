@@ -1009,6 +1009,7 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 #pragma unroll
             for (int nn = 0; nn < 4; ++nn) {
                 const int cg = J0 + wc * 128 + nn * 32 + l32;
+                uint2 pkg[4];                           // 16-bit X' of this lane's rows, per g (plain)
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int rg0 = I0 + wr * 128 + m * 32 + g * 8 + kh * 4;
@@ -1034,35 +1035,74 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
                         union { Op h[4]; uint2 u; } pk, pl;
 #pragma unroll
                         for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
-                        *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
                         if constexpr (kSplit) {
+                            *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
 #pragma unroll
                             for (int e = 0; e < 4; ++e)
                                 pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
                             *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
+                        } else {
+                            pkg[g] = pk.u;
                         }
                     }
                 }
+                // plain operands: the 16-bit mirrored writes as 16-byte pieces.
+                // For g = 2p, 2p + 1 the lane halves swap one quadruple each, so
+                // lane half 0 holds rows 16p .. 16p + 7 of column cg and half 1
+                // rows 16p + 8 .. 16p + 15 (split operands keep 8-byte pieces:
+                // the exchange costs them more than it saves)
+                if (!kSplit && !diag) {
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const int rgp = I0 + wr * 128 + m * 32 + 16 * p + 8 * kh;
+                        const uint2 sh = kh ? pkg[2 * p] : pkg[2 * p + 1];
+                        const uint2 rh = make_uint2(__shfl_xor(sh.x, 32, kWave), __shfl_xor(sh.y, 32, kWave));
+                        const uint4 oh = kh ? make_uint4(rh.x, rh.y, pkg[2 * p + 1].x, pkg[2 * p + 1].y)
+                                            : make_uint4(pkg[2 * p].x, pkg[2 * p].y, rh.x, rh.y);
+                        *reinterpret_cast<uint4 *>(Xnop + (int64_t)cg * ld + rgp) = oh;
+                    }
+                }
             }
-            // the band's rows back from LDS: lane (r2, c4) takes row 2 i + r2,
-            // columns 4 c4 .. 4 c4 + 3 (the wave's own LDS, written above)
-            const int c4 = lane & 31, r2 = lane >> 5;
+            // the band's rows back from LDS (the wave's own, written above).
+            // Plain operands: lane (r4, c8) takes row 4 i + r4, columns 8 c8 ..
+            // 8 c8 + 7, one 16-byte piece of the 16-bit copy.  Split operands:
+            // lane (r2, c4) takes row 2 i + r2, columns 4 c4 .. 4 c4 + 3, one
+            // 8-byte piece of each of hi and lo (the 16-byte form was slower
+            // there).
+            if constexpr (kSplit) {
+                const int c4 = lane & 31, r2 = lane >> 5;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int r = 2 * i + r2;
-                const float4 v4 = *reinterpret_cast<const float4 *>(band + r * kBandRow + c4 * 4);
-                const int64_t o = (int64_t)(I0 + wr * 128 + m * 32 + r) * ld + J0 + wc * 128 + c4 * 4;
-                if (!kSplit && diag) *reinterpret_cast<float4 *>(Xn + o) = v4;
-                const float xv[4] = {v4.x, v4.y, v4.z, v4.w};
-                union { Op h[4]; uint2 u; } pk, pl;
+                for (int i = 0; i < 16; ++i) {
+                    const int r = 2 * i + r2;
+                    const float4 v4 = *reinterpret_cast<const float4 *>(band + r * kBandRow + c4 * 4);
+                    const int64_t o = (int64_t)(I0 + wr * 128 + m * 32 + r) * ld + J0 + wc * 128 + c4 * 4;
+                    const float xv[4] = {v4.x, v4.y, v4.z, v4.w};
+                    union { Op h[4]; uint2 u; } pk, pl;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xv[e]);
-                *reinterpret_cast<uint2 *>(Xnop + o) = pk.u;
-                if constexpr (kSplit) {
+                    for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xv[e]);
+                    *reinterpret_cast<uint2 *>(Xnop + o) = pk.u;
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         pl.h[e] = static_cast<Op>((xv[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
                     *reinterpret_cast<uint2 *>(Xnlo + o) = pl.u;
+                }
+            } else {
+                const int c8 = lane & 15, r4 = lane >> 4;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int r = 4 * i + r4;
+                    const float4 va = *reinterpret_cast<const float4 *>(band + r * kBandRow + c8 * 8);
+                    const float4 vb = *reinterpret_cast<const float4 *>(band + r * kBandRow + c8 * 8 + 4);
+                    const int64_t o = (int64_t)(I0 + wr * 128 + m * 32 + r) * ld + J0 + wc * 128 + c8 * 8;
+                    if (diag) {
+                        *reinterpret_cast<float4 *>(Xn + o) = va;
+                        *reinterpret_cast<float4 *>(Xn + o + 4) = vb;
+                    }
+                    const float xv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
+                    union { Op h[8]; uint4 u; } pk;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) pk.h[e] = static_cast<Op>(xv[e]);
+                    *reinterpret_cast<uint4 *>(Xnop + o) = pk.u;
                 }
             }
         }
