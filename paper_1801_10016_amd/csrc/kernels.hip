@@ -572,11 +572,13 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     //
     // Operands arrive two chunks ahead in two register sets: chunk c + 1 is
     // stored into LDS after the MFMAs of chunk c, from the set loaded before
-    // the MFMAs of chunk c - 1.  Chunk counts are even (s_pad is a multiple of
-    // 128), so the loop takes chunks in pairs with the sets fixed; past the end
+    // the MFMAs of chunk c - 1.  Chunk counts are even (below), so the loop
+    // takes chunks in pairs with the sets fixed; past the end
     // the last chunk is loaded again, so every load is unconditional, and the
     // last pair stores it a second time into a buffer no wave reads again.
-    const int nk = ld / kK;
+    // Columns from s on are zero padding, so the K loop stops at the first
+    // even chunk count covering s (exact: the skipped terms are zeros).
+    const int nk = 2 * ((pd.s + 2 * kK - 1) / (2 * kK));
     const int nc = kSplit ? 3 * nk : nk;
     uint4 pa00, pa01, pa02, pa03, pb00, pb01, pb02, pb03;   // register set 0
     uint4 pa10, pa11, pa12, pa13, pb10, pb11, pb12, pb13;   // register set 1
