@@ -39,9 +39,9 @@ typedef enum {
     GSP2_E_INVALID = 1,        /* bad argument, size mismatch, empty part, non-finite H */
     GSP2_E_HIP = 2,            /* a HIP runtime call failed */
     GSP2_E_OOM = 3,            /* device or host allocation failed */
-    GSP2_E_NOT_CONVERGED = 4,  /* the stop rule did not fire within max_iter products,
-                                  or the iteration left the finite range */
-    GSP2_E_WRONG_TRACE = 5,    /* a replayed branch sequence missed n_occ by more than trace_tol */
+    GSP2_E_NOT_CONVERGED = 4,  /* the stop rule did not fire within max_iter products (or was
+                                  switched off), or the iteration left the finite range */
+    GSP2_E_WRONG_TRACE = 5,    /* the returned P's trace misses n_occ by more than trace_tol */
     GSP2_E_UNSUPPORTED = 6     /* option not available in this library */
 } gsp2_status;
 
@@ -53,15 +53,19 @@ typedef enum {
 } gsp2_alpha_mode;
 
 /* Operand precision of the SP2 products.  Accumulation, the master copy of
- * every iterate and the eq. (2) update are FP32 in all modes; traces FP64. */
+ * every iterate and the eq. (2) update are FP32 in all modes but
+ * GSP2_PREC_FP64, where they are FP64; traces are FP64 in every mode. */
 typedef enum {
     GSP2_PREC_FP32 = 0,        /* FP32 operands (v_mfma_f32_32x32x2_f32) */
     GSP2_PREC_FP16 = 1,        /* FP16 operands (v_mfma_f32_32x32x16_f16) */
     GSP2_PREC_BF16 = 2,        /* BF16 operands (v_mfma_f32_32x32x16_bf16) */
-    GSP2_PREC_FP16X3 = 3       /* split FP16 operands: X = A + 2^-11 B with A = fp16(X) and
+    GSP2_PREC_FP16X3 = 3,      /* split FP16 operands: X = A + 2^-11 B with A = fp16(X) and
                                   B = fp16(2^11 (X - A)); X^2 as 2^-11 (A B + B A) + A A, three
                                   FP16 products accumulated in FP32, about as accurate as FP32
                                   products (the dropped B B term is 2^-22 relative) */
+    GSP2_PREC_FP64 = 4         /* FP64 operands, accumulation, iterate and update
+                                  (v_mfma_f64_16x16x4_f64): the double-precision dgemm
+                                  arithmetic of the paper's runs (Results); P is written in FP64 */
 } gsp2_precision;
 /* The 16-bit modes need every part's padded size (s_k rounded up to 128) to
  * be at most 46,336, so that a part's operand matrix is under 4 GiB; larger
@@ -118,13 +122,17 @@ typedef struct {
     const int8_t *alpha_seq;   /* host, replay mode only: n_alpha entries, each +1 or -1 */
     int32_t n_alpha;           /* replay mode: number of products to apply (<= GSP2_MAX_ITER) */
     int32_t stop_rule;         /* trace mode: 1 = stop when idempotency stops improving
-                                  (default); 0 = always form max_iter products */
-    double trace_tol;          /* replay mode: allowed |Tr P - n_occ|, default 0.5 */
+                                  (default); 0 = always form max_iter products (the run then
+                                  ends with GSP2_E_NOT_CONVERGED: nothing shows convergence) */
+    double trace_tol;          /* allowed |Tr P - n_occ| of the returned P, checked at the end of
+                                  every run (trace mode: after the stop and any refinement;
+                                  replay mode: after the replayed branches), default 0.5 */
     int32_t timing;            /* 1 = record HIP events around every phase and product
                                   (read with gsp2_run_timing); default 0 */
     int32_t precision;         /* gsp2_precision of the products, default GSP2_PREC_FP32 */
-    int32_t refine;            /* FP32 products appended after the stop, alternating X^2 and
-                                  2X - X^2, 0..8, default 0; max_iter + refine <= GSP2_MAX_ITER */
+    int32_t refine;            /* FP32 products (FP64 products in GSP2_PREC_FP64 runs) appended
+                                  after the stop, alternating X^2 and 2X - X^2, 0..8, default 0;
+                                  max_iter + refine <= GSP2_MAX_ITER */
     int32_t persistent;        /* must be 0 (one launch per product, all in one HIP graph).
                                   1 would put all products before the stop in one persistent
                                   launch with a grid barrier per product; that path is switched
@@ -135,6 +143,11 @@ typedef struct {
     const int8_t *alpha_seq_system;  /* host, replay mode: n_systems rows of GSP2_MAX_ITER
                                         branches, row-major; NULL = alpha_seq for every system */
     const int32_t *n_alpha_system;   /* host, n_systems lengths of those rows (<= GSP2_MAX_ITER) */
+    int32_t symmetrize;        /* 0 (default): P[idx_k, j] = X_k[:, j] as assembled from each
+                                  part's core columns, which need not be symmetric; 1: every
+                                  stored entry whose mirror is stored too becomes the mean of the
+                                  two, and an entry whose mirror lies outside P's pattern is kept */
+    int32_t pad_;
 } gsp2_run_options;
 
 #define GSP2_MAX_ITER 100
@@ -242,7 +255,8 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
  *   then, for t = 0, 1, ...: Y_k = X_k X_k on every part (eq. (2)),
  *   e_t = Tr[X_t] - Tr[Y_t]; stop (trace mode, stop_rule = 1) at the first
  *   t >= 2 with |e_t| >= |e_{t-2}| and |e_{t-2}| < max(1, n u), u the unit
- *   roundoff of the product operands (2^-24, 2^-11, 2^-8), returning X_t; otherwise
+ *   roundoff of the product operands (2^-24, 2^-11, 2^-8, 2^-22, 2^-53 for FP32,
+ *   FP16, BF16, split FP16, FP64), returning X_t; otherwise
  *   X_k <- 2 X_k - Y_k when Tr[X_t] <= n_occ, else X_k <- Y_k (replay mode:
  *   the supplied branches, then the trace check).  Tr is the sum over parts
  *   of the diagonal of each part's core rows.  P[idx_k, j] = X_k[:, j]
@@ -253,16 +267,25 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
  *   Gershgorin discs of their rows).
  * Arithmetic: products on the matrix cores with FP32 accumulation and FP32,
  * FP16 or BF16 operands (run->precision); the master iterate and the update
- * stay FP32; Gershgorin bounds, X0 and all traces are FP64.  With refine > 0,
- * that many FP32 products follow the stop (or the last replayed branch),
- * alternating X^2 and 2X - X^2 (each pair a purification sweep that drives
- * every eigenvalue to the nearer of 0 and 1), and the last one is returned.
+ * stay FP32; Gershgorin bounds, X0 and all traces are FP64.  GSP2_PREC_FP64
+ * runs every step in FP64 (operands, accumulation, iterate, update, P).
+ * With refine > 0, that many FP32 products (FP64 in FP64 runs) follow the
+ * stop (or the last replayed branch), alternating X^2 and 2X - X^2 (each pair
+ * a purification sweep that drives every eigenvalue to the nearer of 0 and
+ * 1), and the last one is returned.
+ * Status: the run fails with GSP2_E_WRONG_TRACE when the returned P's trace
+ * misses n_occ by more than run->trace_tol (in trace mode too: a wrong final
+ * trace marks a failed SP2 run), and with GSP2_E_NOT_CONVERGED when the stop
+ * rule did not fire within max_iter products or was switched off
+ * (stop_rule = 0); P_val is written in both cases.
  *
  *  H       device CSR, n x n, symmetric; its pattern may change between calls.
  *  n_occ   number of occupied states N_el / 2, 0 <= n_occ <= n (ignored by
  *          batched plans, which take run->n_occ_system).
  *  run     nullable (defaults).
- *  P_val   device, nnz_P floats in the order of gsp2_plan_pattern; caller-owned.
+ *  P_val   device, nnz_P values in the order of gsp2_plan_pattern, doubles
+ *          when run->precision is GSP2_PREC_FP64 and floats otherwise;
+ *          caller-owned.
  *  info    nullable; otherwise n_systems structs, one per system of the plan.
  *          When given, the call waits for the results and returns the first
  *          failing system's status (GSP2_OK if none); otherwise it returns
@@ -276,7 +299,7 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
  * contents of P_val are unspecified.
  */
 gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ,
-                         const gsp2_run_options *run, float *P_val, gsp2_run_info *info);
+                         const gsp2_run_options *run, void *P_val, gsp2_run_info *info);
 
 /* Wait for the last gsp2_density on this plan and report its device times,
  * measured with HIP events on the plan's stream.  Errors: GSP2_E_INVALID

@@ -12,12 +12,12 @@ from .sp2 import (gershgorin_bounds, initial_guess, sp2_blocks, dense_sp2,
                   SP2Result, NotConverged, WrongTrace)
 from .graph import threshold_graph, core_halo, ch_cost, subproblem_index
 from .gsp2 import gsp2, GSP2Result
-from .spectral import eig_projector, spectral_gap, iterate_on_eigenvalues
+from .spectral import eig_projector, spectral_gap
 from .adjoint import gsp2_grad, gershgorin_rows, GSP2Grad
 
 __all__ = [
     "gershgorin_bounds", "initial_guess", "sp2_blocks", "dense_sp2", "SP2Result",
     "NotConverged", "WrongTrace", "threshold_graph", "core_halo", "ch_cost",
     "subproblem_index", "gsp2", "GSP2Result", "eig_projector", "spectral_gap",
-    "iterate_on_eigenvalues", "gsp2_grad", "gershgorin_rows", "GSP2Grad",
+    "gsp2_grad", "gershgorin_rows", "GSP2Grad",
 ]

@@ -9,7 +9,11 @@ core trace, and reassemble P from each part's core columns.
 
 Every vertex is core in exactly one part, so P has exactly one source for
 each of its columns; entries outside part k's rows in a core column of part
-k are zero.  With ``symmetrize`` the assembled P is replaced by (P + P^T)/2.
+k are zero (not stored).  The assembled P need not be symmetric.  With
+``symmetrize`` every stored entry whose mirror is stored too becomes the mean
+of the two; an entry whose mirror is not stored is kept as it is (reading of
+"collected and reassembled" in the Fig. 1 description: the result keeps the
+pattern the parts define).
 """
 from __future__ import annotations
 
@@ -37,21 +41,31 @@ class GSP2Result:
         return [len(i) for i in self.index]
 
     def dense(self, symmetrize: bool = False) -> np.ndarray:
+        if symmetrize:
+            return self.csc(symmetrize=True).toarray()
         P = np.zeros((self.n, self.n))
         for idx, core, blk in zip(self.index, self.cores, self.core_columns):
             P[np.ix_(idx, core)] = blk
-        if symmetrize:
-            P = 0.5 * (P + P.T)
         return P
 
-    def csc(self) -> sp.csc_matrix:
+    def csc(self, symmetrize: bool = False) -> sp.csc_matrix:
         """P with each core column's rows sorted by global index."""
         rows, cols, vals = [], [], []
         for idx, core, blk in zip(self.index, self.cores, self.core_columns):
             for jl, j in enumerate(core):
                 rows.append(idx); cols.append(np.full(len(idx), j)); vals.append(blk[:, jl])
-        P = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
-                          shape=(self.n, self.n)).tocsc()
+        r, c, v = np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
+        if symmetrize:
+            # position of every stored entry's mirror, or -1 when it is not stored
+            key = r.astype(np.int64) * self.n + c
+            mirror = c.astype(np.int64) * self.n + r
+            order = np.argsort(key)
+            pos = np.searchsorted(key[order], mirror)
+            pos = np.minimum(pos, len(key) - 1)
+            found = key[order][pos] == mirror
+            w = np.where(found, v[order][pos], v)
+            v = np.where(found, 0.5 * (v + w), v)
+        P = sp.coo_matrix((v, (r, c)), shape=(self.n, self.n)).tocsc()
         P.sort_indices()
         return P
 

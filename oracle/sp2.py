@@ -29,6 +29,10 @@ notes):
   applied, no stop rule, and the result is rejected when its trace misses
   N_occ by more than ``trace_tol`` (the paper's check on a stored
   sequence).
+* Occupation.  The same check applies when the stop rule fires: a result
+  whose trace misses N_occ by more than ``trace_tol`` is a failed run
+  (status "wrong_trace"), since the SP2 section ties a correct run to a
+  final trace equal to the electron count.
 """
 from __future__ import annotations
 
@@ -106,7 +110,11 @@ def sp2_blocks(X0: list, cores: list, n_occ: float, max_iter: int = 60,
         errors.append(tr - trY)
         if (not replay and stop_rule and t >= 2 and abs(errors[t]) >= abs(errors[t - 2])
                 and abs(errors[t - 2]) < floor):
-            return SP2Result(X, t + 1, alphas, traces, errors, True)
+            if abs(tr - n_occ) <= trace_tol:
+                return SP2Result(X, t + 1, alphas, traces, errors, True)
+            if raise_on_failure:
+                raise WrongTrace(f"trace {tr} vs N_occ {n_occ}")
+            return SP2Result(X, t + 1, alphas, traces, errors, False, "wrong_trace")
         if replay:
             alpha = int(alpha_seq[t])
         else:

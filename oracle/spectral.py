@@ -2,9 +2,8 @@
 
 The density matrix is the sum of outer products of the occupied eigenstates
 of H (Introduction); SP2 reaches it as the limit of eq. (3).  These helpers
-compute that target by LAPACK diagonalisation, and the scalar recursion of
-eq. (2) on eigenvalues, which every iterate must reproduce in H's eigenbasis
-(each iterate is a polynomial in H).
+compute that target, and the gap between the highest occupied and lowest
+unoccupied eigenvalue that makes it unique, by LAPACK diagonalisation.
 """
 from __future__ import annotations
 
@@ -24,13 +23,7 @@ def eig_projector(H, n_occ: int) -> np.ndarray:
 
 
 def spectral_gap(H, n_occ: int) -> float:
+    """eps_{n_occ + 1} - eps_{n_occ}: lowest unoccupied minus highest occupied
+    eigenvalue (eigenvalues ascending, counted from 1)."""
     w = np.linalg.eigvalsh(_dense(H))
     return float(w[int(n_occ)] - w[int(n_occ) - 1])
-
-
-def iterate_on_eigenvalues(x0: np.ndarray, alphas) -> np.ndarray:
-    """Apply x <- x + a (x - x^2) for each branch a to scalar eigenvalues."""
-    x = np.array(x0, dtype=np.float64, copy=True)
-    for a in alphas:
-        x = x + a * (x - x * x)
-    return x

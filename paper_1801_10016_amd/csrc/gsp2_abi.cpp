@@ -155,7 +155,7 @@ struct GraphKey {
     const void *h_ptr = nullptr, *h_col = nullptr, *h_val = nullptr;
     int64_t h_nnz = -1;
     int32_t h_dtype = -1;
-    float *p_val = nullptr;
+    void *p_val = nullptr;
     RunParams rp{};
     bool timing = false;
     bool operator==(const GraphKey &o) const {
@@ -287,6 +287,7 @@ gsp2_status gsp2_run_options_default(gsp2_run_options *opt) {
         opt->n_occ_system = nullptr;
         opt->alpha_seq_system = nullptr;
         opt->n_alpha_system = nullptr;
+        opt->symmetrize = 0;
     });
 }
 
@@ -887,7 +888,7 @@ static gsp2_status collect(gsp2_plan_s *plan, gsp2_run_info *info) {
 }
 
 gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const gsp2_run_options *run,
-                         float *P_val, gsp2_run_info *info) {
+                         void *P_val, gsp2_run_info *info) {
     gsp2_status st = guarded([&] {
         if (!plan) fail(GSP2_E_INVALID, "null plan");
         if (!H) fail(GSP2_E_INVALID, "null H");
@@ -906,17 +907,21 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         rp.mode = o.alpha_mode;
         rp.stop_rule = o.stop_rule ? 1 : 0;
         if (o.precision != GSP2_PREC_FP32 && o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16 &&
-            o.precision != GSP2_PREC_FP16X3)
+            o.precision != GSP2_PREC_FP16X3 && o.precision != GSP2_PREC_FP64)
             fail(GSP2_E_INVALID, "bad precision");
-        if (o.precision != GSP2_PREC_FP32 && plan->dp.max_s_pad > kMaxWidePad)
+        const bool wide16 = o.precision == GSP2_PREC_FP16 || o.precision == GSP2_PREC_BF16 ||
+                            o.precision == GSP2_PREC_FP16X3;
+        if (wide16 && plan->dp.max_s_pad > kMaxWidePad)
             fail(GSP2_E_UNSUPPORTED, "16-bit products need every padded sub-problem size <= " +
                                          std::to_string(kMaxWidePad));
         if (o.refine < 0 || o.refine > 8) fail(GSP2_E_INVALID, "refine must be in 0..8");
+        if (o.symmetrize != 0 && o.symmetrize != 1) fail(GSP2_E_INVALID, "symmetrize must be 0 or 1");
         rp.precision = o.precision;
         rp.refine = o.refine;
         rp.persistent = o.persistent ? 1 : 0;
+        rp.symmetrize = o.symmetrize;
         rp.tile16 = 0;
-        if (rp.precision != GSP2_PREC_FP32)
+        if (wide16)
             rp.tile16 = plan->tile16_fixed ? plan->tile16_fixed
                         : plan->tile16_tuned[rp.precision] ? plan->tile16_tuned[rp.precision] : kTileWide;
         if (rp.persistent)
@@ -936,9 +941,10 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         const double u = o.precision == GSP2_PREC_FP16     ? std::ldexp(1.0, -11)
                          : o.precision == GSP2_PREC_BF16   ? std::ldexp(1.0, -8)
                          : o.precision == GSP2_PREC_FP16X3 ? std::ldexp(1.0, -22)
+                         : o.precision == GSP2_PREC_FP64   ? std::ldexp(1.0, -53)
                                                            : std::ldexp(1.0, -24);
+        if (!(o.trace_tol >= 0.0)) fail(GSP2_E_INVALID, "trace_tol must be >= 0");
         if (o.alpha_mode == GSP2_ALPHA_REPLAY) {
-            if (!(o.trace_tol >= 0.0)) fail(GSP2_E_INVALID, "trace_tol must be >= 0");
         } else if (o.alpha_mode == GSP2_ALPHA_TRACE) {
             if (o.max_iter < 1 || o.max_iter > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter out of range");
         } else {
@@ -970,7 +976,12 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
             rp.n_steps = std::max(rp.n_steps, sp.n_steps);
         }
         if (rp.n_steps + rp.refine > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter + refine exceeds GSP2_MAX_ITER");
-        if (rp.precision != GSP2_PREC_FP32 && !plan->dp.shadow[0]) {
+        if (rp.precision == GSP2_PREC_FP64 && !plan->dp.buf64[0]) {
+            // FP64 iterates, allocated on the first FP64 run
+            plan->dp.buf64[0] = plan->alloc<double>(plan->arena_floats, "FP64 X buffer 0");
+            plan->dp.buf64[1] = plan->alloc<double>(plan->arena_floats, "FP64 X buffer 1");
+        }
+        if (wide16 && !plan->dp.shadow[0]) {
             // 16-bit operand copies of both X buffers, allocated on the first mixed-precision run
             plan->dp.shadow[0] = plan->alloc<uint16_t>(plan->arena_floats, "16-bit X copy 0");
             plan->dp.shadow[1] = plan->alloc<uint16_t>(plan->arena_floats, "16-bit X copy 1");

@@ -105,7 +105,7 @@ struct RunParams {
     int32_t refine;             // FP32 products after the main phase
     int32_t persistent;         // 1: main-phase products in one persistent launch
     int32_t tile16;             // 16-bit products: 256 (k_sp2_wide) or 128 (k_sp2_step) tiles
-    int32_t pad_;
+    int32_t symmetrize;         // scatter the mean of mirrored stored pairs
 };
 
 // Per-call parameters of one system, uploaded to the device before each run.
@@ -130,6 +130,7 @@ struct DevicePlan {
     int32_t gersh_blocks;       // row blocks of the Gershgorin kernel
     int32_t n_sys;              // systems (1 unless batched)
     float *buf[2];
+    double *buf64[2];           // FP64 iterates (FP64 products), allocated on the first FP64 run
     void *shadow[2];            // 16-bit operand copies of the two X buffers (mixed precision)
     void *shadow_lo[2];         // scaled FP16 low parts of the two X buffers (split FP16 products)
     const PartDesc *parts;
@@ -219,7 +220,7 @@ hipError_t launch_threshold_count(const gsp2_csr &P, double tau, int32_t *counts
 hipError_t launch_threshold_fill(const gsp2_csr &P, double tau, const int64_t *out_ptr,
                                  int32_t *out_col, hipStream_t s);
 hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp,
-                          float *P_val, Recorder &rec, const RunEvents *ev);
+                          void *P_val, Recorder &rec, const RunEvents *ev);
 // Reverse pass for a known branch sequence: dL/dH on H's stored entries.
 hipError_t launch_backward(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, const int8_t *alphas,
                            int n, const float *dLdP, double *dLdH, const BackwardBuffers &bb, hipStream_t s);

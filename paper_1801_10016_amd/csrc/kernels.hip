@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_run_init(const double *__restrict__ 
 // rows.
 // ---------------------------------------------------------------------------
 constexpr int kGatherLdsIdx = 8192;    // vertex list held in LDS up to this size
-constexpr int kGatherChunk = 2048;     // row segment built in LDS per wave and pass
+constexpr int kGatherChunkBytes = 8192;  // row segment built in LDS per wave and pass (2,048 FP32 or 1,024 FP64)
 
 // Orders a wave's LDS accesses: writes by any lane before the call are seen
 // by reads of any lane after it.
@@ -249,19 +249,20 @@ __device__ __forceinline__ uint2 pack4_fp16_lo(float4 v) {
     return x.u;
 }
 
-template <typename T>
+template <typename T, typename XT>
 __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ col,
                                                       const T *__restrict__ val,
                                                       const PartDesc *__restrict__ parts,
                                                       const RowChunk *__restrict__ chunks,
                                                       const int32_t *__restrict__ idx_arena,
-                                                      float *__restrict__ X, uint16_t *__restrict__ Xs,
+                                                      XT *__restrict__ X, uint16_t *__restrict__ Xs,
                                                       uint16_t *__restrict__ Xlo,
                                                       const RunState *__restrict__ st_all,
                                                       double *__restrict__ x0_partials) {
+    constexpr int kChunk = kGatherChunkBytes / static_cast<int>(sizeof(XT));   // a multiple of 128
     __shared__ int32_t idx_s[kGatherLdsIdx];
-    __shared__ float4 row_s4[kBlock / kWave][kGatherChunk / 4];
+    __shared__ uint4 row_u4[kBlock / kWave][kGatherChunkBytes / 16];
     __shared__ double tr_s[kBlock / kWave];
     const RowChunk ch = chunks[blockIdx.x];
     const PartDesc pd = parts[ch.part];
@@ -277,22 +278,23 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
     const double emin = st->eps_min, emax = st->eps_max;
     const double inv = 1.0 / (emax - emin);
     const int ld = pd.s_pad;
-    float *Xp = X + pd.x_off;
+    XT *Xp = X + pd.x_off;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    float4 *row4 = row_s4[wave];
-    float *row_s = reinterpret_cast<float *>(row4);
+    uint4 *row_u = row_u4[wave];
+    XT *row_s = reinterpret_cast<XT *>(row_u);
     const int prec = st->precision;
     double tr = 0.0;
     for (int r = ch.r0 + wave; r < ch.r1; r += kBlock / kWave) {
         const bool real = r < pd.s;
         const int64_t g = real ? idx[r] : -1;
         const int64_t hb = real ? row_ptr[g] : 0, he = real ? row_ptr[g + 1] : 0;
-        for (int c0 = 0; c0 < ld; c0 += kGatherChunk) {
-            const int cw = min(kGatherChunk, ld - c0);   // a multiple of 128
-            for (int i = lane; i < cw / 4; i += kWave) row4[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int c0 = 0; c0 < ld; c0 += kChunk) {
+            const int cw = min(kChunk, ld - c0);         // a multiple of 128
+            const int n16 = cw * static_cast<int>(sizeof(XT)) / 16;
+            for (int i = lane; i < n16; i += kWave) row_u[i] = make_uint4(0u, 0u, 0u, 0u);
             wave_lds_sync();
             if (real && lane == 0 && r >= c0 && r < c0 + cw)
-                row_s[r - c0] = static_cast<float>(emax * inv);       // H_gg = 0 if not stored
+                row_s[r - c0] = static_cast<XT>(emax * inv);          // H_gg = 0 if not stored
             wave_lds_sync();
             for (int64_t e = hb + lane; e < he; e += kWave) {
                 const int32_t cg = col[e];
@@ -304,20 +306,25 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
                 if (q >= c0 && q < c0 + cw) {
                     const double h = as_double(val[e]);
                     const double x = (cg == g) ? (emax - h) * inv : -h * inv;
-                    row_s[q - c0] = static_cast<float>(x);
+                    row_s[q - c0] = static_cast<XT>(x);
                 }
             }
             wave_lds_sync();
             if (real && r < pd.c && lane == 0 && r >= c0 && r < c0 + cw)
                 tr += static_cast<double>(row_s[r - c0]);
-            float4 *dst = reinterpret_cast<float4 *>(Xp + (int64_t)r * ld + c0);
-            uint2 *dsh = Xs ? reinterpret_cast<uint2 *>(Xs + pd.x_off + (int64_t)r * ld + c0) : nullptr;
-            uint2 *dlo = Xlo ? reinterpret_cast<uint2 *>(Xlo + pd.x_off + (int64_t)r * ld + c0) : nullptr;
-            for (int i = lane; i < cw / 4; i += kWave) {
-                const float4 v = row4[i];
-                dst[i] = v;
-                if (dsh) dsh[i] = pack4(v, prec);
-                if (dlo) dlo[i] = pack4_fp16_lo(v);
+            uint4 *dst = reinterpret_cast<uint4 *>(Xp + (int64_t)r * ld + c0);
+            if constexpr (sizeof(XT) == 4) {
+                uint2 *dsh = Xs ? reinterpret_cast<uint2 *>(Xs + pd.x_off + (int64_t)r * ld + c0) : nullptr;
+                uint2 *dlo = Xlo ? reinterpret_cast<uint2 *>(Xlo + pd.x_off + (int64_t)r * ld + c0) : nullptr;
+                for (int i = lane; i < n16; i += kWave) {
+                    const uint4 u = row_u[i];
+                    dst[i] = u;
+                    const float4 v = __builtin_bit_cast(float4, u);
+                    if (dsh) dsh[i] = pack4(v, prec);
+                    if (dlo) dlo[i] = pack4_fp16_lo(v);
+                }
+            } else {
+                for (int i = lane; i < n16; i += kWave) dst[i] = row_u[i];
             }
             wave_lds_sync();                             // reads done before the next zeroing
         }
@@ -365,14 +372,25 @@ __device__ void ctl_store(RunState *st, const Ctl &c) {
     st->n_refine = c.n_refine; st->main_status = c.main_status; st->n_main = c.n_main;
 }
 
-// End of the main phase: hand over to the FP32 refinement products, or stop.
+// Status of a finished run: a trace-mode run whose result misses the
+// occupation by more than trace_tol has failed (a wrong final trace marks a
+// failed SP2 run, Methods, SP2 section); replay runs check it at the end of
+// the replayed branches.
+__device__ __forceinline__ int occupation_status(const Ctl &c, int status, double trace) {
+    if (status == GSP2_OK && c.mode == GSP2_ALPHA_TRACE && !(fabs(trace - c.n_occ) <= c.trace_tol))
+        return GSP2_E_WRONG_TRACE;
+    return status;
+}
+
+// End of the main phase: hand over to the refinement products, or stop.
 // Refinement alternates X^2 and 2X - X^2 whatever the trace: one pair maps
 // an eigenvalue l to 2 l^2 - l^4, whose stable fixed points are 0 and 1
 // (split at (sqrt(5) - 1) / 2), so every pair drives each eigenvalue to the
 // nearer of the two, quadratically.  The trace rule would keep picking the
 // branch that moves the trace towards n_occ; once the occupation is settled
 // that doubles the distance of eigenvalues near 0 (or near 1) at each product.
-__device__ void finish_main(Ctl &c, int result_buf, int result_t, int status, bool refinable) {
+// `trace` is Tr of the iterate the main phase ends on.
+__device__ void finish_main(Ctl &c, int result_buf, int result_t, int status, bool refinable, double trace) {
     c.n_main = c.n_products;
     if (refinable && c.refine > 0) {
         c.phase = 1;
@@ -386,7 +404,7 @@ __device__ void finish_main(Ctl &c, int result_buf, int result_t, int status, bo
     c.done = 1;
     c.result_buf = result_buf;
     c.result_t = result_t;
-    c.status = status;
+    c.status = occupation_status(c, status, trace);
 }
 
 // One product's decision from Tr[X_t^2] (ty) and Tr[X_{t+1}] (tx): the
@@ -409,7 +427,7 @@ __device__ void decide(Ctl &c, double ty, double tx, RunState *st, bool writer) 
     if (c.phase == 0 && c.mode == GSP2_ALPHA_TRACE && c.stop_rule && t >= 2 && fabs(e) >= fabs(c.e2) &&
         fabs(c.e2) < c.stop_floor) {
         c.idem = e;                             // X_t is the result; X_t^2 is discarded
-        finish_main(c, c.cur, t, GSP2_OK, true);
+        finish_main(c, c.cur, t, GSP2_OK, true, c.trX);
         return;
     }
     if (writer) {
@@ -428,19 +446,19 @@ __device__ void decide(Ctl &c, double ty, double tx, RunState *st, bool writer) 
             c.done = 1;
             c.result_buf = c.cur;
             c.result_t = t + 1;
-            c.status = c.main_status;
+            c.status = occupation_status(c, c.main_status, tx);
             return;
         }
         c.alpha = -c.alpha;
         return;
     }
     if (c.n_products >= c.n_steps) {
-        int status;
-        if (c.mode == GSP2_ALPHA_REPLAY)
-            status = fabs(tx - c.n_occ) <= c.trace_tol ? GSP2_OK : GSP2_E_WRONG_TRACE;
-        else
-            status = c.stop_rule ? GSP2_E_NOT_CONVERGED : GSP2_OK;
-        finish_main(c, c.cur, t + 1, status, true);
+        // trace mode: the stop rule did not fire within the budget (or was
+        // switched off), so the run has not shown convergence
+        const int status = c.mode == GSP2_ALPHA_REPLAY
+                               ? (fabs(tx - c.n_occ) <= c.trace_tol ? GSP2_OK : GSP2_E_WRONG_TRACE)
+                               : GSP2_E_NOT_CONVERGED;
+        finish_main(c, c.cur, t + 1, status, true, tx);
         return;
     }
     c.alpha = (c.mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[t + 1] : (tx <= c.n_occ ? 1 : -1);
@@ -464,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_run_start(const double *__restrict__
         if (c.n_steps <= 0) {
             const int status = (c.mode == GSP2_ALPHA_REPLAY && fabs(a - c.n_occ) > c.trace_tol)
                                    ? GSP2_E_WRONG_TRACE : GSP2_OK;
-            finish_main(c, 0, 0, status, true);
+            finish_main(c, 0, 0, status, true, a);
         } else {
             c.alpha = (c.mode == GSP2_ALPHA_REPLAY) ? (int)st->alpha_seq[0] : (a <= c.n_occ ? 1 : -1);
         }
@@ -739,6 +757,162 @@ __global__ __launch_bounds__(kBlock, 2) __attribute__((amdgpu_waves_per_eu(1, 2)
     if (st->done || st->phase != phase) return;
     sp2_tile<Op, kSplit>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, diag_partials,
                          lds, lo0, lo1);
+}
+
+// ---------------------------------------------------------------------------
+// a6 in FP64 (the paper's dgemm arithmetic): one SP2 product with FP64
+// operands, accumulation, master iterate and update, on
+// v_mfma_f64_16x16x4_f64.
+//
+// The tile scheme is the FP32 kernel's: 128 x 128 tiles of the upper
+// triangle, 4 waves in a 2 x 2 grid of 64 x 64 sub-tiles, operands staged
+// through two LDS buffers in K chunks of 128 bytes per row (16 doubles), the
+// update fused into the epilogue and written at (I,J) and mirrored at (J,I).
+// A wave's sub-tile is 4 x 4 blocks of 16 x 16 MFMA output (four doubles per
+// lane each).  MFMA step q of a chunk gives lane group g = lane / 16 the
+// column 4 g + q of its row, for A and B alike, so each lane reads its four
+// columns of a chunk as 32 contiguous bytes of LDS.  FP64 MFMAs are slow
+// enough that one chunk's matrix work covers the next chunk's loads, so one
+// register set suffices.
+// ---------------------------------------------------------------------------
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd, int cur, double alpha,
+                                           double *__restrict__ buf0, double *__restrict__ buf1,
+                                           double *__restrict__ diag_partials, uint4 *__restrict__ lds_base) {
+    auto lds = [&](int b, int ab) { return lds_base + (b * 2 + ab) * kTile * kLdsRow; };
+    const double *__restrict__ X = (cur ? buf1 : buf0) + pd.x_off;
+    double *__restrict__ Xn = (cur ? buf0 : buf1) + pd.x_off;
+    const int ld = pd.s_pad;
+    const int I0 = td.ti * kTile, J0 = td.tj * kTile;
+    const bool diag = td.ti == td.tj;
+    const int tid = threadIdx.x;
+    // global -> LDS: 8 threads per 128-byte row segment, 32 rows per pass
+    const int lr = tid >> 3, lw = tid & 7;
+    const char *Ag = reinterpret_cast<const char *>(X + (int64_t)(I0 + lr) * ld) + lw * 16;
+    const char *Bg = reinterpret_cast<const char *>(X + (int64_t)(J0 + lr) * ld) + lw * 16;
+    const int64_t pass_bytes = (int64_t)32 * ld * sizeof(double);
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int l16 = lane & 15, g = lane >> 4;
+
+    v4d acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+
+    // columns from s on are zero padding: the K loop stops at the first
+    // chunk that covers s (the skipped terms are exact zeros)
+    constexpr int kK64 = 16;
+    const int nk = (pd.s + kK64 - 1) / kK64;
+    uint4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
+#define GSP2_LD64(c)                                                                               \
+    do {                                                                                           \
+        const int64_t kb_ = (int64_t)(c) * 128;                                                    \
+        pa0 = *reinterpret_cast<const uint4 *>(Ag + kb_);                                          \
+        pa1 = *reinterpret_cast<const uint4 *>(Ag + pass_bytes + kb_);                             \
+        pa2 = *reinterpret_cast<const uint4 *>(Ag + 2 * pass_bytes + kb_);                         \
+        pa3 = *reinterpret_cast<const uint4 *>(Ag + 3 * pass_bytes + kb_);                         \
+        pb0 = *reinterpret_cast<const uint4 *>(Bg + kb_);                                          \
+        pb1 = *reinterpret_cast<const uint4 *>(Bg + pass_bytes + kb_);                             \
+        pb2 = *reinterpret_cast<const uint4 *>(Bg + 2 * pass_bytes + kb_);                         \
+        pb3 = *reinterpret_cast<const uint4 *>(Bg + 3 * pass_bytes + kb_);                         \
+    } while (0)
+#define GSP2_ST64(b)                                                                               \
+    do {                                                                                           \
+        uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;                                                \
+        uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                                \
+        As_[0] = pa0; As_[32 * kLdsRow] = pa1; As_[64 * kLdsRow] = pa2; As_[96 * kLdsRow] = pa3;   \
+        Bs_[0] = pb0; Bs_[32 * kLdsRow] = pb1; Bs_[64 * kLdsRow] = pb2; Bs_[96 * kLdsRow] = pb3;   \
+    } while (0)
+    GSP2_LD64(0);
+    GSP2_ST64(0);
+    __syncthreads();
+    for (int kc = 0; kc < nk; ++kc) {
+        const int b = kc & 1;
+        if (kc + 1 < nk) GSP2_LD64(kc + 1);
+        const uint4 *Asb = lds(b, 0);
+        const uint4 *Bsb = lds(b, 1);
+        double fa[4][4], fb[4][4];              // [block][MFMA step]
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const uint4 *ra = Asb + (wr * 64 + m * 16 + l16) * kLdsRow + 2 * g;
+            const uint4 *rb = Bsb + (wc * 64 + m * 16 + l16) * kLdsRow + 2 * g;
+            const double2 a0 = __builtin_bit_cast(double2, ra[0]), a1 = __builtin_bit_cast(double2, ra[1]);
+            const double2 b0 = __builtin_bit_cast(double2, rb[0]), b1 = __builtin_bit_cast(double2, rb[1]);
+            fa[m][0] = a0.x; fa[m][1] = a0.y; fa[m][2] = a1.x; fa[m][3] = a1.y;
+            fb[m][0] = b0.x; fb[m][1] = b0.y; fb[m][2] = b1.x; fb[m][3] = b1.y;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int nn = 0; nn < 4; ++nn)
+                    acc[m][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[m][q], fb[nn][q], acc[m][nn], 0, 0, 0);
+        if (kc + 1 < nk) GSP2_ST64(b ^ 1);
+        __syncthreads();
+    }
+#undef GSP2_LD64
+#undef GSP2_ST64
+
+    // Epilogue.  Element v of a 16 x 16 block's accumulator in lane (l16, g)
+    // is row 4 g + v, column l16.  X_old (for X' = 2X - Y) is read at the
+    // mirrored position, four consecutive doubles of one row of X.
+    double tY = 0.0, tX = 0.0;
+    const bool upd = alpha > 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int nn = 0; nn < 4; ++nn) {
+            const int cg = J0 + wc * 64 + nn * 16 + l16;
+            const int rg0 = I0 + wr * 64 + m * 16 + 4 * g;
+            double xo[4] = {0.0, 0.0, 0.0, 0.0};
+            if (upd) {
+                const double2 u0 = *reinterpret_cast<const double2 *>(X + (int64_t)cg * ld + rg0);
+                const double2 u1 = *reinterpret_cast<const double2 *>(X + (int64_t)cg * ld + rg0 + 2);
+                xo[0] = u0.x; xo[1] = u0.y; xo[2] = u1.x; xo[3] = u1.y;
+            }
+            double xn[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double y = acc[m][nn][v];
+                const double val = upd ? (2.0 * xo[v] - y) : y;
+                xn[v] = val;
+                Xn[(int64_t)(rg0 + v) * ld + cg] = val;
+                if (diag && rg0 + v == cg && cg < pd.c) {
+                    tY += y;
+                    tX += val;
+                }
+            }
+            if (!diag) {
+                *reinterpret_cast<double2 *>(Xn + (int64_t)cg * ld + rg0) = make_double2(xn[0], xn[1]);
+                *reinterpret_cast<double2 *>(Xn + (int64_t)cg * ld + rg0 + 2) = make_double2(xn[2], xn[3]);
+            }
+        }
+    }
+    if (diag) {
+        block_sum2(tY, tX);
+        if (tid == 0) {
+            diag_partials[2 * td.diag_slot + 0] = tY;
+            diag_partials[2 * td.diag_slot + 1] = tX;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sp2_step64(const TileDesc *__restrict__ tiles,
+                                                       const PartDesc *__restrict__ parts,
+                                                       double *__restrict__ buf0, double *__restrict__ buf1,
+                                                       const RunState *__restrict__ st_all,
+                                                       double *__restrict__ diag_partials, int phase) {
+    __shared__ uint4 lds[kLdsWords];
+    const TileDesc td = tiles[blockIdx.x];
+    if (td.part < 0) return;
+    const PartDesc pd = parts[td.part];
+    const RunState *st = st_all + pd.sys;
+    if (st->done || st->phase != phase) return;
+    sp2_tile64(td, pd, st->cur, static_cast<double>(st->alpha), buf0, buf1, diag_partials, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1331,25 +1505,57 @@ __global__ __launch_bounds__(kBlock) void k_persist_check(const PersistCtl *__re
 // ---------------------------------------------------------------------------
 // a8: scatter.  One wave per column of P; the column's rows are the part's
 // vertices in ascending global order, read from the (symmetric) row of the
-// final iterate through the sorted-position map.
+// final iterate through the sorted-position map.  With `symmetrize`, a
+// stored entry (i, j) whose mirror (j, i) is stored too becomes the mean of
+// the two (both computed from the final iterates, so the pair gets the same
+// value); an entry whose mirror the pattern does not hold is kept.
 // ---------------------------------------------------------------------------
+template <typename XT>
 __global__ __launch_bounds__(kBlock) void k_scatter(const PartDesc *__restrict__ parts,
                                                     const int32_t *__restrict__ perm_arena,
+                                                    const int32_t *__restrict__ idx_arena,
                                                     const int64_t *__restrict__ col_ptr,
                                                     const int32_t *__restrict__ col_part,
                                                     const int32_t *__restrict__ col_local, int32_t n,
-                                                    const float *__restrict__ buf0, const float *__restrict__ buf1,
-                                                    const RunState *__restrict__ st_all, float *__restrict__ P_val) {
+                                                    const XT *__restrict__ buf0, const XT *__restrict__ buf1,
+                                                    const RunState *__restrict__ st_all, XT *__restrict__ P_val,
+                                                    int symmetrize) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t j = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
     if (j >= n) return;
     const PartDesc pd = parts[col_part[j]];
     const RunState *st = st_all + pd.sys;
     if (st->status == GSP2_E_INVALID || st->status == GSP2_E_HIP) return;
-    const float *Xr = (st->result_buf ? buf1 : buf0) + pd.x_off + (int64_t)col_local[j] * pd.s_pad;
+    const XT *Xr = (st->result_buf ? buf1 : buf0) + pd.x_off + (int64_t)col_local[j] * pd.s_pad;
     const int32_t *perm = perm_arena + pd.perm_off;
-    float *out = P_val + col_ptr[j];
-    for (int t = lane; t < pd.s; t += kWave) out[t] = Xr[perm[t]];
+    XT *out = P_val + col_ptr[j];
+    if (!symmetrize) {
+        for (int t = lane; t < pd.s; t += kWave) out[t] = Xr[perm[t]];
+        return;
+    }
+    const int32_t *idx = idx_arena + pd.idx_off;
+    for (int t = lane; t < pd.s; t += kWave) {
+        const int loc = perm[t];
+        const XT v = Xr[loc];
+        const int32_t i = idx[loc];             // global row of this entry
+        // the mirror (j, i) sits in column i, held by the part where i is core
+        const PartDesc pq = parts[col_part[i]];
+        const int32_t *iq = idx_arena + pq.idx_off;
+        int r = find_sorted(iq, pq.c, (int32_t)j);
+        if (r < 0) {
+            r = find_sorted(iq + pq.c, pq.s - pq.c, (int32_t)j);
+            if (r >= 0) r += pq.c;
+        }
+        if (r < 0) {
+            out[t] = v;
+        } else {
+            const RunState *sq = st_all + pq.sys;
+            const XT *Xq = (sq->result_buf ? buf1 : buf0) + pq.x_off;
+            // P[j, i] = X_q[r][local i] = X_q[local i][r] (every iterate is symmetric)
+            const XT w = Xq[(int64_t)col_local[i] * pq.s_pad + r];
+            out[t] = static_cast<XT>(0.5) * (v + w);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1630,7 +1836,7 @@ void record(Recorder &rec, void (*f)(KArgs...), dim3 grid, dim3 block, Args &&..
 }
 
 template <typename T>
-hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, float *P_val,
+hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, void *P_val,
                          Recorder &rec, const RunEvents *ev) {
     const T *hv = static_cast<const T *>(H.val);
     const dim3 blk(kBlock);
@@ -1638,12 +1844,18 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     const dim3 sys(dp.n_sys);
     record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.row_bounds);
     record(rec, k_run_init, sys, blk, dp.row_bounds, dp.sys_rows, dp.sys_row_ptr, rp, dp.sys_params, dp.state);
-    const bool mixed = rp.precision != GSP2_PREC_FP32;
+    const bool f64 = rp.precision == GSP2_PREC_FP64;
+    const bool mixed = rp.precision == GSP2_PREC_FP16 || rp.precision == GSP2_PREC_BF16 ||
+                       rp.precision == GSP2_PREC_FP16X3;
     const bool split = rp.precision == GSP2_PREC_FP16X3;
     uint16_t *sh0 = mixed ? static_cast<uint16_t *>(dp.shadow[0]) : nullptr;
     uint16_t *lo0 = split ? static_cast<uint16_t *>(dp.shadow_lo[0]) : nullptr;
-    record(rec, k_gather_x0<T>, dim3(dp.n_chunks), blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx,
-           dp.buf[0], sh0, lo0, dp.state, dp.x0_partials);
+    if (f64)
+        record(rec, k_gather_x0<T, double>, dim3(dp.n_chunks), blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks,
+               dp.idx, dp.buf64[0], (uint16_t *)nullptr, (uint16_t *)nullptr, dp.state, dp.x0_partials);
+    else
+        record(rec, k_gather_x0<T, float>, dim3(dp.n_chunks), blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks,
+               dp.idx, dp.buf[0], sh0, lo0, dp.state, dp.x0_partials);
     record(rec, k_run_start, sys, blk, dp.x0_partials, dp.sys_chunk_ptr, dp.state);
     if (ev) rec.add_event(ev->setup_end);
     const dim3 grid(dp.n_tiles);
@@ -1692,13 +1904,16 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
         else if (rp.precision == GSP2_PREC_BF16)
             record(rec, k_sp2_wide<__bf16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, b16[0], b16[1],
                    dp.state, dp.diag_partials, (__bf16 *)nullptr, (__bf16 *)nullptr);
+        else if (f64)
+            record(rec, k_sp2_step64, grid, blk, dp.tiles, dp.parts, dp.buf64[0], dp.buf64[1], dp.state,
+                   dp.diag_partials, 0);
         else
             record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr,
                    (float *)nullptr, dp.state, dp.diag_partials, 0, (float *)nullptr, (float *)nullptr);
         if (ev) rec.add_event(ev->step[2 * it + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 0);
     }
-    if (!rp.persistent && rp.n_steps > 0 && !narrow16) {
+    if (!rp.persistent && rp.n_steps > 0 && mixed && !narrow16) {
         if (rp.precision == GSP2_PREC_FP16)
             record(rec, k_wide_fixup<_Float16, false>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
                    (const _Float16 *)nullptr, (const _Float16 *)nullptr, (const _Float16 *)nullptr,
@@ -1715,15 +1930,25 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     for (int r = 0; r < rp.refine; ++r) {
         const int slot = rp.n_steps + r;
         if (ev) rec.add_event(ev->step[2 * slot]);
-        record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr, (float *)nullptr,
-               dp.state, dp.diag_partials, 1, (float *)nullptr, (float *)nullptr);
+        if (f64)
+            record(rec, k_sp2_step64, grid, blk, dp.tiles, dp.parts, dp.buf64[0], dp.buf64[1], dp.state,
+                   dp.diag_partials, 1);
+        else
+            record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr,
+                   (float *)nullptr, dp.state, dp.diag_partials, 1, (float *)nullptr, (float *)nullptr);
         if (ev) rec.add_event(ev->step[2 * slot + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 1);
     }
     if (ev) rec.add_event(ev->sp2_end);
     const int wpb = kBlock / kWave;
-    record(rec, k_scatter, dim3((dp.n + wpb - 1) / wpb), blk, dp.parts, dp.perm, dp.col_ptr, dp.col_part,
-           dp.col_local, dp.n, dp.buf[0], dp.buf[1], dp.state, P_val);
+    if (f64)
+        record(rec, k_scatter<double>, dim3((dp.n + wpb - 1) / wpb), blk, dp.parts, dp.perm, dp.idx, dp.col_ptr,
+               dp.col_part, dp.col_local, dp.n, (const double *)dp.buf64[0], (const double *)dp.buf64[1], dp.state,
+               static_cast<double *>(P_val), rp.symmetrize);
+    else
+        record(rec, k_scatter<float>, dim3((dp.n + wpb - 1) / wpb), blk, dp.parts, dp.perm, dp.idx, dp.col_ptr,
+               dp.col_part, dp.col_local, dp.n, (const float *)dp.buf[0], (const float *)dp.buf[1], dp.state,
+               static_cast<float *>(P_val), rp.symmetrize);
     if (ev) rec.add_event(ev->end);
     return rec.err;
 }
@@ -1738,7 +1963,7 @@ hipError_t backward_typed(const DevicePlan &dp, const gsp2_csr &H, const RunPara
     record(rec, k_gershgorin<T>, dim3(dp.gersh_blocks), blk, H.row_ptr, H.col, hv, dp.n, dp.row_bounds);
     record(rec, k_run_init, dim3(dp.n_sys), blk, dp.row_bounds, dp.sys_rows, dp.sys_row_ptr, rp, dp.sys_params,
            dp.state);
-    record(rec, k_gather_x0<T>, chunks, blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx, bb.ckpt[0],
+    record(rec, k_gather_x0<T, float>, chunks, blk, H.row_ptr, H.col, hv, dp.parts, dp.chunks, dp.idx, bb.ckpt[0],
            (uint16_t *)nullptr, (uint16_t *)nullptr, dp.state, dp.x0_partials);
     const int k = bb.seg;
     const int nseg = n > 0 ? (n + k - 1) / k : 1;
@@ -1882,7 +2107,7 @@ hipError_t probe_mfma(int precision, int n_iter, int n_blocks, float *out, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, float *P_val,
+hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunParams &rp, void *P_val,
                           Recorder &rec, const RunEvents *ev) {
     if (H.dtype == GSP2_F64) return density_typed<double>(dp, H, rp, P_val, rec, ev);
     return density_typed<float>(dp, H, rp, P_val, rec, ev);

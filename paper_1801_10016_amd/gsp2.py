@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libgsp2.so")
 GSP2_OK, GSP2_E_INVALID, GSP2_E_HIP, GSP2_E_OOM, GSP2_E_NOT_CONVERGED, GSP2_E_WRONG_TRACE, GSP2_E_UNSUPPORTED = range(7)
 GSP2_F32, GSP2_F64 = 0, 1
 GSP2_ALPHA_TRACE, GSP2_ALPHA_REPLAY = 0, 1
-GSP2_PREC_FP32, GSP2_PREC_FP16, GSP2_PREC_BF16, GSP2_PREC_FP16X3 = 0, 1, 2, 3
+GSP2_PREC_FP32, GSP2_PREC_FP16, GSP2_PREC_BF16, GSP2_PREC_FP16X3, GSP2_PREC_FP64 = 0, 1, 2, 3, 4
 PRECISIONS = {"fp32": GSP2_PREC_FP32, "fp16": GSP2_PREC_FP16, "bf16": GSP2_PREC_BF16,
-              "fp16x3": GSP2_PREC_FP16X3}
+              "fp16x3": GSP2_PREC_FP16X3, "fp64": GSP2_PREC_FP64}
 GSP2_MAX_ITER = 100
 
 STATUS_NAMES = {0: "GSP2_OK", 1: "GSP2_E_INVALID", 2: "GSP2_E_HIP", 3: "GSP2_E_OOM",
@@ -54,7 +54,8 @@ class gsp2_run_options(C.Structure):
                 ("n_alpha", C.c_int32), ("stop_rule", C.c_int32), ("trace_tol", C.c_double),
                 ("timing", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
                 ("persistent", C.c_int32), ("n_occ_system", C.POINTER(C.c_double)),
-                ("alpha_seq_system", C.POINTER(C.c_int8)), ("n_alpha_system", C.POINTER(C.c_int32))]
+                ("alpha_seq_system", C.POINTER(C.c_int8)), ("n_alpha_system", C.POINTER(C.c_int32)),
+                ("symmetrize", C.c_int32), ("pad_", C.c_int32)]
 
 
 class gsp2_run_info(C.Structure):
@@ -345,7 +346,7 @@ def gsp2_plan_set_stream(plan: Plan, stream=None):
 
 
 def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5, timing=False,
-                     precision="fp32", refine=0, persistent=False, n_occ_system=None):
+                     precision="fp32", refine=0, persistent=False, n_occ_system=None, symmetrize=False):
     """Options struct and the arrays it points to (keep them alive for the
     call).  alpha_seq: one sequence, or (batched plans) a list of sequences,
     one per system; n_occ_system: occupations of a batched plan's systems."""
@@ -357,6 +358,7 @@ def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5,
     o.refine = int(refine)
     o.stop_rule = 1 if stop_rule else 0
     o.trace_tol = float(trace_tol)
+    o.symmetrize = 1 if symmetrize else 0
     keep = []
     if alpha_seq is not None:
         o.alpha_mode = GSP2_ALPHA_REPLAY
@@ -399,15 +401,17 @@ def run_info_dict(info: gsp2_run_info) -> dict:
 
 def gsp2_density(plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=None,
                  stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False,
-                 precision="fp32", refine=0, persistent=False):
-    """Enqueue one density matrix into P_val (torch float32 on the GPU, nnz_P
-    entries).  With want_info the call waits and returns the run's info dict
-    (a list of them, one per system, for a batched plan); with check a
-    failing status raises Gsp2Error.  For a batched plan n_occ lists every
-    system's occupation, and alpha_seq, if given, one sequence per system."""
+                 precision="fp32", refine=0, persistent=False, symmetrize=False):
+    """Enqueue one density matrix into P_val (torch on the GPU, nnz_P entries:
+    float64 for precision "fp64", float32 otherwise).  With want_info the
+    call waits and returns the run's info dict (a list of them, one per
+    system, for a batched plan); with check a failing status raises
+    Gsp2Error.  For a batched plan n_occ lists every system's occupation,
+    and alpha_seq, if given, one sequence per system."""
     import torch
-    if P_val.dtype != torch.float32 or not P_val.is_cuda or not P_val.is_contiguous():
-        raise ValueError("P_val must be a contiguous float32 GPU tensor")
+    want = torch.float64 if precision in ("fp64", GSP2_PREC_FP64) else torch.float32
+    if P_val.dtype != want or not P_val.is_cuda or not P_val.is_contiguous():
+        raise ValueError(f"P_val must be a contiguous {want} GPU tensor")
     if P_val.numel() < plan.nnz_P:
         raise ValueError(f"P_val holds {P_val.numel()} values, the plan needs {plan.nnz_P}")
     batched = plan.n_systems > 1
@@ -415,7 +419,7 @@ def gsp2_density(plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=
         raise ValueError("a batched plan takes one n_occ per system")
     c = H.as_c()
     o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine, persistent,
-                               n_occ_system=n_occ if batched else None)
+                               n_occ_system=n_occ if batched else None, symmetrize=symmetrize)
     info = (gsp2_run_info * plan.n_systems)() if want_info else None
     st = load().gsp2_density(plan.handle, C.byref(c), 0.0 if batched else float(n_occ), C.byref(o),
                              C.c_void_p(P_val.data_ptr()), info)

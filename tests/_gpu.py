@@ -19,7 +19,9 @@ def run_gsp2(H, P_prev, tau, part, n_parts, n_occ, h_dtype=None, p_dtype=None, t
         rec = g.gsp2_plan_tune(plan, Hd, n_occ, tune, n_products=4) if tune else None
         info, cs, ss = g.gsp2_plan_query(plan)
         col_ptr, row_idx = g.gsp2_plan_pattern(plan)
-        P_val = torch.full((info["nnz_P"],), float("nan"), dtype=torch.float32, device="cuda")
+        p64 = kw.get("precision") == "fp64"
+        P_val = torch.full((info["nnz_P"],), float("nan"), dtype=torch.float64 if p64 else torch.float32,
+                           device="cuda")
         run = g.gsp2_density(plan, Hd, n_occ, P_val, **kw)
         torch.cuda.synchronize()
         if rec is not None:

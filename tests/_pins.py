@@ -151,6 +151,11 @@ def check_monomer():
     mono = monomer_eigenvalues()
     assert np.allclose(w, np.repeat(mono, 8), atol=1e-10)
     assert np.allclose(mono[[0, 1, 5]], [-23.010, -15.473, 3.483], atol=1e-3)
+    # four occupied states per molecule: the highest is the flat -10 eV band,
+    # the lowest empty one the -5 eV H combination, so the gap is 5 eV
+    assert abs(oracle.spectral_gap(s.H, s.n_occ) - 5.0) <= 1e-10
+    # textbook: a diagonal matrix with two states occupied
+    assert oracle.spectral_gap(np.diag([7.0, 1.0, 3.0, 2.0]), 2) == 1.0
     # one part per molecule: the halo is empty and G-SP2 is exact
     Pprev = s.H  # block diagonal pattern, no intermolecular entries
     part = molecule_partition(s)
@@ -240,6 +245,50 @@ def check_gsp2_full_halo_is_dense(sys_):
     assert rel(g.dense(), P) <= 1e-12
 
 
+def check_symmetrize(sys_, tau=1e-2, n_parts=8):
+    """P assembled from core columns, symmetrised on its own pattern: every
+    stored entry whose mirror is stored becomes the mean of the two, others
+    stay (brute force over the stored entries); with complete halos the
+    pattern is full and the result is (P + P^T) / 2."""
+    P0, _ = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    part = uneven_spatial_partition(sys_, n_parts, seed=0)
+    g = oracle.gsp2(sys_.H, P0, tau, part, n_parts, sys_.n_occ)
+    A = g.csc().toarray()
+    stored = np.zeros(A.shape, dtype=bool)
+    for idx, core in zip(g.index, g.cores):
+        stored[np.ix_(idx, core)] = True
+    B = g.csc(symmetrize=True).toarray()
+    assert g.csc(symmetrize=True).nnz == g.csc().nnz
+    n_mirrored = 0
+    for i, j in zip(*np.nonzero(stored)):
+        if stored[j, i]:
+            assert B[i, j] == 0.5 * (A[i, j] + A[j, i])
+            n_mirrored += 1
+        else:
+            assert B[i, j] == A[i, j]
+    assert 0 < n_mirrored < stored.sum()          # both kinds occur at this tau
+    assert np.array_equal(g.dense(symmetrize=True), B)
+    full = oracle.gsp2(sys_.H, sp.csr_matrix(np.ones(A.shape)), 0.5, part, n_parts, sys_.n_occ)
+    F = full.dense()
+    assert np.allclose(full.dense(symmetrize=True), 0.5 * (F + F.T), rtol=0, atol=1e-15)
+
+
+def check_occupation_status(sys_, tau=1e-2, n_parts=4):
+    """A stop whose result misses N_occ by more than trace_tol is a failed
+    run; the same run with a bound above its miss succeeds.  Truncated halos
+    leave the G-SP2 trace a little off N_occ."""
+    P, _ = oracle.dense_sp2(sys_.H, sys_.n_occ)
+    part = uneven_spatial_partition(sys_, n_parts, seed=0)
+    ok = oracle.gsp2(sys_.H, P, tau, part, n_parts, sys_.n_occ).sp2
+    miss = abs(ok.traces[-1] - sys_.n_occ)
+    assert ok.converged and ok.status == "ok" and miss > 0.0
+    bad = oracle.gsp2(sys_.H, P, tau, part, n_parts, sys_.n_occ, trace_tol=0.5 * miss).sp2
+    assert not bad.converged and bad.status == "wrong_trace" and bad.n_products == ok.n_products
+    assert bad.alphas == ok.alphas
+    again = oracle.gsp2(sys_.H, P, tau, part, n_parts, sys_.n_occ, trace_tol=2.0 * miss).sp2
+    assert again.status == "ok"
+
+
 def check_gsp2_truncation(sys_, n_parts=8):
     P, _ = oracle.dense_sp2(sys_.H, sys_.n_occ)
     Ps = oracle.eig_projector(sys_.H, sys_.n_occ)
@@ -310,6 +359,8 @@ def battery():
     check_gsp2_truncation(water(64, 0))
     check_gsp2_blocks_share_sequence(water(64, 0))
     check_core_column_layout(water(64, 0))
+    check_symmetrize(water(32, 0))
+    check_occupation_status(water(32, 0))
     check_adjoint_finite_differences()
     check_adjoint_closed_form()
 

@@ -33,6 +33,10 @@ MUTANTS = {
     "adjoint_one_sided": ("adjoint.py", "S = G @ X + X @ G", "S = 2.0 * (G @ X)"),
     "adjoint_no_symmetrise": ("adjoint.py", "G = 0.5 * (G + G.T)", "G = G"),
     "adjoint_x0_sign": ("adjoint.py", "dH[np.ix_(idx, idx)] += -G / D", "dH[np.ix_(idx, idx)] += G / D"),
+    "symmetrize_mirror_ignored": ("gsp2.py", "v = np.where(found, 0.5 * (v + w), v)", "v = np.where(found, 0.5 * (v + v), v)"),
+    "gap_off_by_one": ("spectral.py", "return float(w[int(n_occ)] - w[int(n_occ) - 1])",
+                       "return float(w[int(n_occ) + 1] - w[int(n_occ)])"),
+    "occupation_unchecked": ("sp2.py", "            if abs(tr - n_occ) <= trace_tol:", "            if True:"),
     "adjoint_no_bound_terms": ("adjoint.py", "                dH[row, row] += g", "                dH[row, row] += 0.0"),
 }
 

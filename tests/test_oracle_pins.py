@@ -77,6 +77,14 @@ def test_gsp2_complete_halo_is_dense_sp2():
     pins.check_gsp2_full_halo_is_dense(pins.water(24, 2))
 
 
+def test_symmetrize_on_the_pattern():
+    pins.check_symmetrize(pins.water(32, 0))
+
+
+def test_occupation_check_of_a_stopped_run():
+    pins.check_occupation_status(pins.water(32, 0))
+
+
 def test_gsp2_truncation_error_is_order_tau():
     pins.check_gsp2_truncation(pins.water(64, 0))
 
