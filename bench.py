@@ -31,9 +31,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3
-PEAK_MFMA_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp16x3": 2500.0}   # dense, per operand format
-MFMA_PRODUCTS = {"fp32": 1, "fp16": 1, "bf16": 1, "fp16x3": 3}   # matrix-core products per SP2 product
-DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp16x3": "f16x3"}
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "fp16": 2500.0, "bf16": 2500.0, "fp16x3": 2500.0,
+                    "fp64": 78.6}                                  # dense, per operand format
+MFMA_PRODUCTS = {"fp32": 1, "fp16": 1, "bf16": 1, "fp16x3": 3, "fp64": 1}   # matrix-core products per SP2 product
+DTYPE = {"fp32": "f32", "fp16": "f16", "bf16": "bf16", "fp16x3": "f16x3", "fp64": "f64"}
 PEAK_HBM_GBS = 8000.0
 METRIC = "ms per density matrix P + batched-GEMM TFLOP/s (frac. of MFMA peak) at 10k atoms"
 
@@ -62,9 +63,12 @@ def parse():
     ap.add_argument("--save-state", help="write the thresholded graph and product count to this .npz")
     ap.add_argument("--load-state", help="reuse a graph and product count saved by --save-state "
                     "(skips the previous-P computation and the first, stop-finding run)")
-    ap.add_argument("--precision", choices=["fp32", "fp16", "bf16", "fp16x3"], default=None,
+    ap.add_argument("--precision", choices=["fp32", "fp16", "bf16", "fp16x3", "fp64"], default=None,
                     help="operand precision of the timed products (default: fp32, or fp16 for batch16)")
-    ap.add_argument("--compare-precisions", default="fp16,bf16,fp16x3",
+    ap.add_argument("--variant-tau", type=float, default=1e-3,
+                    help="also time the same P thresholded at this tau (sub-problems in the 400-1,600 range); 0: skip")
+    ap.add_argument("--variant-steps", type=int, default=5)
+    ap.add_argument("--compare-precisions", default="fp16,bf16,fp16x3,fp64",
                     help="after the FP32 timing, also time these operand precisions (empty: none)")
     ap.add_argument("--compare-steps", type=int, default=3)
     ap.add_argument("--no-library-compare", action="store_true",
@@ -84,14 +88,15 @@ def parse():
 
 
 def dense_bootstrap(g, torch, Hd, n, n_occ, stream):
-    """Regular SP2 on the whole H (one part, no halo) -> previous P as a device CSR."""
+    """Regular SP2 on the whole H (one part, no halo) with FP64 products, the
+    arithmetic of the paper's runs -> previous P as a device CSR (FP64)."""
     part = np.zeros(n, dtype=np.int32)
     with torch.cuda.stream(stream):
         with g.gsp2_plan_create(Hd, 0.0, part, 1, stream=stream) as plan:
             info, _, _ = g.gsp2_plan_query(plan)
             assert info["nnz_P"] == n * n
-            P = torch.empty(n * n, dtype=torch.float32, device="cuda")
-            run = g.gsp2_density(plan, Hd, n_occ, P)
+            P = torch.empty(n * n, dtype=torch.float64, device="cuda")
+            run = g.gsp2_density(plan, Hd, n_occ, P, precision="fp64")
             torch.cuda.synchronize()
     # with a single part every column holds all n rows in ascending order
     col_ptr = torch.arange(0, n * n + 1, n, dtype=torch.int64, device="cuda")
@@ -156,20 +161,6 @@ def library_products(torch, stream, sizes, gemm_flops, ours_ms, reps=3):
     return out
 
 
-def threshold_on_host(Pprev, tau):
-    """Graph of a device CSR thresholded at tau, as host CSR arrays (for --save-state)."""
-    import scipy.sparse as sp
-    ptr = Pprev.row_ptr.cpu().numpy()
-    col = Pprev.col.cpu().numpy()
-    n = Pprev.n
-    keep = np.abs(Pprev.val.double().cpu().numpy()) > tau
-    rows = np.repeat(np.arange(n), np.diff(ptr))
-    keep &= rows != col
-    A = sp.csr_matrix((np.ones(int(keep.sum()), dtype=np.int8), (rows[keep], col[keep])), shape=(n, n))
-    A.sort_indices()
-    return A.indptr.astype(np.int64), A.indices.astype(np.int32)
-
-
 def copy_probe(torch, gib):
     """A plain device-to-device copy of known size, for scaling HBM counters."""
     n = int(gib * 2**30) // 4
@@ -182,44 +173,57 @@ def copy_probe(torch, gib):
     return 0
 
 
-def cpu_baseline(system, part, n_parts, tau, n_products, sub_sizes, n_sample):
-    """Time the FP64 oracle's SP2 products on a few parts and scale by sum s^3."""
-    import oracle
-    from synth.locality import surrogate_prev_density
+def host_cores():
     try:
         from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") == "openblas"]
-                      or [os.cpu_count() or 1])
+        return max([p.get("num_threads", 1) for p in threadpool_info() if p.get("internal_api") == "openblas"]
+                   or [os.cpu_count() or 1])
     except Exception:
-        threads = os.cpu_count() or 1
-    Q = surrogate_prev_density(system)
-    adj = oracle.threshold_graph(Q, tau)
-    cores, halos = oracle.core_halo(adj, part, n_parts)
-    sizes = np.array([len(c) + len(h) for c, h in zip(cores, halos)])
-    order = np.argsort(sizes)
-    pick = [int(order[int(q * (n_parts - 1))]) for q in np.linspace(0.0, 1.0, n_sample)]
-    emin, emax = oracle.gershgorin_bounds(system.H)
-    X0 = []
-    for k in pick:
-        idx = oracle.subproblem_index(cores[k], halos[k])
-        X0.append(oracle.initial_guess(system.H[idx][:, idx].toarray(), emin, emax))
-    seq = [(-1) ** t for t in range(n_products)]
-    t0 = time.perf_counter()
-    oracle.sp2_blocks(X0, [len(cores[k]) for k in pick], system.n_occ, alpha_seq=seq, trace_tol=1e30)
-    dt = time.perf_counter() - t0
-    s3_sample = float(sum(sizes[k] ** 3 for k in pick))
-    s3_all = float(np.sum(np.asarray(sub_sizes, dtype=np.float64) ** 3))
-    ms = dt * 1e3 * s3_all / s3_sample
-    model = "unknown"
+        return os.cpu_count() or 1
+
+
+def cpu_model():
     try:
         with open("/proc/cpuinfo") as f:
-            model = next((line.split(":", 1)[1].strip() for line in f if line.startswith("model name")), model)
+            return next((line.split(":", 1)[1].strip() for line in f if line.startswith("model name")), "unknown")
     except OSError:
-        pass
-    return {"value": ms, "unit": "ms/P", "cores": int(threads), "kind": "oracle", "cpu_model": model,
-            "sample": (f"FP64 numpy/OpenBLAS SP2 products of {len(pick)} of {n_parts} parts "
-                       f"(s = {', '.join(str(int(sizes[k])) for k in pick)}), {n_products} products each, "
-                       f"{dt:.1f} s, scaled by sum_k s_k^3 of the timed workload")}
+        return "unknown"
+
+
+def cpu_baseline(system, index, cores, alphas, budget_flop=6e12, whole=False):
+    """Time the FP64 oracle's SP2 products (numpy/OpenBLAS) on parts of the
+    benched plan: sub-problems built by the oracle from H with the plan's own
+    index lists, the run's branch sequence replayed.  `whole`: every part;
+    otherwise parts spread over the size range, within about budget_flop of
+    work, and the time scaled by sum_k s_k^3 of the whole plan."""
+    import oracle
+    sizes = np.array([len(ix) for ix in index])
+    order = np.argsort(sizes, kind="stable")
+    if whole:
+        pick = [int(k) for k in order]
+    else:
+        pick, spent = [], 0.0
+        for q in np.linspace(0.0, 1.0, 9):
+            k = int(order[int(q * (len(order) - 1))])
+            cost = 2.0 * float(sizes[k]) ** 3 * len(alphas)
+            if k not in pick and (not pick or spent + cost <= budget_flop):
+                pick.append(k)
+                spent += cost
+    emin, emax = oracle.gershgorin_bounds(system.H)
+    X0 = [oracle.initial_guess(system.H[index[k]][:, index[k]].toarray(), emin, emax) for k in pick]
+    t0 = time.perf_counter()
+    oracle.sp2_blocks(X0, [int(cores[k]) for k in pick], system.n_occ, alpha_seq=list(alphas), trace_tol=1e30)
+    dt = time.perf_counter() - t0
+    s3_sample = float(sum(float(sizes[k]) ** 3 for k in pick))
+    s3_all = float(np.sum(sizes.astype(np.float64) ** 3))
+    ms = dt * 1e3 * s3_all / s3_sample
+    what = ("all" if whole else f"{len(pick)}") + f" of {len(index)} parts of the benched plan"
+    return {"value": round(ms, 1), "unit": "ms/P", "cores": int(host_cores()), "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": (f"FP64 numpy/OpenBLAS SP2 products of {what} (s = "
+                       f"{', '.join(str(int(sizes[k])) for k in pick[:9])}{', ...' if len(pick) > 9 else ''}), "
+                       f"{len(alphas)} products each, {dt:.1f} s" +
+                       ("" if whole else ", scaled by sum_k s_k^3 of the whole plan"))}
 
 
 def syrk_flops(sizes) -> float:
@@ -422,33 +426,83 @@ def bench_batch(args, g, torch):
     return 0
 
 
-def main():
-    args = parse()
-    batch = args.workload == "batch16"
-    args.precision = args.precision or ("fp16" if batch else "fp32")
-    args.refine = (2 if batch else 0) if args.refine is None else args.refine
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
-              "run with --gpus 1", file=sys.stderr)
-        return 2
-    import torch
+def graph_digest(g, plan, n):
+    """SHA-256 of the plan's graph (union of both orientations, canonical CSR),
+    hashed as the stored oracle expectations hash the oracle's graph."""
+    import hashlib
 
-    import paper_1801_10016_amd as g
+    import scipy.sparse as sp
+    adj_ptr, adj_col = g.gsp2_plan_graph(plan)
+    A = sp.csr_matrix((np.ones(len(adj_col), dtype=np.int8), adj_col, adj_ptr), shape=(n, n))
+    A = ((A + A.T) > 0).astype(np.int8).tocsr()
+    A.sort_indices()
+    h = hashlib.sha256()
+    h.update(np.asarray(A.indptr, dtype="<i8").tobytes())
+    h.update(np.asarray(A.indices, dtype="<i4").tobytes())
+    return h.hexdigest(), int(A.nnz)
+
+
+GOLDEN_STEM = os.path.join(ROOT, "tests", "golden", "gsp2_water3500_densep_tau1e-5")
+
+
+def stored_oracle(args, digest):
+    """The FP64 oracle's stored per-part sketches of this workload (written by
+    tests/golden/make_full_size_golden.py), when the benched graph is the one
+    they were taken on; else None."""
+    try:
+        gold = json.load(open(GOLDEN_STEM + ".json"))
+        arrays = dict(np.load(GOLDEN_STEM + ".npz"))
+    except (OSError, ValueError):
+        return None
+    sp_ = gold["spec"]
+    same = (sp_["n_mol"], sp_["seed"], sp_["n_parts"], sp_["core_lo"], sp_["core_hi"], sp_["tau"]) == \
+        (args.n_mol, args.seed, args.n_parts, args.core_lo, args.core_hi, args.tau)
+    return (gold, arrays) if same and gold["graph"]["sha256"] == digest else None
+
+
+def oracle_sketch_errors(stored, vals, col_ptr, part):
+    """Relative error of every part's core columns against the oracle's,
+    through the stored Gaussian sketches (synth.sketch): max and median."""
+    from synth import sketch
+    gold, arrays = stored
+    errs = []
+    for k, p in enumerate(gold["parts"]):
+        core = np.flatnonzero(part == k)
+        B = vals[col_ptr[core][None, :] + np.arange(p["s"])[:, None]].astype(np.float64)
+        S, R = sketch.probes(k, p["s"], p["c"])
+        want = arrays["part_sketch"][k]
+        errs.append(float(np.linalg.norm(S @ B @ R - want) / np.linalg.norm(want)))
+    return {"max": float(np.max(errs)), "median": float(np.median(errs)), "parts": len(errs),
+            "against": "FP64 oracle, per-part Gaussian sketches of the core columns, oracle's branch sequence"}
+
+
+def timed_runs(g, torch, plan, Hd, n_occ, P, steps, warmup, stream, **kw):
+    """`warmup` untimed and `steps` timed density matrices; each timed step is
+    bracketed by device synchronisations.  Returns per-step wall ms, per-step
+    event timings and the last run's status."""
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            g.gsp2_density(plan, Hd, n_occ, P, want_info=False, check=False, **kw)
+        torch.cuda.synchronize()
+        wall, timings = [], []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            g.gsp2_density(plan, Hd, n_occ, P, want_info=False, check=False, **kw)
+            if kw.get("timing"):
+                timings.append(g.gsp2_run_timing(plan))
+            torch.cuda.synchronize()
+            wall.append((time.perf_counter() - t0) * 1e3)
+        last = g.gsp2_run_status(plan)
+    return wall, timings, last
+
+
+def bench_water(args, g, torch):
+    """The headline workload: 3,500 water molecules, 128 uneven parts, graph
+    of the regular-SP2 previous P at tau, FP32 products; then the same P
+    with the other operand precisions, and the shape-matched tau variant."""
     from synth.locality import surrogate_prev_density
     from synth.partition import uneven_spatial_partition
     from synth.water import make_water
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        return 2
-    g.load()
-    torch.cuda.set_device(0)
-    if args.copy_probe_gib > 0:
-        return copy_probe(torch, args.copy_probe_gib)
-    if args.workload == "batch16":
-        return bench_batch(args, g, torch)
-    if args.workload == "backward1000":
-        return bench_backward(args, g, torch)
     stream = torch.cuda.Stream()
     t = time.perf_counter()
     system = make_water(args.n_mol, seed=args.seed)
@@ -469,7 +523,7 @@ def main():
         boot_desc = str(saved["previous_P"])
     elif args.graph == "dense-sp2":
         Pprev, boot = dense_bootstrap(g, torch, Hd, n, n_occ, stream)
-        boot_desc = f"regular SP2 of H on the GPU ({boot['n_products']} products)"
+        boot_desc = f"regular SP2 of H on the GPU, FP64 products ({boot['n_products']} products)"
         tau = args.tau
     else:
         Pprev = g.csr_to_device(surrogate_prev_density(system))
@@ -482,33 +536,30 @@ def main():
     with torch.cuda.stream(stream):
         plan = g.gsp2_plan_create(Pprev, tau, part, args.n_parts, stream=stream)
     plan_s = time.perf_counter() - t
+    digest, nnz_sym = graph_digest(g, plan, n)
     if args.save_state:
-        adj_ptr, adj_col = threshold_on_host(Pprev, args.tau)
+        adj_ptr, adj_col = g.gsp2_plan_graph(plan)
         np.savez(args.save_state, adj_ptr=adj_ptr, adj_col=adj_col, previous_P=boot_desc)
-    del Pprev
-    torch.cuda.empty_cache()
     info, core_sizes, sub_sizes = g.gsp2_plan_query(plan)
     log(f"plan: s in [{info['min_s']}, {info['max_s']}], sum s^3 = {info['sum_s3']:.3e}, "
-        f"tiles/product = {info['n_tiles']}, workspace = {info['workspace_bytes'] / 2**30:.2f} GiB, {plan_s:.1f} s")
+        f"tiles/product = {info['n_tiles']}, workspace = {info['workspace_bytes'] / 2**30:.2f} GiB, {plan_s:.1f} s, "
+        f"graph {nnz_sym} entries sha256 {digest[:16]}")
+    stored = stored_oracle(args, digest) if saved is None else None
+    log("stored oracle sketches: " + ("used (the benched graph is the oracle's)" if stored else "not applicable"))
     P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
-
-    # 16-bit products: the tile autotuner picks the tile edge on this plan
-    # first (outside every timed region)
-    tuning = None
-    if args.precision != "fp32" and not args.no_tune:
-        with torch.cuda.stream(stream):
-            tuning = g.gsp2_plan_tune(plan, Hd, n_occ, args.precision, n_products=6)
-        log(f"tile autotuner: {tuning}")
+    col_ptr, _ = g.gsp2_plan_pattern(plan)
 
     # the first run finds where the stop rule fires; later runs form exactly
     # that many products (the same stop fires at the same product), so no
     # empty launches follow the stop
     if saved is not None:
         n_prod = int(saved["n_products"])
+        alphas = None
     else:
         with torch.cuda.stream(stream):
             first = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=args.max_iter, precision=args.precision)
         n_prod = first["n_products"]
+        alphas = first["alpha"]
         log(f"first run: status {first['status_name']}, {n_prod} products, Tr P = {first['trace']:.6f}")
     if args.save_state:
         with np.load(args.save_state) as z:
@@ -516,104 +567,108 @@ def main():
         np.savez(args.save_state, n_products=n_prod, **d)
         log(f"state saved to {args.save_state}")
     timed = not args.no_kernel_timing
-    with torch.cuda.stream(stream):
-        for i in range(args.warmup):
-            w = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=timed, precision=args.precision)
-            assert w["status"] == 0 and w["n_products"] == n_prod, w
-            log(f"warmup {i + 1}/{args.warmup}" +
-                (f": {g.gsp2_run_timing(plan)['total_ms']:.1f} ms" if timed else ""))
-
-        totals, product_ms, setup, sp2, scatter = [], [], [], [], []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for i in range(args.steps):
-            g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=n_prod, timing=timed, want_info=False,
-                           precision=args.precision)
-            if timed:
-                tm = g.gsp2_run_timing(plan)
-                totals.append(tm["total_ms"]); product_ms += tm["product_ms"]
-                setup.append(tm["setup_ms"]); sp2.append(tm["sp2_ms"]); scatter.append(tm["scatter_ms"])
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        last = g.gsp2_run_status(plan)
-    log(f"timed {args.steps} steps: {wall * 1e3 / args.steps:.1f} ms per P")
-    assert last["status"] == 0, last
-    if not timed:
-        product_ms, setup, sp2, scatter, totals = [float("nan")], [float("nan")], [wall * 1e3 / args.steps], \
-            [float("nan")], [float("nan")]
+    kw = dict(max_iter=n_prod, precision=args.precision, timing=timed)
+    wall, timings, last = timed_runs(g, torch, plan, Hd, n_occ, P_val, args.steps, args.warmup, stream, **kw)
+    assert last["status"] == 0 and last["n_products"] == n_prod, last
+    ms_median = statistics.median(wall)
+    log(f"timed {args.steps} steps: median {ms_median:.1f} ms per P (mean {statistics.fmean(wall):.1f})")
+    if timed:
+        product_ms = [x for tm in timings for x in tm["product_ms"]]
+        setup = [tm["setup_ms"] for tm in timings]
+        sp2 = [tm["sp2_ms"] for tm in timings]
+        scatter = [tm["scatter_ms"] for tm in timings]
+        totals = [tm["total_ms"] for tm in timings]
+    else:
+        product_ms, setup, scatter, totals = [float("nan")], [float("nan")], [float("nan")], [float("nan")]
+        sp2 = wall
+    fp32_err = None
+    if stored is not None:
+        with torch.cuda.stream(stream):
+            g.gsp2_density(plan, Hd, n_occ, P_val, alpha_seq=stored[0]["alphas"], trace_tol=1e9)
+        fp32_err = oracle_sketch_errors(stored, P_val.cpu().numpy(), col_ptr, part)
+        log(f"fp32 vs oracle: max {fp32_err['max']:.2e}")
 
     s = np.asarray(sub_sizes, dtype=np.float64)
-    syrk_flops = float(np.sum(s * s * (s + 1.0)))        # distinct entries s(s+1)/2, 2s flops each
-    product_kernel = ("k_sp2_wide" if args.precision != "fp32" and (tuning or {}).get("tile16", 256) == 256
-                      else "k_sp2_step")
-    # the matrix-core rate measured on this GPU at its clock, beside the published peak
+    sym_flops = float(np.sum(s * s * (s + 1.0)))          # distinct entries s(s+1)/2, 2s flops each
+    product_kernel = {"fp32": "k_sp2_step", "fp64": "k_sp2_step64"}.get(args.precision, "k_sp2_wide")
     with torch.cuda.stream(stream):
         probe = {p: g.gsp2_probe_mfma(p, stream=stream)
-                 for p in {args.precision, *[q for q in args.compare_precisions.split(",") if q]}}
+                 for p in {"fp32", args.precision, *[q for q in args.compare_precisions.split(",") if q]}
+                 if p != "fp64"}
     log("measured MFMA rate: " + ", ".join(f"{p} {v:.1f} TFLOP/s" for p, v in sorted(probe.items())))
-    gemm_flops = float(np.sum(2.0 * s ** 3))
     avg_prod_ms = statistics.fmean(product_ms)
-    achieved = MFMA_PRODUCTS[args.precision] * syrk_flops / (avg_prod_ms * 1e-3) / 1e12
+    achieved = MFMA_PRODUCTS[args.precision] * sym_flops / (avg_prod_ms * 1e-3) / 1e12
     peak = PEAK_MFMA_TFLOPS[args.precision]
-    ms_per_step = wall * 1e3 / args.steps
     sp2_med = statistics.median(sp2)
 
-    # the same density matrix with 16-bit product operands, on the same GPU
+    # the same density matrix with other product precisions, on the same GPU
     compare = {}
-    P_ref = P_val.double()
     for prec in [p for p in args.compare_precisions.split(",") if p]:
-        P_mp = torch.empty_like(P_val)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        P_mp = torch.empty(info["nnz_P"], dtype=dt, device="cuda")
         tune_rec = None
         with torch.cuda.stream(stream):
-            if not args.no_tune:
+            if not args.no_tune and prec in ("fp16", "bf16", "fp16x3"):
                 tune_rec = g.gsp2_plan_tune(plan, Hd, n_occ, prec, n_products=6)
-            r0 = g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=args.max_iter, precision=prec)
-            n_mp = r0["n_products"]
-            g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=n_mp, precision=prec)      # builds the graph
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(args.compare_steps):
-                g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=n_mp, precision=prec, want_info=False)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / args.compare_steps
-            g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=n_mp, precision=prec, timing=True)
-            tm = g.gsp2_run_timing(plan)
-        diff = float(torch.linalg.vector_norm(P_mp.double() - P_ref) / torch.linalg.vector_norm(P_ref))
-        avg = statistics.fmean(tm["product_ms"])
-        hw = MFMA_PRODUCTS[prec] * syrk_flops
-        compare[prec] = {"ms_per_P": round(ms, 3), "n_products": n_mp,
-                         "product_kernel_ms": round(avg, 4),
-                         "tflops": round(syrk_flops / (avg * 1e-3) / 1e12, 2),
-                         "mfma_products_per_product": MFMA_PRODUCTS[prec],
-                         "frac_of_peak": round(hw / (avg * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[prec], 4),
-                         "frac_of_measured_peak": round(hw / (avg * 1e-3) / 1e12 / probe[prec], 4),
-                         "rel_diff_vs_fp32_P": diff, "trace_minus_nocc": r0["trace"] - n_occ,
-                         "tile16_tuning": tune_rec}
-        log(f"{prec}: {ms:.1f} ms/P, {n_mp} products, |P - P_fp32|/|P_fp32| = {diff:.2e}")
+            r0 = g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=args.max_iter, precision=prec, check=False)
+        n_mp = r0["n_products"]
+        w, tms, last_mp = timed_runs(g, torch, plan, Hd, n_occ, P_mp, args.compare_steps, 1, stream,
+                                     max_iter=n_mp, precision=prec, timing=True)
+        avg = statistics.fmean([x for tm in tms for x in tm["product_ms"]])
+        hw = MFMA_PRODUCTS[prec] * sym_flops
+        rec = {"ms_per_P": round(statistics.median(w), 3), "n_products": n_mp, "status": r0["status_name"],
+               "trace_minus_nocc": r0["trace"] - n_occ, "product_kernel_ms": round(avg, 4),
+               "tflops": round(sym_flops / (avg * 1e-3) / 1e12, 2), "mfma_products_per_product": MFMA_PRODUCTS[prec],
+               "frac_of_peak": round(hw / (avg * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[prec], 4),
+               "tile16_tuning": tune_rec}
+        if prec in probe:
+            rec["frac_of_measured_peak"] = round(hw / (avg * 1e-3) / 1e12 / probe[prec], 4)
+        if stored is not None:
+            with torch.cuda.stream(stream):
+                for refine in ((0, 2) if prec in ("fp16", "bf16") else (0,)):
+                    g.gsp2_density(plan, Hd, n_occ, P_mp, alpha_seq=stored[0]["alphas"], trace_tol=1e9,
+                                   precision=prec, refine=refine)
+                    rec[f"error_vs_oracle_refine{refine}"] = oracle_sketch_errors(
+                        stored, P_mp.cpu().numpy(), col_ptr, part)["max"]
+        compare[prec] = rec
+        log(f"{prec}: {rec['ms_per_P']:.1f} ms/P, {n_mp} products, status {r0['status_name']}, "
+            f"Tr P - N_occ = {rec['trace_minus_nocc']:.3e}" +
+            (f", error vs oracle {rec['error_vs_oracle_refine0']:.2e}" if stored is not None else ""))
         del P_mp
         torch.cuda.empty_cache()
 
     library = None
     if not args.no_library_compare:
         ours = {args.precision: avg_prod_ms, **{p: c["product_kernel_ms"] for p, c in compare.items()}}
-        library = library_products(torch, stream, [int(v) for v in sub_sizes], gemm_flops, ours)
+        library = library_products(torch, stream, [int(v) for v in sub_sizes], float(np.sum(2.0 * s ** 3)), ours)
         log("library products: " + ", ".join(f"{p} {v['ms_per_product']:.2f} ms" for p, v in library.items()
                                              if isinstance(v, dict)))
 
     cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline: timing the FP64 oracle on a sample of parts")
-        cpu = cpu_baseline(system, part, args.n_parts, args.tau, n_prod, sub_sizes, args.cpu_sample_parts)
-        log(f"cpu baseline: {cpu['value']:.0f} ms/P on {cpu['cores']} threads")
+    if not args.no_cpu_baseline and alphas is not None:
+        log("cpu baseline: timing the FP64 oracle on parts of the benched plan")
+        index = [g.gsp2_plan_part_index(plan, k) for k in range(args.n_parts)]
+        cpu = cpu_baseline(system, index, core_sizes, alphas)
+        log(f"cpu baseline: {cpu['value']:.0f} ms/P on {cpu['cores']} threads ({cpu['sample']})")
+    plan.close()
+    del P_val
+    torch.cuda.empty_cache()
+
+    variant = None
+    if args.variant_tau > 0 and saved is None:
+        variant = shape_matched(args, g, torch, system, part, Hd, Pprev, stream, probe)
+    del Pprev
+    torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
-        "value": round(ms_per_step, 3),
+        "value": round(ms_median, 3),
         "unit": "ms/P",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(ms_median, 3),
+        "ms_per_step_mean": round(statistics.fmean(wall), 3),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -623,23 +678,28 @@ def main():
             "workload": (f"G-SP2 density matrix of {args.n_mol} synthetic water molecules ({n} orbitals), "
                          f"{args.n_parts} uneven spatial parts, graph of the previous P at tau={args.tau:g}"),
             "n_mol": args.n_mol, "n_orbitals": n, "n_occ": n_occ, "n_parts": args.n_parts,
-            "tau": args.tau, "previous_P": boot_desc, "s_min": info["min_s"], "s_max": info["max_s"],
-            "s_mean": round(float(s.mean()), 1), "sum_s3": info["sum_s3"], "n_products": n_prod,
-            "tiles_per_product": info["n_tiles"],
+            "tau": args.tau, "previous_P": boot_desc, "graph_entries": nnz_sym, "graph_sha256": digest,
+            "s_min": info["min_s"], "s_max": info["max_s"], "s_mean": round(float(s.mean()), 1),
+            "sum_s3": info["sum_s3"], "n_products": n_prod, "tiles_per_product": info["n_tiles"],
             "precision": f"{args.precision.upper()} MFMA operands, FP32 accumulation and iterate, FP64 traces",
         },
-        "batched_gemm_tflops": round(n_prod * gemm_flops / (sp2_med * 1e-3) / 1e12, 2),
-        "batched_gemm_tflops_convention": "n_products * sum_k 2 s_k^3 / SP2-phase time (GEMM convention)",
+        "error_vs_oracle": fp32_err,
+        "gemm_convention_rate": {
+            "value": round(n_prod * float(np.sum(2.0 * s ** 3)) / (sp2_med * 1e-3) / 1e12, 2),
+            "convention": ("n_products * sum_k 2 s_k^3 / SP2-phase time, in 1e12 per second: the flop count of "
+                           "full dense GEMMs, twice what the symmetric product performs; not a rate of executed "
+                           "flops (roofline.achieved is)")},
         "roofline": {
             "bound": "mfma", "kernel": product_kernel,
             "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4),
-            "measured_peak": round(probe[args.precision], 1),
-            "frac_of_measured_peak": round(achieved / probe[args.precision], 4), "traffic": counter_traffic(
+            "measured_peak": round(probe[args.precision], 1) if args.precision in probe else None,
+            "frac_of_measured_peak": round(achieved / probe[args.precision], 4) if args.precision in probe else None,
+            "traffic": counter_traffic(
                 args.precision, {"n_mol": args.n_mol, "n_parts": args.n_parts, "tau": args.tau,
                                  "sum_s3": info["sum_s3"]}, product_kernel),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
-            "flops_per_launch": MFMA_PRODUCTS[args.precision] * syrk_flops, "avg_launch_ms": round(avg_prod_ms, 4),
+            "flops_per_launch": MFMA_PRODUCTS[args.precision] * sym_flops, "avg_launch_ms": round(avg_prod_ms, 4),
             "flops_convention": "symmetric product: sum_k s_k^2 (s_k + 1) per launch (one launch = one product)",
         },
         "phase_ms": {"setup": round(statistics.median(setup), 3), "sp2": round(sp2_med, 3),
@@ -653,7 +713,7 @@ def main():
                                      "update and trace partials) against the rest of one P: Gershgorin, gather, "
                                      "branch decisions, scatter and launch gaps"},
         "precision_compare": compare,
-        "tile16_tuning": tuning,
+        "shape_matched": variant,
         "plan_ms": round(plan_s * 1e3, 1),
         "plan_info": {k: info[k] for k in ("nnz_graph", "nnz_P", "sum_s", "workspace_bytes")},
         "previous_P_s": round(boot_s, 2),
@@ -661,8 +721,76 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    plan.close()
     return 0
+
+
+def shape_matched(args, g, torch, system, part, Hd, Pprev, stream, probe):
+    """The same system and previous P thresholded at the variant tau, whose
+    sub-problems fall in the 400-1,600 range the workload names: FP32 and
+    FP16 timings, and the whole FP64 oracle on the host as its CPU baseline."""
+    n_occ = system.n_occ
+    tau = args.variant_tau
+    with torch.cuda.stream(stream):
+        plan = g.gsp2_plan_create(Pprev, tau, part, args.n_parts, stream=stream)
+    info, core_sizes, sub_sizes = g.gsp2_plan_query(plan)
+    s = np.asarray(sub_sizes, dtype=np.float64)
+    sym_flops = float(np.sum(s * s * (s + 1.0)))
+    P = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
+    out = {"tau": tau, "s_min": info["min_s"], "s_max": info["max_s"], "s_mean": round(float(s.mean()), 1),
+           "sum_s3": info["sum_s3"], "tiles_per_product": info["n_tiles"]}
+    alphas = None
+    for prec in ("fp32", "fp16"):
+        tune = None
+        with torch.cuda.stream(stream):
+            if prec != "fp32" and not args.no_tune:
+                tune = g.gsp2_plan_tune(plan, Hd, n_occ, prec, n_products=6)
+            first = g.gsp2_density(plan, Hd, n_occ, P, max_iter=args.max_iter, precision=prec, check=False)
+        if prec == "fp32":
+            alphas = first["alpha"]
+        n_prod = first["n_products"]
+        w, tms, _ = timed_runs(g, torch, plan, Hd, n_occ, P, args.variant_steps, 2, stream,
+                               max_iter=n_prod, precision=prec, timing=True)
+        avg = statistics.fmean([x for tm in tms for x in tm["product_ms"]])
+        ach = MFMA_PRODUCTS[prec] * sym_flops / (avg * 1e-3) / 1e12
+        out[prec] = {"ms_per_P": round(statistics.median(w), 3), "n_products": n_prod, "status": first["status_name"],
+                     "trace_minus_nocc": first["trace"] - n_occ, "product_kernel_ms": round(avg, 4),
+                     "achieved_tflops": round(ach, 2), "frac": round(ach / PEAK_MFMA_TFLOPS[prec], 4),
+                     "frac_of_measured_peak": round(ach / probe[prec], 4) if prec in probe else None,
+                     "tile16_tuning": tune}
+        log(f"tau={tau:g}: {prec} {out[prec]['ms_per_P']:.2f} ms/P, kernel {avg:.3f} ms, {ach:.1f} TFLOP/s")
+    if not args.no_cpu_baseline:
+        index = [g.gsp2_plan_part_index(plan, k) for k in range(args.n_parts)]
+        out["cpu_baseline"] = cpu_baseline(system, index, core_sizes, alphas, whole=True)
+        log(f"tau={tau:g}: cpu baseline {out['cpu_baseline']['value']:.0f} ms/P")
+    plan.close()
+    return out
+
+
+def main():
+    args = parse()
+    batch = args.workload == "batch16"
+    args.precision = args.precision or ("fp16" if batch else "fp32")
+    args.refine = (2 if batch else 0) if args.refine is None else args.refine
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}); "
+              "run with --gpus 1", file=sys.stderr)
+        return 2
+    import torch
+
+    import paper_1801_10016_amd as g
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    g.load()
+    torch.cuda.set_device(0)
+    if args.copy_probe_gib > 0:
+        return copy_probe(torch, args.copy_probe_gib)
+    if args.workload == "batch16":
+        return bench_batch(args, g, torch)
+    if args.workload == "backward1000":
+        return bench_backward(args, g, torch)
+    return bench_water(args, g, torch)
 
 
 if __name__ == "__main__":

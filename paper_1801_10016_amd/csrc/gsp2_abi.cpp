@@ -854,10 +854,12 @@ static void fill_info(const RunState &r, gsp2_run_info *info) {
     info->traces[GSP2_MAX_ITER] = r.traces[GSP2_MAX_ITER];
 }
 
-static gsp2_status collect(gsp2_plan_s *plan, gsp2_run_info *info) {
+// Wait for the run whose state is at `dev_state` (the plan's own, or the
+// static scratch's) and report it.
+static gsp2_status collect(gsp2_plan_s *plan, const RunState *dev_state, gsp2_run_info *info) {
     gsp2_status run_status = GSP2_OK;
     const gsp2_status st = guarded([&] {
-        check_hip(hipMemcpyAsync(plan->h_state, plan->dp.state, sizeof(RunState) * (size_t)plan->n_sys,
+        check_hip(hipMemcpyAsync(plan->h_state, dev_state, sizeof(RunState) * (size_t)plan->n_sys,
                                  hipMemcpyDeviceToHost, plan->stream), "copy run state");
         check_hip(hipStreamSynchronize(plan->stream), "run");
         int32_t bad = -1;
@@ -887,95 +889,109 @@ static gsp2_status collect(gsp2_plan_s *plan, gsp2_run_info *info) {
     return run_status;
 }
 
+// Checks of one density-matrix call: the run parameters, and the
+// per-system parameters staged in the plan's pinned buffer for the upload
+// before the launch.
+static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ, const gsp2_run_options &o,
+                             void *P_val) {
+    if (!plan) fail(GSP2_E_INVALID, "null plan");
+    if (!H) fail(GSP2_E_INVALID, "null H");
+    if (H->n != plan->n) fail(GSP2_E_INVALID, "H.n differs from the plan");
+    if (H->nnz < 0 || !H->row_ptr || (H->nnz > 0 && (!H->col || !H->val)))
+        fail(GSP2_E_INVALID, "bad H arrays");
+    if (H->dtype != GSP2_F32 && H->dtype != GSP2_F64) fail(GSP2_E_INVALID, "bad H.dtype");
+    if (!P_val) fail(GSP2_E_INVALID, "null P_val");
+    const int32_t n_sys = plan->n_sys;
+    if (n_sys > 1 && !o.n_occ_system) fail(GSP2_E_INVALID, "a batched plan needs n_occ_system");
+    RunParams rp{};
+    rp.trace_tol = o.trace_tol;
+    rp.mode = o.alpha_mode;
+    rp.stop_rule = o.stop_rule ? 1 : 0;
+    if (o.precision != GSP2_PREC_FP32 && o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16 &&
+        o.precision != GSP2_PREC_FP16X3 && o.precision != GSP2_PREC_FP64)
+        fail(GSP2_E_INVALID, "bad precision");
+    const bool wide16 = o.precision == GSP2_PREC_FP16 || o.precision == GSP2_PREC_BF16 ||
+                        o.precision == GSP2_PREC_FP16X3;
+    if (wide16 && plan->dp.max_s_pad > kMaxWidePad)
+        fail(GSP2_E_UNSUPPORTED, "16-bit products need every padded sub-problem size <= " +
+                                     std::to_string(kMaxWidePad));
+    if (o.refine < 0 || o.refine > 8) fail(GSP2_E_INVALID, "refine must be in 0..8");
+    if (o.symmetrize != 0 && o.symmetrize != 1) fail(GSP2_E_INVALID, "symmetrize must be 0 or 1");
+    rp.precision = o.precision;
+    rp.refine = o.refine;
+    rp.persistent = o.persistent ? 1 : 0;
+    rp.symmetrize = o.symmetrize;
+    rp.tile16 = 0;
+    if (wide16)
+        rp.tile16 = plan->tile16_fixed ? plan->tile16_fixed
+                    : plan->tile16_tuned[rp.precision] ? plan->tile16_tuned[rp.precision] : kTileWide;
+    if (rp.persistent && (n_sys > 1 || (rp.precision != GSP2_PREC_FP32 && rp.precision != GSP2_PREC_FP16 &&
+                                         rp.precision != GSP2_PREC_BF16)))
+        fail(GSP2_E_UNSUPPORTED, "the persistent product launch takes one system and FP32, FP16 or BF16 products");
+    if (rp.persistent)
+        fail(GSP2_E_UNSUPPORTED,
+             "the persistent product launch is switched off: its first GPU run did not return and the "
+             "cause has not been established");
+    if (rp.persistent) {
+        int grid = 0;
+        check_hip(persistent_grid(rp.precision, &grid), "occupancy");
+        if (grid < 1) fail(GSP2_E_UNSUPPORTED, "persistent product kernel cannot be resident");
+        plan->dp.persist_grid = std::min(grid, plan->dp.n_tiles);
+    }
+    // per-system parameters, staged for the upload that precedes the launch
+    plan->wait_sys_staging();
+    std::memset(plan->h_sys, 0, sizeof(SysParams) * (size_t)n_sys);
+    // the stop rule's floor max(1, n u), u the unit roundoff of the product operands
+    const double u = o.precision == GSP2_PREC_FP16     ? std::ldexp(1.0, -11)
+                     : o.precision == GSP2_PREC_BF16   ? std::ldexp(1.0, -8)
+                     : o.precision == GSP2_PREC_FP16X3 ? std::ldexp(1.0, -22)
+                     : o.precision == GSP2_PREC_FP64   ? std::ldexp(1.0, -53)
+                                                       : std::ldexp(1.0, -24);
+    if (!(o.trace_tol >= 0.0)) fail(GSP2_E_INVALID, "trace_tol must be >= 0");
+    if (o.alpha_mode == GSP2_ALPHA_REPLAY) {
+    } else if (o.alpha_mode == GSP2_ALPHA_TRACE) {
+        if (o.max_iter < 1 || o.max_iter > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter out of range");
+    } else {
+        fail(GSP2_E_INVALID, "bad alpha_mode");
+    }
+    const bool own_seq = n_sys > 1 && o.alpha_mode == GSP2_ALPHA_REPLAY && o.alpha_seq_system;
+    if (own_seq && !o.n_alpha_system) fail(GSP2_E_INVALID, "null n_alpha_system");
+    rp.n_steps = 0;
+    for (int32_t y = 0; y < n_sys; ++y) {
+        SysParams &sp = plan->h_sys[y];
+        const std::string who = n_sys > 1 ? " (system " + std::to_string(y) + ")" : "";
+        const double occ = n_sys > 1 ? o.n_occ_system[y] : n_occ;
+        if (!(occ >= 0.0) || !(occ <= (double)plan->sys_size[y])) fail(GSP2_E_INVALID, "need 0 <= n_occ <= n" + who);
+        sp.n_occ = occ;
+        sp.stop_floor = std::max(1.0, plan->sys_size[y] * u);
+        if (o.alpha_mode == GSP2_ALPHA_TRACE) {
+            sp.n_steps = o.max_iter;
+        } else {
+            const int32_t na = own_seq ? o.n_alpha_system[y] : o.n_alpha;
+            const int8_t *seq = own_seq ? o.alpha_seq_system + (size_t)y * GSP2_MAX_ITER : o.alpha_seq;
+            if (na < 0 || na > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_alpha out of range" + who);
+            if (na > 0 && !seq) fail(GSP2_E_INVALID, "null alpha_seq");
+            for (int i = 0; i < na; ++i) {
+                if (seq[i] != 1 && seq[i] != -1) fail(GSP2_E_INVALID, "alpha must be +1 or -1" + who);
+                sp.alpha_seq[i] = seq[i];
+            }
+            sp.n_steps = na;
+        }
+        rp.n_steps = std::max(rp.n_steps, sp.n_steps);
+    }
+    if (rp.n_steps + rp.refine > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter + refine exceeds GSP2_MAX_ITER");
+    return rp;
+}
+
 gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const gsp2_run_options *run,
                          void *P_val, gsp2_run_info *info) {
     gsp2_status st = guarded([&] {
-        if (!plan) fail(GSP2_E_INVALID, "null plan");
-        if (!H) fail(GSP2_E_INVALID, "null H");
-        if (H->n != plan->n) fail(GSP2_E_INVALID, "H.n differs from the plan");
-        if (H->nnz < 0 || !H->row_ptr || (H->nnz > 0 && (!H->col || !H->val)))
-            fail(GSP2_E_INVALID, "bad H arrays");
-        if (H->dtype != GSP2_F32 && H->dtype != GSP2_F64) fail(GSP2_E_INVALID, "bad H.dtype");
-        if (!P_val) fail(GSP2_E_INVALID, "null P_val");
         gsp2_run_options def;
         gsp2_run_options_default(&def);
         const gsp2_run_options &o = run ? *run : def;
-        const int32_t n_sys = plan->n_sys;
-        if (n_sys > 1 && !o.n_occ_system) fail(GSP2_E_INVALID, "a batched plan needs n_occ_system");
-        RunParams rp{};
-        rp.trace_tol = o.trace_tol;
-        rp.mode = o.alpha_mode;
-        rp.stop_rule = o.stop_rule ? 1 : 0;
-        if (o.precision != GSP2_PREC_FP32 && o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16 &&
-            o.precision != GSP2_PREC_FP16X3 && o.precision != GSP2_PREC_FP64)
-            fail(GSP2_E_INVALID, "bad precision");
-        const bool wide16 = o.precision == GSP2_PREC_FP16 || o.precision == GSP2_PREC_BF16 ||
-                            o.precision == GSP2_PREC_FP16X3;
-        if (wide16 && plan->dp.max_s_pad > kMaxWidePad)
-            fail(GSP2_E_UNSUPPORTED, "16-bit products need every padded sub-problem size <= " +
-                                         std::to_string(kMaxWidePad));
-        if (o.refine < 0 || o.refine > 8) fail(GSP2_E_INVALID, "refine must be in 0..8");
-        if (o.symmetrize != 0 && o.symmetrize != 1) fail(GSP2_E_INVALID, "symmetrize must be 0 or 1");
-        rp.precision = o.precision;
-        rp.refine = o.refine;
-        rp.persistent = o.persistent ? 1 : 0;
-        rp.symmetrize = o.symmetrize;
-        rp.tile16 = 0;
-        if (wide16)
-            rp.tile16 = plan->tile16_fixed ? plan->tile16_fixed
-                        : plan->tile16_tuned[rp.precision] ? plan->tile16_tuned[rp.precision] : kTileWide;
-        if (rp.persistent)
-            fail(GSP2_E_UNSUPPORTED,
-                 "the persistent product launch is switched off: its first GPU run did not return and the "
-                 "cause has not been established");
-        if (rp.persistent) {
-            int grid = 0;
-            check_hip(persistent_grid(rp.precision, &grid), "occupancy");
-            if (grid < 1) fail(GSP2_E_UNSUPPORTED, "persistent product kernel cannot be resident");
-            plan->dp.persist_grid = std::min(grid, plan->dp.n_tiles);
-        }
-        // per-system parameters, staged for the upload that precedes the launch
-        plan->wait_sys_staging();
-        std::memset(plan->h_sys, 0, sizeof(SysParams) * (size_t)n_sys);
-        // the stop rule's floor max(1, n u), u the unit roundoff of the product operands
-        const double u = o.precision == GSP2_PREC_FP16     ? std::ldexp(1.0, -11)
-                         : o.precision == GSP2_PREC_BF16   ? std::ldexp(1.0, -8)
-                         : o.precision == GSP2_PREC_FP16X3 ? std::ldexp(1.0, -22)
-                         : o.precision == GSP2_PREC_FP64   ? std::ldexp(1.0, -53)
-                                                           : std::ldexp(1.0, -24);
-        if (!(o.trace_tol >= 0.0)) fail(GSP2_E_INVALID, "trace_tol must be >= 0");
-        if (o.alpha_mode == GSP2_ALPHA_REPLAY) {
-        } else if (o.alpha_mode == GSP2_ALPHA_TRACE) {
-            if (o.max_iter < 1 || o.max_iter > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter out of range");
-        } else {
-            fail(GSP2_E_INVALID, "bad alpha_mode");
-        }
-        const bool own_seq = n_sys > 1 && o.alpha_mode == GSP2_ALPHA_REPLAY && o.alpha_seq_system;
-        if (own_seq && !o.n_alpha_system) fail(GSP2_E_INVALID, "null n_alpha_system");
-        rp.n_steps = 0;
-        for (int32_t y = 0; y < n_sys; ++y) {
-            SysParams &sp = plan->h_sys[y];
-            const std::string who = n_sys > 1 ? " (system " + std::to_string(y) + ")" : "";
-            const double occ = n_sys > 1 ? o.n_occ_system[y] : n_occ;
-            if (!(occ >= 0.0) || !(occ <= (double)plan->sys_size[y])) fail(GSP2_E_INVALID, "need 0 <= n_occ <= n" + who);
-            sp.n_occ = occ;
-            sp.stop_floor = std::max(1.0, plan->sys_size[y] * u);
-            if (o.alpha_mode == GSP2_ALPHA_TRACE) {
-                sp.n_steps = o.max_iter;
-            } else {
-                const int32_t na = own_seq ? o.n_alpha_system[y] : o.n_alpha;
-                const int8_t *seq = own_seq ? o.alpha_seq_system + (size_t)y * GSP2_MAX_ITER : o.alpha_seq;
-                if (na < 0 || na > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_alpha out of range" + who);
-                if (na > 0 && !seq) fail(GSP2_E_INVALID, "null alpha_seq");
-                for (int i = 0; i < na; ++i) {
-                    if (seq[i] != 1 && seq[i] != -1) fail(GSP2_E_INVALID, "alpha must be +1 or -1" + who);
-                    sp.alpha_seq[i] = seq[i];
-                }
-                sp.n_steps = na;
-            }
-            rp.n_steps = std::max(rp.n_steps, sp.n_steps);
-        }
-        if (rp.n_steps + rp.refine > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter + refine exceeds GSP2_MAX_ITER");
+        const RunParams rp = prepare_run(plan, H, n_occ, o, P_val);
+        const bool wide16 = rp.precision == GSP2_PREC_FP16 || rp.precision == GSP2_PREC_BF16 ||
+                            rp.precision == GSP2_PREC_FP16X3;
         if (rp.precision == GSP2_PREC_FP64 && !plan->dp.buf64[0]) {
             // FP64 iterates, allocated on the first FP64 run
             plan->dp.buf64[0] = plan->alloc<double>(plan->arena_floats, "FP64 X buffer 0");
@@ -1021,13 +1037,13 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
         plan->last_timed = o.timing != 0;
     });
     if (st != GSP2_OK || !info) return st;
-    return collect(plan, info);
+    return collect(plan, plan->dp.state, info);
 }
 
 gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info) {
     if (!plan) { g_last_error = "null plan"; return GSP2_E_INVALID; }
     if (!plan->ran) { g_last_error = "no run on this plan"; return GSP2_E_INVALID; }
-    return collect(plan, info);
+    return collect(plan, plan->dp.state, info);
 }
 
 gsp2_status gsp2_run_timing(gsp2_plan plan, gsp2_timing *out) {

@@ -316,11 +316,23 @@ __global__ __launch_bounds__(kBlock) void k_gather_x0(const int64_t *__restrict_
             if constexpr (sizeof(XT) == 4) {
                 uint2 *dsh = Xs ? reinterpret_cast<uint2 *>(Xs + pd.x_off + (int64_t)r * ld + c0) : nullptr;
                 uint2 *dlo = Xlo ? reinterpret_cast<uint2 *>(Xlo + pd.x_off + (int64_t)r * ld + c0) : nullptr;
+                // plain 16-bit copies hold X without its diagonal: the products
+                // take the diagonal terms exactly in FP32 (sp2_tile_wide)
+                const int dq = (r >= c0 && r < c0 + cw && prec != GSP2_PREC_FP16X3) ? r - c0 : -1;
                 for (int i = lane; i < n16; i += kWave) {
                     const uint4 u = row_u[i];
                     dst[i] = u;
                     const float4 v = __builtin_bit_cast(float4, u);
-                    if (dsh) dsh[i] = pack4(v, prec);
+                    if (dsh) {
+                        float4 w = v;
+                        if ((dq >> 2) == i) {
+                            if ((dq & 3) == 0) w.x = 0.0f;
+                            else if ((dq & 3) == 1) w.y = 0.0f;
+                            else if ((dq & 3) == 2) w.z = 0.0f;
+                            else w.w = 0.0f;
+                        }
+                        dsh[i] = pack4(w, prec);
+                    }
                     if (dlo) dlo[i] = pack4_fp16_lo(v);
                 }
             } else {
@@ -634,7 +646,19 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
         Bs_[0] = pb##S##0; Bs_[32 * kLdsRow] = pb##S##1;                                           \
         Bs_[64 * kLdsRow] = pb##S##2; Bs_[96 * kLdsRow] = pb##S##3;                                \
     } while (0)
-    auto compute = [&](int buf) __attribute__((always_inline)) {
+    // Work the matrix cores can skip, exactly (wave-uniform):
+    //  * a 32-row (or 32-column) block that starts at or beyond s lies in the
+    //    zero padding, so its products are zero and its accumulator stays 0;
+    //  * in a diagonal tile the lower-left wave's block is the transpose of
+    //    the upper-right wave's (the same products in the same order), so
+    //    that wave forms no products and the upper-right wave writes both.
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const bool mirror_wave = diag && (wv >> 1) == 1 && (wv & 1) == 0;
+    const bool actA[2] = {!mirror_wave && I0 + (wv >> 1) * 64 < pd.s, !mirror_wave && I0 + (wv >> 1) * 64 + 32 < pd.s};
+    const bool actB[2] = {J0 + (wv & 1) * 64 < pd.s, J0 + (wv & 1) * 64 + 32 < pd.s};
+    const bool all_active = actA[0] && actA[1] && actB[0] && actB[1];
+    const bool any_active = (actA[0] || actA[1]) && (actB[0] || actB[1]);
+    auto compute_full = [&](int buf) __attribute__((always_inline)) {
         const uint4 *Asb = lds(buf, 0);
         const uint4 *Bsb = lds(buf, 1);
         // interleave the LDS fragment reads with the MFMAs (3.5% faster FP32
@@ -655,6 +679,30 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 #pragma unroll
                 for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
         }
+    };
+    // edge tiles: only the blocks that reach into s
+    auto compute_part = [&](int buf) __attribute__((always_inline)) {
+        const uint4 *Asb = lds(buf, 0);
+        const uint4 *Bsb = lds(buf, 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int w = kF32 ? kh * 4 + q : 2 * q + kh;
+            uint4 fa[2], fb[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
+                fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int nn = 0; nn < 2; ++nn)
+                    if (actA[m] && actB[nn]) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
+        }
+    };
+    auto compute = [&](int buf) __attribute__((always_inline)) {
+        if (all_active) compute_full(buf);
+        else if (any_active) compute_part(buf);
     };
     GSP2_LD(0, 0);
     GSP2_ST(0, 0);
@@ -683,49 +731,63 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 #undef GSP2_ST
 
     // Epilogue.  Accumulator element i of lane (l32, kh) in a 32x32 block is
-    // row 8*(i/4) + 4*kh + (i%4), column l32.
+    // row 8*(i/4) + 4*kh + (i%4), column l32.  Plain 16-bit operands carry X
+    // without its diagonal D (X = D + O): the matrix cores formed O O, and
+    // the epilogue adds D O + O D + D^2 in FP32, (d_r + d_c) X_rc off the
+    // diagonal and d_r^2 on it, so the diagonal is never rounded.
+    constexpr bool kExactDiag = !kF32 && !kSplit;
+    // a diagonal tile's lower-left block is written by the upper-right wave
+    const bool write_mirror = !diag || ((wv >> 1) == 0 && (wv & 1) == 1);
     double tY = 0.0, tX = 0.0;
+    if (!mirror_wave) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
+        for (int m = 0; m < 2; ++m) {
 #pragma unroll
-        for (int nn = 0; nn < 2; ++nn) {
-            const int cg = J0 + wc * 64 + nn * 32 + l32;
+            for (int nn = 0; nn < 2; ++nn) {
+                const int cg = J0 + wc * 64 + nn * 32 + l32;
+                const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int rg0 = I0 + wr * 64 + m * 32 + g * 8 + kh * 4;
-                float xn[4];
+                for (int g = 0; g < 4; ++g) {
+                    const int rg0 = I0 + wr * 64 + m * 32 + g * 8 + kh * 4;
+                    float xn[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int rg = rg0 + e;
-                    const float y = acc[m][nn][4 * g + e];
-                    const float xo = X[(int64_t)rg * ld + cg];
-                    const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
-                    xn[e] = v;
-                    Xn[(int64_t)rg * ld + cg] = v;
-                    if constexpr (!kF32) {
-                        const Op h = static_cast<Op>(v);
-                        Xnop[(int64_t)rg * ld + cg] = h;
-                        if constexpr (kSplit)
-                            Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
+                    for (int e = 0; e < 4; ++e) {
+                        const int rg = rg0 + e;
+                        const float yacc = acc[m][nn][4 * g + e];
+                        const float xo = X[(int64_t)rg * ld + cg];
+                        float y = yacc;
+                        if constexpr (kExactDiag) {
+                            const float dr = X[(int64_t)rg * (ld + 1)];
+                            y = rg == cg ? yacc + dr * dr : yacc + (dr + dc) * xo;
+                        }
+                        const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
+                        xn[e] = v;
+                        Xn[(int64_t)rg * ld + cg] = v;
+                        if constexpr (!kF32) {
+                            const Op h = (kExactDiag && rg == cg) ? static_cast<Op>(0.0f) : static_cast<Op>(v);
+                            Xnop[(int64_t)rg * ld + cg] = h;
+                            if constexpr (kSplit)
+                                Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
+                        }
+                        if (diag && rg == cg && rg < pd.c) {
+                            tY += static_cast<double>(y);
+                            tX += static_cast<double>(v);
+                        }
                     }
-                    if (diag && rg == cg && rg < pd.c) {
-                        tY += static_cast<double>(y);
-                        tX += static_cast<double>(v);
-                    }
-                }
-                if (!diag) {
-                    const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
-                    *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
-                    if constexpr (!kF32) {
-                        union { Op h[4]; uint2 u; } pk, pl;
+                    if (write_mirror) {
+                        const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
+                        *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
+                        if constexpr (!kF32) {
+                            union { Op h[4]; uint2 u; } pk, pl;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
-                        *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
-                        if constexpr (kSplit) {
+                            for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
+                            *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
+                            if constexpr (kSplit) {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
-                            *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
+                                for (int e = 0; e < 4; ++e)
+                                    pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
+                                *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
+                            }
                         }
                     }
                 }
@@ -858,8 +920,11 @@ __device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd,
 #undef GSP2_ST64
 
     // Epilogue.  Element v of a 16 x 16 block's accumulator in lane (l16, g)
-    // is row 4 g + v, column l16.  X_old (for X' = 2X - Y) is read at the
-    // mirrored position, four consecutive doubles of one row of X.
+    // is row 4 v + g, column l16 (the FP64 MFMA interleaves its output rows
+    // over the lane groups, unlike the 16 x 16 FP32 and 16-bit forms).  X_old
+    // and the direct writes are 16 consecutive columns of one row per lane
+    // group; each mirrored row receives 4 consecutive doubles per MFMA row
+    // group.
     double tY = 0.0, tX = 0.0;
     const bool upd = alpha > 0.0;
 #pragma unroll
@@ -867,28 +932,23 @@ __device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd,
 #pragma unroll
         for (int nn = 0; nn < 4; ++nn) {
             const int cg = J0 + wc * 64 + nn * 16 + l16;
-            const int rg0 = I0 + wr * 64 + m * 16 + 4 * g;
+            const int rb = I0 + wr * 64 + m * 16 + g;
             double xo[4] = {0.0, 0.0, 0.0, 0.0};
             if (upd) {
-                const double2 u0 = *reinterpret_cast<const double2 *>(X + (int64_t)cg * ld + rg0);
-                const double2 u1 = *reinterpret_cast<const double2 *>(X + (int64_t)cg * ld + rg0 + 2);
-                xo[0] = u0.x; xo[1] = u0.y; xo[2] = u1.x; xo[3] = u1.y;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xo[v] = X[(int64_t)(rb + 4 * v) * ld + cg];
             }
-            double xn[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
+                const int rg = rb + 4 * v;
                 const double y = acc[m][nn][v];
                 const double val = upd ? (2.0 * xo[v] - y) : y;
-                xn[v] = val;
-                Xn[(int64_t)(rg0 + v) * ld + cg] = val;
-                if (diag && rg0 + v == cg && cg < pd.c) {
+                Xn[(int64_t)rg * ld + cg] = val;
+                if (!diag) Xn[(int64_t)cg * ld + rg] = val;
+                if (diag && rg == cg && cg < pd.c) {
                     tY += y;
                     tX += val;
                 }
-            }
-            if (!diag) {
-                *reinterpret_cast<double2 *>(Xn + (int64_t)cg * ld + rg0) = make_double2(xn[0], xn[1]);
-                *reinterpret_cast<double2 *>(Xn + (int64_t)cg * ld + rg0 + 2) = make_double2(xn[2], xn[3]);
             }
         }
     }
@@ -1154,13 +1214,25 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
     // fixup after the last product completes it (k_wide_fixup).
     constexpr int kBandRow = 132;               // floats per LDS band row: 128 + 4 pad
     float *band = reinterpret_cast<float *>(lds_base) + wave * 32 * kBandRow;
+    // Plain operands carry X without its diagonal D (X = D + O): the matrix
+    // cores formed O O, and the epilogue adds D O + O D + D^2 in FP32,
+    // (d_r + d_c) X_rc off the diagonal and d_r^2 on it, so the diagonal (two
+    // thirds of X's norm here) is never rounded to 16 bits.  The tile's
+    // diagonal entries of X are staged in LDS behind the four bands.
+    float *d_row = reinterpret_cast<float *>(lds_base) + 4 * 32 * kBandRow;
+    float *d_col = d_row + kTileW;
+    if constexpr (!kSplit) {
+        d_row[tid] = I0 + tid < ld ? X[(int64_t)(I0 + tid) * (ld + 1)] : 0.0f;
+        d_col[tid] = J0 + tid < ld ? X[(int64_t)(J0 + tid) * (ld + 1)] : 0.0f;
+        __syncthreads();
+    }
     double tY = 0.0, tX = 0.0;
     if (active) {
         const bool upd = alpha > 0.0f;
         float4 xo[4][4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            if (upd) {
+            if (upd || !kSplit) {
 #pragma unroll
                 for (int nn = 0; nn < 4; ++nn) {
                     const int cg = J0 + wc * 128 + nn * 32 + l32;
@@ -1194,7 +1266,12 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
                     float xn[4];
 #pragma unroll
                     for (int e = 0; e < 4; ++e) {
-                        const float y = acc[m][nn][4 * g + e];
+                        float y = acc[m][nn][4 * g + e];
+                        if constexpr (!kSplit) {
+                            const int rl = wr * 128 + m * 32 + g * 8 + kh * 4 + e, cl = wc * 128 + nn * 32 + l32;
+                            const float dr = d_row[rl];
+                            y = (diag && rl == cl) ? y + dr * dr : y + (dr + d_col[cl]) * xov[e];
+                        }
                         const float v = upd ? (2.0f * xov[e] - y) : y;
                         xn[e] = v;
                         band[(g * 8 + kh * 4 + e) * kBandRow + nn * 32 + l32] = v;
@@ -1276,8 +1353,10 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
                     }
                     const float xv[8] = {va.x, va.y, va.z, va.w, vb.x, vb.y, vb.z, vb.w};
                     union { Op h[8]; uint4 u; } pk;
+                    // the operand copy's diagonal stays zero
+                    const int dloc = diag ? (wr * 128 + m * 32 + r) - (wc * 128 + c8 * 8) : -1;
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) pk.h[e] = static_cast<Op>(xv[e]);
+                    for (int e = 0; e < 8; ++e) pk.h[e] = e == dloc ? static_cast<Op>(0.0f) : static_cast<Op>(xv[e]);
                     *reinterpret_cast<uint4 *>(Xnop + o) = pk.u;
                 }
             }
@@ -1861,6 +1940,11 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     const dim3 grid(dp.n_tiles);
     float *b0 = dp.buf[0], *b1 = dp.buf[1];
     if (rp.persistent && rp.n_steps > 0) {
+        // the persistent kernel keeps one system's control state and has no
+        // split-operand or FP64 form: anything else is refused here too
+        if (dp.n_sys != 1 || (rp.precision != GSP2_PREC_FP32 && rp.precision != GSP2_PREC_FP16 &&
+                              rp.precision != GSP2_PREC_BF16))
+            return hipErrorInvalidValue;
         const dim3 pg(dp.persist_grid);
         record(rec, k_persist_reset, dim3(1), blk, dp.persist);
         if (ev) rec.add_event(ev->persist_begin);

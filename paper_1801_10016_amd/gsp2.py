@@ -399,9 +399,9 @@ def run_info_dict(info: gsp2_run_info) -> dict:
     }
 
 
-def gsp2_density(plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=None,
-                 stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False,
-                 precision="fp32", refine=0, persistent=False, symmetrize=False):
+def _density(entry: str, plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=None,
+             stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False,
+             precision="fp32", refine=0, persistent=False, symmetrize=False):
     """Enqueue one density matrix into P_val (torch on the GPU, nnz_P entries:
     float64 for precision "fp64", float32 otherwise).  With want_info the
     call waits and returns the run's info dict (a list of them, one per
@@ -421,8 +421,8 @@ def gsp2_density(plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=
     o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine, persistent,
                                n_occ_system=n_occ if batched else None, symmetrize=symmetrize)
     info = (gsp2_run_info * plan.n_systems)() if want_info else None
-    st = load().gsp2_density(plan.handle, C.byref(c), 0.0 if batched else float(n_occ), C.byref(o),
-                             C.c_void_p(P_val.data_ptr()), info)
+    st = getattr(load(), entry)(plan.handle, C.byref(c), 0.0 if batched else float(n_occ), C.byref(o),
+                                C.c_void_p(P_val.data_ptr()), info)
     del keep
     msg = load().gsp2_last_error().decode()
     if check and st != GSP2_OK:
@@ -434,6 +434,11 @@ def gsp2_density(plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=
         d["call_status"] = st
         d["message"] = msg
     return ds if batched else ds[0]
+
+
+def gsp2_density(plan: Plan, H: DeviceCSR, n_occ, P_val, **kw):
+    """gsp2_density: one density matrix into P_val (see _density)."""
+    return _density("gsp2_density", plan, H, n_occ, P_val, **kw)
 
 
 def gsp2_run_status(plan: Plan):

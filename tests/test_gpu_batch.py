@@ -21,7 +21,7 @@ from tests import _pins as pins
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-MIXED_TOL = {"fp16": 3e-3, "bf16": 3e-2}
+MIXED_TOL_FP16 = 1e-3          # the stated bar of 16-bit products, against the FP64 oracle
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -151,7 +151,7 @@ def test_batch_mixed_precision_against_oracle():
         assert runs[i]["status"] == 0 and runs[i]["n_refine"] == 2, (i, runs[i])
         err = rel_fro(b.block(P, i), ref.csc())
         print(f"fp16+2 system {i}: rel_err={err:.2e}", flush=True)
-        assert err <= MIXED_TOL["fp16"], (i, err)
+        assert err <= MIXED_TOL_FP16, (i, err)
 
 
 def test_per_system_status_is_independent():

@@ -21,7 +21,7 @@ from synth.batch import make_batch
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-MIXED_TOL_FP16 = 3e-3
+MIXED_TOL_FP16 = 1e-3          # the stated bar of 16-bit products, against the FP64 oracle
 
 
 def tie_band(n):

@@ -1,30 +1,29 @@
-"""Full-size G-SP2 on the GPU against the FP64 oracle: 3,500 water molecules
-(21,000 orbitals), 128 uneven parts, tau = 1e-5, in the bench's launch
-configuration (one HIP graph, FP32 products).
+"""Full-size G-SP2 on the GPU against the FP64 oracle, in the benchmark's
+workload and launch configuration: 3,500 water molecules (21,000 orbitals),
+128 uneven parts, tau = 1e-5, one HIP graph per density matrix.
 
-The oracle cannot redo the whole run inside a test, so the stored
-expectations (tests/golden/gsp2_water3500_tau1e-5.json, written by
-tests/golden/make_full_size_golden.py from the oracle alone) give its branch
-sequence and per-part norms and traces; a few parts are recomputed here by
-the oracle, one by one, by replaying that sequence, and compared with the
-GPU element by element.  The graph comes from the distance-based stand-in
-for the previous P, which both sides threshold in FP64."""
-import json
-import os
-
+The graph comes from a previous P computed by regular SP2 (Methods, "Graph
+Theory"): here the library's FP64 dense SP2 of H, whose threshold must give
+exactly the graph of the oracle's own FP64 dense SP2 P (stored digest; no
+entry of the oracle's P lies within 1e-7 relative of tau, so rounding-level
+differences cannot move an edge).  The stored expectations
+(tests/golden/gsp2_water3500_densep_tau1e-5.*, oracle calls only) give, per
+part, its index list digest and a Gaussian sketch of its core columns, so
+every one of the 128 parts is compared element-sensitively; three parts are
+also recomputed here by the oracle and compared element by element."""
 import numpy as np
 import pytest
 
-import oracle
-from synth.locality import surrogate_prev_density
 from synth.partition import uneven_spatial_partition
 from synth.water import make_water
+from tests import _full
 
 pytestmark = pytest.mark.gpu
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-GOLDEN = os.path.join(HERE, "golden", "gsp2_water3500_tau1e-5.json")
-TOL = 1e-5
+STEM = "gsp2_water3500_densep_tau1e-5"
+TOL = 1e-5                 # FP32 products
+TOL64 = 1e-10              # FP64 products
+MIXED_TOL = 1e-3           # 16-bit products, before refinement
 
 
 @pytest.fixture(scope="module")
@@ -33,138 +32,178 @@ def case():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     import paper_1801_10016_amd as g
-    with open(GOLDEN) as f:
-        gold = json.load(f)
-    sp = gold["spec"]
-    s = make_water(sp["n_mol"], sp["seed"])
-    part = uneven_spatial_partition(s, sp["n_parts"], sp["core_lo"], sp["core_hi"], seed=sp["seed"])
-    Q = surrogate_prev_density(s, sp["q_floor"])
-    print(f"full size: N={s.n} nnz(Q)={Q.nnz}", flush=True)
+    gold, arrays = _full.load_golden(STEM)
+    sp_ = gold["spec"]
+    s = make_water(sp_["n_mol"], sp_["seed"])
+    part = uneven_spatial_partition(s, sp_["n_parts"], sp_["core_lo"], sp_["core_hi"], seed=sp_["seed"])
     stream = torch.cuda.Stream()
     Hd = g.csr_to_device(s.H)
-    Qd = g.csr_to_device(Q)
+    print(f"full size: N={s.n}; FP64 regular SP2 for the previous P", flush=True)
+    Pprev, dense_run = _full.fp64_previous_p(g, torch, Hd, s.n, s.n_occ, stream)
+    dsk = _full.dense_sketch(torch, Pprev.val, s.n)
     with torch.cuda.stream(stream):
-        plan = g.gsp2_plan_create(Qd, sp["tau"], part, sp["n_parts"], stream=stream)
+        plan = g.gsp2_plan_create(Pprev, sp_["tau"], part, sp_["n_parts"], stream=stream)
+    del Pprev
+    torch.cuda.empty_cache()
     info, cs, ss = g.gsp2_plan_query(plan)
-    col_ptr, row_idx = g.gsp2_plan_pattern(plan)
+    col_ptr, _ = g.gsp2_plan_pattern(plan)
+    adj_ptr, adj_col = g.gsp2_plan_graph(plan)
+    digest, nnz_sym = _full.graph_digest(adj_ptr, adj_col, s.n)
     P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
-    # the oracle recomputes three parts (smallest, median, largest) by replaying its sequence
-    sizes = np.array([p["s"] for p in gold["parts"]])
-    order = np.argsort(sizes)
-    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
-    ref = oracle.gsp2(s.H, Q, sp["tau"], part, sp["n_parts"], s.n_occ, alpha_seq=gold["alphas"],
-                      parts_subset=pick, trace_tol=1e9)
-    yield dict(g=g, torch=torch, gold=gold, s=s, part=part, Q=Q, plan=plan, info=info, cs=cs, ss=ss,
-               col_ptr=col_ptr, row_idx=row_idx, P_val=P_val, Hd=Hd, stream=stream, pick=pick, ref=ref,
-               sizes=sizes)
+    print("oracle: replaying the stored sequence on the three sampled parts", flush=True)
+    samples = _full.oracle_sampled_parts(gold, arrays, s, gold["alphas"])
+    yield dict(g=g, torch=torch, gold=gold, arrays=arrays, s=s, part=part, plan=plan, info=info, cs=cs, ss=ss,
+               col_ptr=col_ptr, P_val=P_val, Hd=Hd, stream=stream, dense_run=dense_run, dense_sketch=dsk,
+               digest=digest, nnz_sym=nnz_sym, samples=samples)
     plan.close()
 
 
-def _sampled_errors(c, vals):
-    errs = {}
-    for i, k in enumerate(c["pick"]):
-        idx, blk = _core_block(c, vals, k)
-        assert np.array_equal(idx, c["ref"].index[i])
-        errs[k] = np.linalg.norm(blk - c["ref"].core_columns[i]) / np.linalg.norm(c["ref"].core_columns[i])
-    return errs
+def _run(c, precision="fp32", **kw):
+    torch = c["torch"]
+    P = c["P_val"] if precision != "fp64" else torch.empty(c["info"]["nnz_P"], dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(c["stream"]):
+        run = c["g"].gsp2_density(c["plan"], c["Hd"], c["s"].n_occ, P, precision=precision, **kw)
+    torch.cuda.synchronize()
+    return run, P.cpu().numpy()
 
 
-def _run(c, **kw):
-    with c["torch"].cuda.stream(c["stream"]):
-        run = c["g"].gsp2_density(c["plan"], c["Hd"], c["s"].n_occ, c["P_val"], **kw)
-    c["torch"].cuda.synchronize()
-    return run, c["P_val"].cpu().numpy()
+def test_fp64_previous_p_is_the_oracles(case):
+    """The GPU's FP64 dense SP2 of H against the oracle's: sequence, trace and
+    a sketch of the whole 21,000 x 21,000 P."""
+    gold, run = case["gold"]["dense_run"], case["dense_run"]
+    m = min(len(run["alpha"]), len(gold["alphas"]))
+    err = float(np.linalg.norm(case["dense_sketch"] - case["arrays"]["dense_sketch"]) /
+                np.linalg.norm(case["arrays"]["dense_sketch"]))
+    print(f"dense FP64: products {run['n_products']} / oracle {gold['n_products']}, "
+          f"Tr P {run['trace']:.9f} / {gold['trace_P']:.9f}, sketch rel_err {err:.2e}", flush=True)
+    assert run["status"] == 0 and run["alpha"][:m] == gold["alphas"][:m]
+    assert abs(run["n_products"] - gold["n_products"]) <= 2
+    assert abs(run["trace"] - gold["trace_P"]) <= 1e-9 * case["s"].n
+    assert err <= TOL64
 
 
-def _core_block(c, vals, k):
-    """Part k's core columns from the GPU's P, rows in the part's local order."""
-    g, plan = c["g"], c["plan"]
-    idx = g.gsp2_plan_part_index(plan, k)
-    core = np.flatnonzero(c["part"] == k)
-    order = np.argsort(idx, kind="stable")          # pattern rows are ascending global ids
-    blk = np.empty((len(idx), len(core)))
-    for jl, j in enumerate(core):
-        col = vals[c["col_ptr"][j]:c["col_ptr"][j + 1]]
-        blk[order, jl] = col
-    return idx, blk
-
-
-def test_plan_sizes_match_oracle(case):
+def test_graph_and_plan_are_the_oracles(case):
     gold = case["gold"]
+    print(f"graph: {case['nnz_sym']} entries (oracle {gold['graph']['nnz_sym']}); "
+          f"s in [{case['info']['min_s']}, {case['info']['max_s']}]", flush=True)
+    assert case["nnz_sym"] == gold["graph"]["nnz_sym"] and case["digest"] == gold["graph"]["sha256"]
     assert case["cs"].tolist() == [p["c"] for p in gold["parts"]]
     assert case["ss"].tolist() == [p["s"] for p in gold["parts"]]
-    print(f"s in [{case['info']['min_s']}, {case['info']['max_s']}]", flush=True)
+    g, plan = case["g"], case["plan"]
+    for k, p in enumerate(gold["parts"]):
+        assert _full.index_digest(g.gsp2_plan_part_index(plan, k)) == p["idx_sha256"], k
 
 
 def test_replayed_sequence_matches_oracle(case):
+    """FP32 products replaying the oracle's branch sequence: every part's core
+    columns against the oracle's (sketch), three parts element by element."""
     gold = case["gold"]
     run, vals = _run(case, alpha_seq=gold["alphas"], trace_tol=1e9)
     assert np.isfinite(vals).all()
     assert abs(run["eps_min"] - gold["eps"][0]) <= 1e-12 * abs(gold["eps"][0])
     assert abs(run["eps_max"] - gold["eps"][1]) <= 1e-12 * abs(gold["eps"][1])
-    # every part: Frobenius norm and core trace of its core columns
-    fro_err = []
-    for k, p in enumerate(gold["parts"]):
-        _, blk = _core_block(case, vals, k)
-        fro_err.append(abs(np.linalg.norm(blk) - p["fro"]) / p["fro"])
-        assert abs(np.trace(blk[:p["c"], :p["c"]]) - p["core_trace"]) <= 1e-5 * p["c"]
-    print(f"max per-part |fro - fro_oracle| / fro_oracle = {max(fro_err):.2e}", flush=True)
-    assert max(fro_err) <= TOL
-    # sampled parts, element by element, against the oracle replaying the sequence
-    for k, err in _sampled_errors(case, vals).items():
-        print(f"part {k} (s={case['sizes'][k]}): rel_err={err:.2e}", flush=True)
-        assert err <= TOL
+    errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
+    print(f"all 128 parts: sketch rel_err max {errs.max():.2e}, median {np.median(errs):.2e}", flush=True)
+    assert errs.max() <= TOL
+    for k, e in _full.sampled_errors(case["samples"], vals, case["col_ptr"], case["part"]).items():
+        print(f"part {k} (s={gold['parts'][k]['s']}): element-wise rel_err={e:.2e}", flush=True)
+        assert e <= TOL
+    assert abs(run["trace"] - gold["traces"][-1]) <= 1e-5 * case["s"].n
 
 
 def test_trace_mode_run(case):
+    """FP32 products taking their own branches.  Where the run parts from the
+    oracle's sequence, the two traces must sit on either side of N_occ by no
+    more than FP32 rounding moves the trace: at that product the GPU's trace
+    differs from the oracle's by more than the oracle's distance to N_occ,
+    and by no more than sqrt(N) ||dP||_F (Cauchy-Schwarz over the N diagonal
+    entries), ||dP||_F measured on the replayed sequence.  Different branch
+    sequences give different (equally valid) G-SP2 results, so P is compared
+    with the oracle's only when the sequences agree."""
     gold = case["gold"]
+    _, rvals = _run(case, alpha_seq=gold["alphas"], trace_tol=1e9)
+    rerr = _full.part_errors(gold, case["arrays"], rvals, case["col_ptr"], case["part"]).max()
     run, vals = _run(case)
     assert run["status"] == 0, run
-    assert np.isfinite(vals).all()
     n_occ = case["s"].n_occ
     ga, oa = run["alpha"], gold["alphas"]
     m = min(len(ga), len(oa))
     diff = [i for i in range(m) if ga[i] != oa[i]]
+    errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
     print(f"gpu products {run['n_products']}, oracle {gold['n_products']}; first branch difference "
-          f"{diff[0] if diff else None}; Tr P - N_occ = {run['trace'] - n_occ:.3e}", flush=True)
+          f"{diff[0] if diff else None}; Tr P - N_occ = {run['trace'] - n_occ:.3e}; "
+          f"parts sketch rel_err max {errs.max():.2e}", flush=True)
     if diff:
         d = diff[0]
-        assert abs(gold["traces"][d] - n_occ) <= 1e-4 * case["s"].n / 1000.0
-    assert abs(run["trace"] - gold["traces"][-1]) <= 1e-2
-    # same branches, same bits: a replay of the GPU's own sequence is identical
-    if not diff and run["n_alpha"] == len(oa):
-        _, vals2 = _run(case, alpha_seq=oa, trace_tol=1e9)
-        assert np.array_equal(vals, vals2)
+        gap = abs(gold["traces"][d] - n_occ)
+        dtr = abs(run["traces"][d] - gold["traces"][d])
+        bound = np.sqrt(case["s"].n) * rerr * gold["fro_total"]
+        print(f"product {d}: oracle |Tr - N_occ| = {gap:.3e}, |Tr_gpu - Tr_oracle| = {dtr:.3e}, "
+              f"sqrt(N) ||dP||_F = {bound:.3e}", flush=True)
+        assert (run["traces"][d] - n_occ) * (gold["traces"][d] - n_occ) <= 0.0
+        assert gap <= dtr <= bound
+    else:
+        assert errs.max() <= TOL
+    assert abs(run["trace"] - gold["traces"][-1]) <= 1e-1
 
 
-@pytest.mark.parametrize("precision,bar", [("fp16", 3e-3), ("bf16", 3e-2)])
-def test_mixed_precision_error_vs_oracle(case, precision, bar):
-    """FP16/BF16 product operands on the full workload: the error against the
-    FP64 oracle, stated per mode (same replayed sequence), with and without
-    two FP32 refinement products."""
+def test_fp64_products_full_size(case):
     gold = case["gold"]
-    for refine in (0, 2):
-        run, vals = _run(case, alpha_seq=gold["alphas"], trace_tol=1e9, precision=precision, refine=refine)
-        assert np.isfinite(vals).all()
-        errs = _sampled_errors(case, vals)
-        print(f"{precision} refine={refine}: sampled-part rel_err " +
-              ", ".join(f"{e:.2e}" for e in errs.values()) + f"; Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}",
-              flush=True)
-        if refine == 0:
-            assert max(errs.values()) <= bar
+    run, vals = _run(case, precision="fp64", alpha_seq=gold["alphas"], trace_tol=1e9)
+    errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
+    print(f"fp64 replay: parts sketch rel_err max {errs.max():.2e}", flush=True)
+    assert run["status"] == 0 and errs.max() <= TOL64
+
+
+@pytest.mark.parametrize("refine", [0, 2])
+def test_fp16_error_vs_oracle(case, refine):
+    """FP16 operands (diagonal exact) on the full workload, the oracle's
+    sequence replayed: every part at the 16-bit bar, with and without two
+    FP32 refinement products."""
+    gold = case["gold"]
+    run, vals = _run(case, precision="fp16", alpha_seq=gold["alphas"], trace_tol=1e9, refine=refine)
+    assert np.isfinite(vals).all()
+    errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
+    samp = _full.sampled_errors(case["samples"], vals, case["col_ptr"], case["part"])
+    print(f"fp16 refine={refine}: parts sketch rel_err max {errs.max():.2e} median {np.median(errs):.2e}; "
+          f"sampled " + ", ".join(f"{e:.2e}" for e in samp.values()) +
+          f"; Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}", flush=True)
+    assert errs.max() <= MIXED_TOL and max(samp.values()) <= MIXED_TOL
+
+
+def test_fp16_trace_mode_full_size(case):
+    """FP16 products in trace mode with two FP32 refinement products: the run
+    takes its own branches and stop, passes the occupation check, and its P
+    meets the 16-bit bar against the oracle's P."""
+    gold = case["gold"]
+    run, vals = _run(case, precision="fp16", refine=2, check=False)
+    errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
+    print(f"fp16 trace mode: status {run['status_name']}, {run['n_products']} products, "
+          f"Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}, parts sketch rel_err max {errs.max():.2e}",
+          flush=True)
+    assert run["status"] == 0 and abs(run["trace"] - case["s"].n_occ) <= 0.5
+    assert errs.max() <= MIXED_TOL
+
+
+@pytest.mark.xfail(strict=True, raises=AssertionError,
+                   reason="BF16 products miss the 1e-3 bar at full size (6.4e-3 to 7.1e-3 measured with the "
+                          "diagonal rounded; the subspace rotation of 2^-8 rounding accumulates over the run)")
+def test_bf16_error_vs_oracle(case):
+    gold = case["gold"]
+    run, vals = _run(case, precision="bf16", alpha_seq=gold["alphas"], trace_tol=1e9)
+    errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
+    print(f"bf16: parts sketch rel_err max {errs.max():.2e} median {np.median(errs):.2e}", flush=True)
+    assert np.isfinite(vals).all() and errs.max() <= MIXED_TOL
 
 
 def test_split_fp16_full_size(case):
-    """Split FP16 products (three FP16 products per product) on the full
-    workload meet the FP32 bar against the FP64 oracle."""
+    """Split FP16 products meet the FP32 bar on every part, replayed and in
+    trace mode."""
     gold = case["gold"]
-    run, vals = _run(case, alpha_seq=gold["alphas"], trace_tol=1e9, precision="fp16x3")
-    assert np.isfinite(vals).all() and run["precision"] == 3
-    errs = _sampled_errors(case, vals)
-    print("fp16x3: sampled-part rel_err " + ", ".join(f"{e:.2e}" for e in errs.values()) +
-          f"; Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}", flush=True)
-    assert max(errs.values()) <= TOL
-    # trace mode: the stop rule fires, as with FP32 products
+    run, vals = _run(case, precision="fp16x3", alpha_seq=gold["alphas"], trace_tol=1e9)
+    errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
+    print(f"fp16x3: parts sketch rel_err max {errs.max():.2e}", flush=True)
+    assert run["precision"] == 3 and errs.max() <= TOL
     run, vals = _run(case, precision="fp16x3")
     print(f"fp16x3 trace mode: {run['n_products']} products, Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}",
           flush=True)

@@ -141,11 +141,19 @@ def test_small_system_near_tie_branch():
     _check_parity(pins.water(32, 0), 1e-3, 4)
 
 
-# Mixed precision: FP16/BF16 operands, FP32 accumulation and master iterate.
-# Rounding X to the operand format costs a relative 2^-11 (FP16) or 2^-8
-# (BF16) per product; the bars below are the error budgets stated for each
-# mode, measured against the FP64 oracle.
-MIXED_TOL = {"fp16": 3e-3, "bf16": 3e-2}
+# Mixed precision: FP16/BF16 operands, FP32 accumulation and master iterate,
+# the diagonal of X taken exactly in FP32.  The bar is the stated one for
+# 16-bit products before refinement, 1e-3 against the FP64 oracle.  FP16
+# meets it.  BF16 cannot: one product alone costs 2.4e-3 (2^-8 relative
+# rounding of the off-diagonal operand), and over a run the rotation of the
+# occupied subspace that each rounded product leaves behind adds up to
+# 3-4e-3, which purification does not undo (CPU emulation, 200 molecules:
+# 5.7e-3 with the diagonal rounded, 3.5e-3 exact); its tests against the bar
+# are expected failures, so a BF16 result that met it would be reported.
+MIXED_TOL = 1e-3
+BF16_MISSES = pytest.mark.xfail(strict=True, raises=AssertionError,
+                                reason="BF16 products miss the 1e-3 bar (measured 3.5e-3 to 7e-3 against the "
+                                       "oracle; the subspace rotation of 2^-8 rounding accumulates over the run)")
 
 
 @pytest.mark.parametrize("precision", ["fp16", "bf16"])
@@ -186,8 +194,9 @@ def test_16bit_one_update_product(precision):
     assert err <= 4 * unit
 
 
-@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+@pytest.mark.parametrize("precision", ["fp16", pytest.param("bf16", marks=BF16_MISSES)])
 def test_mixed_precision_trace_mode(precision):
+    # trace mode: the run's own branches, stop and occupation check
     from tests._gpu import rel_fro, run_gsp2
     s = pins.water(200, 1)
     Pp = _dense_prev(s)
@@ -195,17 +204,18 @@ def test_mixed_precision_trace_mode(precision):
     ref = oracle.gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ)
     out = {}
     for refine in (0, 2):
-        P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, refine=refine)
-        assert run["status"] == 0 and run["n_refine"] == refine, run
+        P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, refine=refine,
+                                      check=False)
         assert np.isfinite(vals).all()
         out[refine] = rel_fro(P, ref.csc())
-        print(f"{precision} refine={refine}: products={run['n_products']} rel_err={out[refine]:.2e} "
-              f"|Tr P - N_occ|={abs(run['trace'] - s.n_occ):.2e}", flush=True)
-    assert out[0] <= MIXED_TOL[precision]
+        print(f"{precision} refine={refine}: status {run['status_name']} products={run['n_products']} "
+              f"rel_err={out[refine]:.2e} |Tr P - N_occ|={abs(run['trace'] - s.n_occ):.2e}", flush=True)
+        assert run["status"] == 0 and run["n_refine"] == refine, run
+    assert out[0] <= MIXED_TOL and out[2] <= MIXED_TOL
     assert out[2] <= 1.05 * out[0]           # a purification pair cannot undo the subspace error, nor add to it
 
 
-@pytest.mark.parametrize("precision", ["fp16", "bf16", "fp16x3"])
+@pytest.mark.parametrize("precision", ["fp16", pytest.param("bf16", marks=BF16_MISSES), "fp16x3"])
 def test_16bit_products_on_128_tiles(precision):
     # the tile autotuner's other candidate: 16-bit products on 128 x 128
     # tiles meet the same bars as on 256 x 256 tiles, against the oracle
@@ -214,7 +224,7 @@ def test_16bit_products_on_128_tiles(precision):
     Pp = _dense_prev(s)
     part = uneven_spatial_partition(s, 6, seed=0)
     ref = oracle.gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ)
-    bar = {"fp16": MIXED_TOL["fp16"], "bf16": MIXED_TOL["bf16"], "fp16x3": 1e-5}[precision]
+    bar = {"fp16": MIXED_TOL, "bf16": MIXED_TOL, "fp16x3": 1e-5}[precision]
     errs = {}
     for tile16 in (128, 256):
         P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, tile16=tile16)
@@ -247,7 +257,7 @@ def test_tile_autotuner_choice_is_used():
     assert rec["ms_per_product_128"] > 0 and rec["ms_per_product_256"] > 0
     faster = 128 if rec["ms_per_product_128"] < rec["ms_per_product_256"] else 256
     assert rec["tile16"] == faster
-    assert run["status"] == 0 and rel_fro(P, ref.csc()) <= MIXED_TOL["fp16"]
+    assert run["status"] == 0 and rel_fro(P, ref.csc()) <= MIXED_TOL
 
 
 @pytest.mark.parametrize("n_mol,seed,n_parts,tau", [(64, 0, 8, 1e-5), (200, 1, 6, 1e-4)])
@@ -290,7 +300,7 @@ def test_refinement_products_do_not_drift():
         print(f"fp16 refine={refine}: rel_err={err[refine]:.2e} branches after the stop "
               f"{run['alpha'][n - refine:]} |Tr P - N_occ|={abs(run['trace'] - s.n_occ):.2e}", flush=True)
         assert run["alpha"][n - refine:] == [-1, 1] * (refine // 2)
-    assert err[8] <= 1.05 * err[2] and err[2] <= MIXED_TOL["fp16"]
+    assert err[8] <= 1.05 * err[2] and err[2] <= MIXED_TOL
 
 
 def test_fp32_refinement_products():
