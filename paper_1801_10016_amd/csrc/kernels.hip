@@ -646,19 +646,7 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
         Bs_[0] = pb##S##0; Bs_[32 * kLdsRow] = pb##S##1;                                           \
         Bs_[64 * kLdsRow] = pb##S##2; Bs_[96 * kLdsRow] = pb##S##3;                                \
     } while (0)
-    // Work the matrix cores can skip, exactly (wave-uniform):
-    //  * a 32-row (or 32-column) block that starts at or beyond s lies in the
-    //    zero padding, so its products are zero and its accumulator stays 0;
-    //  * in a diagonal tile the lower-left wave's block is the transpose of
-    //    the upper-right wave's (the same products in the same order), so
-    //    that wave forms no products and the upper-right wave writes both.
-    const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const bool mirror_wave = diag && (wv >> 1) == 1 && (wv & 1) == 0;
-    const bool actA[2] = {!mirror_wave && I0 + (wv >> 1) * 64 < pd.s, !mirror_wave && I0 + (wv >> 1) * 64 + 32 < pd.s};
-    const bool actB[2] = {J0 + (wv & 1) * 64 < pd.s, J0 + (wv & 1) * 64 + 32 < pd.s};
-    const bool all_active = actA[0] && actA[1] && actB[0] && actB[1];
-    const bool any_active = (actA[0] || actA[1]) && (actB[0] || actB[1]);
-    auto compute_full = [&](int buf) __attribute__((always_inline)) {
+    auto compute = [&](int buf) __attribute__((always_inline)) {
         const uint4 *Asb = lds(buf, 0);
         const uint4 *Bsb = lds(buf, 1);
         // interleave the LDS fragment reads with the MFMAs (3.5% faster FP32
@@ -679,30 +667,6 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 #pragma unroll
                 for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
         }
-    };
-    // edge tiles: only the blocks that reach into s
-    auto compute_part = [&](int buf) __attribute__((always_inline)) {
-        const uint4 *Asb = lds(buf, 0);
-        const uint4 *Bsb = lds(buf, 1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int w = kF32 ? kh * 4 + q : 2 * q + kh;
-            uint4 fa[2], fb[2];
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
-                fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
-            }
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-                for (int nn = 0; nn < 2; ++nn)
-                    if (actA[m] && actB[nn]) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
-        }
-    };
-    auto compute = [&](int buf) __attribute__((always_inline)) {
-        if (all_active) compute_full(buf);
-        else if (any_active) compute_part(buf);
     };
     GSP2_LD(0, 0);
     GSP2_ST(0, 0);
@@ -736,58 +700,54 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // the epilogue adds D O + O D + D^2 in FP32, (d_r + d_c) X_rc off the
     // diagonal and d_r^2 on it, so the diagonal is never rounded.
     constexpr bool kExactDiag = !kF32 && !kSplit;
-    // a diagonal tile's lower-left block is written by the upper-right wave
-    const bool write_mirror = !diag || ((wv >> 1) == 0 && (wv & 1) == 1);
     double tY = 0.0, tX = 0.0;
-    if (!mirror_wave) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
+    for (int m = 0; m < 2; ++m) {
 #pragma unroll
-            for (int nn = 0; nn < 2; ++nn) {
-                const int cg = J0 + wc * 64 + nn * 32 + l32;
-                const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
+        for (int nn = 0; nn < 2; ++nn) {
+            const int cg = J0 + wc * 64 + nn * 32 + l32;
+            const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
 #pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int rg0 = I0 + wr * 64 + m * 32 + g * 8 + kh * 4;
-                    float xn[4];
+            for (int g = 0; g < 4; ++g) {
+                const int rg0 = I0 + wr * 64 + m * 32 + g * 8 + kh * 4;
+                float xn[4];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int rg = rg0 + e;
-                        const float yacc = acc[m][nn][4 * g + e];
-                        const float xo = X[(int64_t)rg * ld + cg];
-                        float y = yacc;
-                        if constexpr (kExactDiag) {
-                            const float dr = X[(int64_t)rg * (ld + 1)];
-                            y = rg == cg ? yacc + dr * dr : yacc + (dr + dc) * xo;
-                        }
-                        const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
-                        xn[e] = v;
-                        Xn[(int64_t)rg * ld + cg] = v;
-                        if constexpr (!kF32) {
-                            const Op h = (kExactDiag && rg == cg) ? static_cast<Op>(0.0f) : static_cast<Op>(v);
-                            Xnop[(int64_t)rg * ld + cg] = h;
-                            if constexpr (kSplit)
-                                Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
-                        }
-                        if (diag && rg == cg && rg < pd.c) {
-                            tY += static_cast<double>(y);
-                            tX += static_cast<double>(v);
-                        }
+                for (int e = 0; e < 4; ++e) {
+                    const int rg = rg0 + e;
+                    const float yacc = acc[m][nn][4 * g + e];
+                    const float xo = X[(int64_t)rg * ld + cg];
+                    float y = yacc;
+                    if constexpr (kExactDiag) {
+                        const float dr = X[(int64_t)rg * (ld + 1)];
+                        y = rg == cg ? yacc + dr * dr : yacc + (dr + dc) * xo;
                     }
-                    if (write_mirror) {
-                        const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
-                        *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
-                        if constexpr (!kF32) {
-                            union { Op h[4]; uint2 u; } pk, pl;
+                    const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
+                    xn[e] = v;
+                    Xn[(int64_t)rg * ld + cg] = v;
+                    if constexpr (!kF32) {
+                        const Op h = (kExactDiag && rg == cg) ? static_cast<Op>(0.0f) : static_cast<Op>(v);
+                        Xnop[(int64_t)rg * ld + cg] = h;
+                        if constexpr (kSplit)
+                            Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
+                    }
+                    if (diag && rg == cg && rg < pd.c) {
+                        tY += static_cast<double>(y);
+                        tX += static_cast<double>(v);
+                    }
+                }
+                if (!diag) {
+                    const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
+                    *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
+                    if constexpr (!kF32) {
+                        union { Op h[4]; uint2 u; } pk, pl;
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
-                            *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
-                            if constexpr (kSplit) {
+                        for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
+                        *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
+                        if constexpr (kSplit) {
 #pragma unroll
-                                for (int e = 0; e < 4; ++e)
-                                    pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
-                                *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
-                            }
+                            for (int e = 0; e < 4; ++e)
+                                pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
+                            *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
                         }
                     }
                 }
