@@ -301,6 +301,31 @@ gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream);
 gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ,
                          const gsp2_run_options *run, void *P_val, gsp2_run_info *info);
 
+/*
+ * gsp2_density without allocation, for callers that cannot allocate device
+ * memory (code under HIP stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, arithmetic, kernels and results as
+ * gsp2_density; the per-run buffers (run state, per-system parameters, trace
+ * partials, Gershgorin discs and the iterates: 2 x sum_k s_pad_k^2 values of
+ * 4 bytes, 8 in FP64 runs, plus 16-bit operand copies in 16-bit runs) live in
+ * a static device array of 64 MiB that every GPU the library runs on holds
+ * until the process ends, instead of the plan's workspace.  The kernels are
+ * launched directly on the plan's stream (no HIP graph); the plan's own index
+ * lists and descriptors (built by gsp2_plan_create) are read as they are.
+ * The call makes no hipMalloc, hipFree or other allocation.  Nothing in the
+ * array needs clearing: every run writes each part of it before reading it.
+ * Every call on one GPU shares the array, which keeps the last call's
+ * contents: calls that overlap on one GPU (several streams, several plans,
+ * several threads) race, and must be ordered by the caller.
+ * gsp2_run_status and gsp2_run_timing keep describing the last gsp2_density
+ * run of the plan; pass info to see this call's outcome.
+ * Errors: as gsp2_density; GSP2_E_UNSUPPORTED when the run needs more than
+ * the static array holds (the message gives both sizes); GSP2_E_INVALID for
+ * run->timing = 1 (events would need allocation).
+ */
+gsp2_status gsp2_density_noalloc(gsp2_plan plan, const gsp2_csr *H, double n_occ,
+                                 const gsp2_run_options *run, void *P_val, gsp2_run_info *info);
+
 /* Wait for the last gsp2_density on this plan and report its device times,
  * measured with HIP events on the plan's stream.  Errors: GSP2_E_INVALID
  * when the last run was not timed. */

@@ -889,9 +889,9 @@ static gsp2_status collect(gsp2_plan_s *plan, const RunState *dev_state, gsp2_ru
     return run_status;
 }
 
-// Checks of one density-matrix call: the run parameters, and the
-// per-system parameters staged in the plan's pinned buffer for the upload
-// before the launch.
+// Checks of one density-matrix call shared by gsp2_density and
+// gsp2_density_noalloc: the run parameters, and the per-system parameters
+// staged in the plan's pinned buffer for the upload before the launch.
 static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ, const gsp2_run_options &o,
                              void *P_val) {
     if (!plan) fail(GSP2_E_INVALID, "null plan");
@@ -1038,6 +1038,74 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
     });
     if (st != GSP2_OK || !info) return st;
     return collect(plan, plan->dp.state, info);
+}
+
+gsp2_status gsp2_density_noalloc(gsp2_plan plan, const gsp2_csr *H, double n_occ, const gsp2_run_options *run,
+                                 void *P_val, gsp2_run_info *info) {
+    const RunState *dev_state = nullptr;
+    gsp2_status st = guarded([&] {
+        gsp2_run_options def;
+        gsp2_run_options_default(&def);
+        const gsp2_run_options &o = run ? *run : def;
+        if (o.timing) fail(GSP2_E_INVALID, "timing is not available without allocation (it needs events)");
+        const RunParams rp = prepare_run(plan, H, n_occ, o, P_val);
+        const bool wide16 = rp.precision == GSP2_PREC_FP16 || rp.precision == GSP2_PREC_BF16 ||
+                            rp.precision == GSP2_PREC_FP16X3;
+        // every per-run buffer of the plan, laid out in the static scratch
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            const size_t at = off;
+            off += (bytes + 255) & ~size_t(255);
+            return at;
+        };
+        const int32_t n_sys = plan->n_sys;
+        const size_t arena = (size_t)plan->arena_floats;
+        const size_t o_state = take(sizeof(RunState) * (size_t)n_sys);
+        const size_t o_sys = take(sizeof(SysParams) * (size_t)n_sys);
+        const size_t o_diag = take(sizeof(double) * 4 * (size_t)std::max(1, plan->n_diag));
+        const size_t o_x0 = take(sizeof(double) * (size_t)std::max(1, plan->dp.n_chunks));
+        const size_t o_rows = take(sizeof(double) * 3 * (size_t)plan->n);
+        const size_t elem = rp.precision == GSP2_PREC_FP64 ? sizeof(double) : sizeof(float);
+        const size_t o_x[2] = {take(elem * arena), take(elem * arena)};
+        size_t o_sh[2] = {0, 0}, o_lo[2] = {0, 0};
+        if (wide16) { o_sh[0] = take(2 * arena); o_sh[1] = take(2 * arena); }
+        if (rp.precision == GSP2_PREC_FP16X3) { o_lo[0] = take(2 * arena); o_lo[1] = take(2 * arena); }
+        if (off > kStaticScratchBytes)
+            fail(GSP2_E_UNSUPPORTED, "this run needs " + std::to_string(off) + " bytes of device scratch; the "
+                                     "static scratch of gsp2_density_noalloc holds " +
+                                     std::to_string(kStaticScratchBytes));
+        void *base = nullptr;
+        check_hip(static_scratch(&base), "static scratch address");
+        char *b = static_cast<char *>(base);
+        DevicePlan dp = plan->dp;
+        dp.state = reinterpret_cast<RunState *>(b + o_state);
+        dp.sys_params = reinterpret_cast<SysParams *>(b + o_sys);
+        dp.diag_partials = reinterpret_cast<double *>(b + o_diag);
+        dp.x0_partials = reinterpret_cast<double *>(b + o_x0);
+        dp.row_bounds = reinterpret_cast<double *>(b + o_rows);
+        dp.buf[0] = dp.buf[1] = nullptr;
+        dp.buf64[0] = dp.buf64[1] = nullptr;
+        dp.shadow[0] = dp.shadow[1] = dp.shadow_lo[0] = dp.shadow_lo[1] = nullptr;
+        dp.persist = nullptr;
+        for (int i = 0; i < 2; ++i) {
+            if (rp.precision == GSP2_PREC_FP64) dp.buf64[i] = reinterpret_cast<double *>(b + o_x[i]);
+            else dp.buf[i] = reinterpret_cast<float *>(b + o_x[i]);
+            if (wide16) dp.shadow[i] = b + o_sh[i];
+            if (rp.precision == GSP2_PREC_FP16X3) dp.shadow_lo[i] = b + o_lo[i];
+        }
+        // per-system parameters into the scratch, in stream order; the next
+        // call rewrites the pinned staging buffer only after this copy ends
+        check_hip(hipMemcpyAsync(dp.sys_params, plan->h_sys, sizeof(SysParams) * (size_t)n_sys,
+                                 hipMemcpyHostToDevice, plan->stream), "upload system parameters");
+        check_hip(hipEventRecord(plan->sys_uploaded, plan->stream), "parameter upload");
+        plan->sys_upload_pending = true;
+        Recorder rec;
+        rec.stream = plan->stream;
+        check_hip(launch_density(dp, *H, rp, P_val, rec, nullptr), "launch density");
+        dev_state = dp.state;
+    });
+    if (st != GSP2_OK || !info) return st;
+    return collect(plan, dev_state, info);
 }
 
 gsp2_status gsp2_run_status(gsp2_plan plan, gsp2_run_info *info) {

@@ -231,6 +231,11 @@ hipError_t probe_mfma(int precision, int n_iter, int n_blocks, float *out, hipSt
 // Workgroups of the persistent product kernel that the device keeps resident.
 hipError_t persistent_grid(int precision, int *grid);
 
+// Static device scratch of gsp2_density_noalloc (kernels.hip): its size, and
+// its address on the current device (looked up once per device).
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+hipError_t static_scratch(void **ptr);
+
 // Simulated-annealing refinement of a partition for eq. (4) (partition.cpp).
 struct AnnealResult {
     int64_t cost_before, cost_after;

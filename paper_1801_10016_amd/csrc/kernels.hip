@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
 #include <tuple>
 #include <utility>
 
@@ -2155,6 +2156,38 @@ hipError_t launch_density(const DevicePlan &dp, const gsp2_csr &H, const RunPara
                           Recorder &rec, const RunEvents *ev) {
     if (H.dtype == GSP2_F64) return density_typed<double>(dp, H, rp, P_val, rec, ev);
     return density_typed<float>(dp, H, rp, P_val, rec, ev);
+}
+
+// ---------------------------------------------------------------------------
+// Static device scratch of gsp2_density_noalloc: the per-run buffers of a
+// density matrix (run state, per-system parameters, trace partials,
+// Gershgorin discs and the iterates) live in this file-scope array instead
+// of memory the library allocates, for callers that cannot allocate.  Every
+// GPU the library runs on holds its own copy until the process ends.  In
+// host code the array's name is only a stand-in: its device address on the
+// current device comes from hipGetSymbolAddress, looked up once per device
+// and kept.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+hipError_t static_scratch(void **ptr) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace gsp2

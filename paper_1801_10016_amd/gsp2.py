@@ -100,6 +100,8 @@ SIGNATURES = {
     "gsp2_plan_set_stream": (C.c_int, [_PLAN, C.c_void_p]),
     "gsp2_density": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.c_double, C.POINTER(gsp2_run_options),
                                C.c_void_p, C.POINTER(gsp2_run_info)]),
+    "gsp2_density_noalloc": (C.c_int, [_PLAN, C.POINTER(gsp2_csr), C.c_double, C.POINTER(gsp2_run_options),
+                                       C.c_void_p, C.POINTER(gsp2_run_info)]),
     "gsp2_run_status": (C.c_int, [_PLAN, C.POINTER(gsp2_run_info)]),
     "gsp2_run_timing": (C.c_int, [_PLAN, C.POINTER(gsp2_timing)]),
     "gsp2_plan_destroy": (None, [_PLAN]),
@@ -439,6 +441,12 @@ def _density(entry: str, plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, al
 def gsp2_density(plan: Plan, H: DeviceCSR, n_occ, P_val, **kw):
     """gsp2_density: one density matrix into P_val (see _density)."""
     return _density("gsp2_density", plan, H, n_occ, P_val, **kw)
+
+
+def gsp2_density_noalloc(plan: Plan, H: DeviceCSR, n_occ, P_val, **kw):
+    """gsp2_density_noalloc: the same run with its buffers in the library's
+    static device scratch and no allocation (no timing option)."""
+    return _density("gsp2_density_noalloc", plan, H, n_occ, P_val, **kw)
 
 
 def gsp2_run_status(plan: Plan):
