@@ -74,7 +74,8 @@ def parse():
     ap.add_argument("--no-library-compare", action="store_true",
                     help="skip timing the same sub-matrix products with torch.matmul (rocBLAS / hipBLASLt)")
     ap.add_argument("--no-tune", action="store_true",
-                    help="skip the 16-bit tile autotuner (gsp2_plan_tune) and use 256 x 256 tiles")
+                    help="skip the kernel autotuner (gsp2_plan_tune) and use the default forms: 128 x 128 "
+                         "tiles for FP32 products, 256 x 256 for 16-bit ones")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM counter calibration)")
     ap.add_argument("--workload", choices=["water3500", "batch16", "backward1000"], default="water3500",
@@ -102,6 +103,15 @@ def dense_bootstrap(g, torch, Hd, n, n_occ, stream):
     col_ptr = torch.arange(0, n * n + 1, n, dtype=torch.int64, device="cuda")
     row_idx = torch.arange(n, dtype=torch.int32, device="cuda").repeat(n)
     return g.DeviceCSR(n, col_ptr, row_idx, P), run
+
+
+def kernel_name(precision, form):
+    """Name of the product kernel that runs `precision` in the tuner's `form`."""
+    if precision == "fp64":
+        return "k_sp2_step64"
+    if form == "t256" or (form == "auto" and precision != "fp32"):
+        return "k_sp2_wide"
+    return "k_sp2_step_skip" if form == "t128_skip" else "k_sp2_step"
 
 
 def counter_traffic(precision, workload, kernel=None):
@@ -322,17 +332,17 @@ def bench_batch(args, g, torch):
     P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
     sys_flops = [syrk_flops(sub_sizes[b.part_offs[i]:b.part_offs[i + 1]]) for i in range(len(b.steps))]
     tuning = None
-    if precision != "fp32" and not args.no_tune:
+    if not args.no_tune:
         with torch.cuda.stream(stream):
             tuning = g.gsp2_plan_tune(plan, Hd, 0.0, precision, n_products=6)
-        log(f"tile autotuner: {tuning}")
-    tile16 = tuning["tile16"] if tuning else 256
+        log(f"kernel autotuner: {tuning}")
+    form = tuning["chosen"] if tuning else "auto"
     with torch.cuda.stream(stream):
         first = g.gsp2_density(plan, Hd, b.n_occ, P_val, max_iter=args.max_iter, precision=precision, refine=refine)
     n_main = [r["n_products"] - r["n_refine"] for r in first]
     max_main = max(n_main)
     log(f"first run: main products per system {n_main}")
-    kw = dict(max_iter=max_main, precision=precision, refine=refine)
+    kw = dict(max_iter=max_main, precision=precision, refine=refine, kernel=form)
     with torch.cuda.stream(stream):
         for i in range(args.warmup):
             runs = g.gsp2_density(plan, Hd, b.n_occ, P_val, timing=True, **kw)
@@ -373,8 +383,8 @@ def bench_batch(args, g, torch):
         for i, st in enumerate(b.steps):
             Hs = g.csr_to_device(st.system.H)
             with torch.cuda.stream(stream):
-                with g.gsp2_plan_create(g.csr_to_device(st.P_prev), b.tau, st.part, st.n_parts, stream=stream,
-                                        tile16=tile16 if precision != "fp32" else 0) as p1:
+                with g.gsp2_plan_create(g.csr_to_device(st.P_prev), b.tau, st.part, st.n_parts,
+                                        stream=stream) as p1:
                     Pv = torch.empty(p1.nnz_P, dtype=torch.float32, device="cuda")
                     k1 = dict(kw, max_iter=n_main[i])
                     g.gsp2_density(p1, Hs, st.system.n_occ, Pv, **k1)
@@ -408,14 +418,13 @@ def bench_batch(args, g, torch):
         "aggregate_tflops_convention": "symmetric-product flops of every system in every launch it took part in "
                                        "/ summed product-kernel time",
         "roofline": {"bound": "mfma",
-                     "kernel": (f"k_sp2_wide<{precision}>" if precision != "fp32" and tile16 == 256
-                                else f"k_sp2_step<{precision}>"), "achieved": round(main_tf, 2),
+                     "kernel": f"{kernel_name(precision, form)}<{precision}>", "achieved": round(main_tf, 2),
                      "peak": peak_main, "unit": "TFLOP/s", "frac": round(main_tf / peak_main, 4), "traffic": None,
                      "refine_kernel_tflops": round(ref_flops / (ref_ms * 1e-3) / 1e12, 2) if ref_ms > 0 else None},
         "event_total_ms_median": round(statistics.median(totals), 3),
         "main_launches": max_main, "main_launch_ms": round(main_ms, 3), "refine_launch_ms": round(ref_ms, 3),
         "alone_total_ms": round(sum(alone_ms), 3) if alone_ms else None,
-        "tile16_tuning": tuning,
+        "kernel_tuning": tuning,
         "per_system": per_system,
         "plan_ms": round(plan_s * 1e3, 1),
         "workspace_gib": round(info["workspace_bytes"] / 2**30, 2),
@@ -566,8 +575,15 @@ def bench_water(args, g, torch):
             d = dict(z)
         np.savez(args.save_state, n_products=n_prod, **d)
         log(f"state saved to {args.save_state}")
+    # the kernel autotuner's form for the headline precision, timed on this plan
+    head_tune = None
+    if not args.no_tune and args.precision != "fp64":
+        with torch.cuda.stream(stream):
+            head_tune = g.gsp2_plan_tune(plan, Hd, n_occ, args.precision, n_products=6)
+        log(f"kernel autotuner: {head_tune}")
+    head_form = head_tune["chosen"] if head_tune else "auto"
     timed = not args.no_kernel_timing
-    kw = dict(max_iter=n_prod, precision=args.precision, timing=timed)
+    kw = dict(max_iter=n_prod, precision=args.precision, timing=timed, kernel=head_form)
     wall, timings, last = timed_runs(g, torch, plan, Hd, n_occ, P_val, args.steps, args.warmup, stream, **kw)
     assert last["status"] == 0 and last["n_products"] == n_prod, last
     ms_median = statistics.median(wall)
@@ -584,13 +600,13 @@ def bench_water(args, g, torch):
     fp32_err = None
     if stored is not None:
         with torch.cuda.stream(stream):
-            g.gsp2_density(plan, Hd, n_occ, P_val, alpha_seq=stored[0]["alphas"], trace_tol=1e9)
+            g.gsp2_density(plan, Hd, n_occ, P_val, alpha_seq=stored[0]["alphas"], trace_tol=1e9, kernel=head_form)
         fp32_err = oracle_sketch_errors(stored, P_val.cpu().numpy(), col_ptr, part)
         log(f"fp32 vs oracle: max {fp32_err['max']:.2e}")
 
     s = np.asarray(sub_sizes, dtype=np.float64)
     sym_flops = float(np.sum(s * s * (s + 1.0)))          # distinct entries s(s+1)/2, 2s flops each
-    product_kernel = {"fp32": "k_sp2_step", "fp64": "k_sp2_step64"}.get(args.precision, "k_sp2_wide")
+    product_kernel = kernel_name(args.precision, head_form)
     with torch.cuda.stream(stream):
         probe = {p: g.gsp2_probe_mfma(p, stream=stream)
                  for p in {"fp32", args.precision, *[q for q in args.compare_precisions.split(",") if q]}
@@ -608,7 +624,7 @@ def bench_water(args, g, torch):
         P_mp = torch.empty(info["nnz_P"], dtype=dt, device="cuda")
         tune_rec = None
         with torch.cuda.stream(stream):
-            if not args.no_tune and prec in ("fp16", "bf16", "fp16x3"):
+            if not args.no_tune and prec in ("fp32", "fp16", "bf16", "fp16x3"):
                 tune_rec = g.gsp2_plan_tune(plan, Hd, n_occ, prec, n_products=6)
             r0 = g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=args.max_iter, precision=prec, check=False)
         n_mp = r0["n_products"]
@@ -620,7 +636,7 @@ def bench_water(args, g, torch):
                "trace_minus_nocc": r0["trace"] - n_occ, "product_kernel_ms": round(avg, 4),
                "tflops": round(sym_flops / (avg * 1e-3) / 1e12, 2), "mfma_products_per_product": MFMA_PRODUCTS[prec],
                "frac_of_peak": round(hw / (avg * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[prec], 4),
-               "tile16_tuning": tune_rec}
+               "kernel": kernel_name(prec, tune_rec["chosen"] if tune_rec else "auto"), "kernel_tuning": tune_rec}
         if prec in probe:
             rec["frac_of_measured_peak"] = round(hw / (avg * 1e-3) / 1e12 / probe[prec], 4)
         if stored is not None:
@@ -712,6 +728,7 @@ def bench_water(args, g, torch):
                        "convention": "event time of the product launches (matrix products with their fused "
                                      "update and trace partials) against the rest of one P: Gershgorin, gather, "
                                      "branch decisions, scatter and launch gaps"},
+        "kernel_tuning": head_tune,
         "precision_compare": compare,
         "shape_matched": variant,
         "plan_ms": round(plan_s * 1e3, 1),
@@ -742,7 +759,7 @@ def shape_matched(args, g, torch, system, part, Hd, Pprev, stream, probe):
     for prec in ("fp32", "fp16"):
         tune = None
         with torch.cuda.stream(stream):
-            if prec != "fp32" and not args.no_tune:
+            if not args.no_tune:
                 tune = g.gsp2_plan_tune(plan, Hd, n_occ, prec, n_products=6)
             first = g.gsp2_density(plan, Hd, n_occ, P, max_iter=args.max_iter, precision=prec, check=False)
         if prec == "fp32":
@@ -756,7 +773,7 @@ def shape_matched(args, g, torch, system, part, Hd, Pprev, stream, probe):
                      "trace_minus_nocc": first["trace"] - n_occ, "product_kernel_ms": round(avg, 4),
                      "achieved_tflops": round(ach, 2), "frac": round(ach / PEAK_MFMA_TFLOPS[prec], 4),
                      "frac_of_measured_peak": round(ach / probe[prec], 4) if prec in probe else None,
-                     "tile16_tuning": tune}
+                     "kernel": kernel_name(prec, tune["chosen"] if tune else "auto"), "kernel_tuning": tune}
         log(f"tau={tau:g}: {prec} {out[prec]['ms_per_P']:.2f} ms/P, kernel {avg:.3f} ms, {ach:.1f} TFLOP/s")
     if not args.no_cpu_baseline:
         index = [g.gsp2_plan_part_index(plan, k) for k in range(args.n_parts)]

@@ -67,6 +67,25 @@ typedef enum {
                                   (v_mfma_f64_16x16x4_f64): the double-precision dgemm
                                   arithmetic of the paper's runs (Results); P is written in FP64 */
 } gsp2_precision;
+/* Forms of the product kernel; gsp2_plan_tune times them on a plan's own
+ * sub-problems and keeps the fastest per precision.  All forms of one
+ * precision give the same arithmetic.  T128 and T128_SKIP give the same bits
+ * for FP32, FP16 and BF16 operands; with split FP16 operands the formed
+ * quarter of a diagonal tile sums its two cross terms in the other order
+ * than the skipped quarter would, so the two agree to FP32 rounding (and
+ * T128_SKIP's iterates are exactly symmetric there, T128's to rounding). */
+typedef enum {
+    GSP2_KERNEL_AUTO = 0,      /* the form gsp2_plan_tune kept for the precision, else the default:
+                                  T128 for FP32 and FP64 products, T256 for 16-bit ones */
+    GSP2_KERNEL_T128 = 1,      /* 128 x 128 product tiles, two workgroups per CU, every 32 x 32
+                                  block of the padded tile formed */
+    GSP2_KERNEL_T128_SKIP = 2, /* 128 x 128 tiles; 32-row (column) blocks lying wholly in the zero
+                                  padding, and the lower-left quarter of a diagonal tile (the
+                                  transpose of the upper-right one), form no products.  Not for
+                                  FP64 products. */
+    GSP2_KERNEL_T256 = 3       /* 256 x 256 tiles, one workgroup per CU; 16-bit operands only */
+} gsp2_kernel;
+
 /* The 16-bit modes need every part's padded size (s_k rounded up to 128) to
  * be at most 46,336, so that a part's operand matrix is under 4 GiB; larger
  * plans get GSP2_E_UNSUPPORTED from gsp2_density for those modes. */
@@ -91,8 +110,9 @@ typedef struct {
                                   least one part: the system of every part.  Ignored (may be
                                   NULL) when n_systems <= 1. */
     int32_t tile16;            /* macro-tile edge of the 16-bit products: 0 = automatic (the
-                                  edge gsp2_plan_tune chose for the precision, else 256), 128
-                                  or 256 (fixed; gsp2_plan_tune does not override it) */
+                                  form gsp2_plan_tune kept for the precision, else 256 x 256
+                                  tiles), 128 or 256 (fixed: GSP2_KERNEL_T128 or T256, which
+                                  gsp2_plan_tune does not override; a run's `kernel` does) */
     int32_t reserved[3];
 } gsp2_plan_options;
 
@@ -147,7 +167,9 @@ typedef struct {
                                   part's core columns, which need not be symmetric; 1: every
                                   stored entry whose mirror is stored too becomes the mean of the
                                   two, and an entry whose mirror lies outside P's pattern is kept */
-    int32_t pad_;
+    int32_t kernel;            /* gsp2_kernel of the products, default GSP2_KERNEL_AUTO; anything
+                                  else overrides the plan's tile16 and the tuned form.  The FP32
+                                  refinement products use the FP32 form (tuned or default). */
 } gsp2_run_options;
 
 #define GSP2_MAX_ITER 100
@@ -382,33 +404,34 @@ gsp2_status gsp2_plan_graph(gsp2_plan plan, int64_t *adj_ptr, int32_t *adj_col);
 gsp2_status gsp2_probe_mfma(int32_t precision, void *stream, double *tflops);
 
 /* Result of gsp2_plan_tune. */
+#define GSP2_TUNE_MAX 4
 typedef struct {
-    int32_t precision;         /* the 16-bit gsp2_precision tuned */
-    int32_t tile16;            /* the macro-tile edge chosen: 128 or 256 */
-    double ms_128;             /* mean product time over the timed products, 128 x 128 tiles */
-    double ms_256;             /* the same with 256 x 256 tiles */
+    int32_t precision;         /* the gsp2_precision tuned */
+    int32_t chosen;            /* the gsp2_kernel kept */
+    int32_t n_candidates;      /* entries of candidate and ms */
     int32_t n_products;        /* products timed per candidate */
-    int32_t pad_;
+    int32_t candidate[GSP2_TUNE_MAX];   /* gsp2_kernel of each candidate, in the order timed */
+    double ms[GSP2_TUNE_MAX];           /* mean product time of each candidate */
 } gsp2_tune_info;
 
-/* Autotuner of the 16-bit product tile (the paper's products are dense
+/* Autotuner of the product kernel (the paper's products are dense
  * matrix-matrix sub-problems, Methods, eq. (4); their tiling is this
  * library's choice).  Times n_products products of the plan's own
- * sub-problems, built from H, with each candidate macro-tile edge (128 x 128
- * tiles, several workgroups per CU; 256 x 256 tiles, one workgroup per CU)
- * and keeps the edge with the lower mean product time for `precision`:
- * gsp2_density then uses it for that precision unless the plan was created
- * with a fixed tile16.  The products replay alternating branches (X^2,
- * 2X - X^2, ...), so every product carries the same work as in a run; the
- * trace check of those runs is not applied.  Runs on the plan's stream and
- * waits for it.
+ * sub-problems, built from H, with each candidate form: FP32 products
+ * GSP2_KERNEL_T128 and T128_SKIP; 16-bit products T128, T128_SKIP and T256.
+ * Keeps the form with the lowest mean product time for `precision`;
+ * gsp2_density then uses it for that precision unless the run names a form
+ * or (16-bit products) the plan was created with a fixed tile16.  The
+ * products replay alternating branches (X^2, 2X - X^2, ...), so every
+ * product carries the same work as in a run; the trace check of those runs
+ * is not applied.  Runs on the plan's stream and waits for it.
  *
  *  H           device CSR as for gsp2_density.
  *  n_occ       as for gsp2_density (batched plans: ignored).
- *  precision   GSP2_PREC_FP16, GSP2_PREC_BF16 or GSP2_PREC_FP16X3.
+ *  precision   GSP2_PREC_FP32, GSP2_PREC_FP16, GSP2_PREC_BF16 or GSP2_PREC_FP16X3.
  *  n_products  2..GSP2_MAX_ITER products per candidate (after one untimed run).
  *  info        nullable; filled with the timings and the choice.
- * Returns GSP2_E_INVALID for other precisions or a bad n_products; the
+ * Returns GSP2_E_INVALID for FP64 (one form only) or a bad n_products; the
  * plan's previous choice is kept on any error.  The library allocates and
  * frees a P-sized scratch output of its own. */
 gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int32_t precision,

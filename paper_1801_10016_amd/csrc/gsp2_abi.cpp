@@ -170,7 +170,7 @@ struct GraphKey {
 struct gsp2_plan_s {
     int32_t n = 0, n_parts = 0, tile = kTile;
     int32_t tile16_fixed = 0;             // plan option: 0 = tuned or default
-    int32_t tile16_tuned[4] = {0, 0, 0, 0};   // gsp2_plan_tune's choice per precision, 0 = none
+    int32_t kernel_tuned[5] = {0, 0, 0, 0, 0};   // gsp2_plan_tune's gsp2_kernel per precision, 0 = none
     int32_t n_sys = 1;
     std::vector<int32_t> part_system;     // system of every part
     std::vector<int32_t> sys_size;        // vertices of every system
@@ -288,6 +288,7 @@ gsp2_status gsp2_run_options_default(gsp2_run_options *opt) {
         opt->alpha_seq_system = nullptr;
         opt->n_alpha_system = nullptr;
         opt->symmetrize = 0;
+        opt->kernel = GSP2_KERNEL_AUTO;
     });
 }
 
@@ -426,13 +427,17 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         }
         plan->arena_floats = xoff;
         // Tile order.  A workgroup b of a launch runs on XCD b mod kXcds, so
-        // whole parts are dealt to XCDs by LPT on their product work, and each
-        // XCD's list walks its parts in kTileBlock x kTileBlock blocks of
-        // tiles: the workgroups resident on one XCD then share a few row and
-        // column panels in that XCD's L2.  Grid index b takes entry b / kXcds
-        // of XCD (b mod kXcds)'s list; short lists are padded with empty tiles.
+        // work is dealt to XCDs by LPT and each XCD's list walks its parts in
+        // kTileBlock x kTileBlock blocks of tiles: the workgroups resident on
+        // one XCD then share a few row and column panels in that XCD's L2.
+        // The unit dealt is a whole part, or, for a part holding more than
+        // half an XCD's share of the work (one dense block, a few large parts),
+        // each of its blocks, so that no XCD idles while one carries a large
+        // part.  Grid index b takes entry b / kXcds of XCD (b mod kXcds)'s
+        // list; short lists are padded with empty tiles.
         constexpr int kXcds = 8;
-        constexpr int kTileBlock = 8;
+        constexpr int kTileBlock = 8;                  // 128-tiles per block edge
+        constexpr int kBlockRows = kTileBlock * T;     // rows per block edge (4 256-tiles as well)
         std::vector<int32_t> order(n_parts);
         std::iota(order.begin(), order.end(), 0);
         auto work = [&](int32_t k) {
@@ -440,13 +445,42 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             return nt * (nt + 1) / 2 * plan->desc[k].s_pad;
         };
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work(a) > work(b); });
-        std::vector<double> load(kXcds, 0.0);
-        std::vector<std::vector<int32_t>> xcd_parts(kXcds);
-        for (int32_t k : order) {
-            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-            load[x] += work(k);
-            xcd_parts[x].push_back(k);
+        std::vector<int32_t> rank(n_parts);
+        double total_work = 0.0;
+        for (int32_t i = 0; i < n_parts; ++i) {
+            rank[order[i]] = i;
+            total_work += work(order[i]);
         }
+        struct Unit { int32_t k, bi, bj; double w; };   // bi < 0: the whole part
+        std::vector<Unit> units;
+        for (int32_t k : order) {
+            if (work(k) <= 0.5 * total_work / kXcds) {
+                units.push_back(Unit{k, -1, -1, work(k)});
+                continue;
+            }
+            const int nt = plan->desc[k].s_pad / T;
+            for (int bi = 0; bi < nt; bi += kTileBlock)
+                for (int bj = bi; bj < nt; bj += kTileBlock) {
+                    double tiles = 0.0;
+                    for (int ti = bi; ti < std::min(bi + kTileBlock, nt); ++ti)
+                        tiles += std::min(bj + kTileBlock, nt) - std::max(ti, bj);
+                    units.push_back(Unit{k, bi / kTileBlock, bj / kTileBlock, tiles * plan->desc[k].s_pad});
+                }
+        }
+        std::stable_sort(units.begin(), units.end(), [](const Unit &a, const Unit &b) { return a.w > b.w; });
+        std::vector<double> load(kXcds, 0.0);
+        std::vector<std::vector<Unit>> xcd_units(kXcds);
+        for (const Unit &u : units) {
+            const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[x] += u.w;
+            xcd_units[x].push_back(u);
+        }
+        // within an XCD: parts in LPT order, a split part's blocks row by row
+        for (auto &l : xcd_units)
+            std::stable_sort(l.begin(), l.end(), [&](const Unit &a, const Unit &b) {
+                if (rank[a.k] != rank[b.k]) return rank[a.k] < rank[b.k];
+                return a.bi != b.bi ? a.bi < b.bi : a.bj < b.bj;
+            });
         // Trace partials of the diagonal tiles: slots grouped by system, then
         // by part and tile row, so a system's traces are reduced in an order
         // that does not depend on the other systems of the batch.
@@ -462,37 +496,34 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             }
             sys_diag_ptr[y + 1] = slot;
         }
-        std::vector<std::vector<TileDesc>> lists(kXcds);
-        for (int x = 0; x < kXcds; ++x) {
-            for (int32_t k : xcd_parts[x]) {
-                const int nt = plan->desc[k].s_pad / T;
-                for (int bi = 0; bi < nt; bi += kTileBlock)
-                    for (int bj = bi; bj < nt; bj += kTileBlock)
-                        for (int ti = bi; ti < std::min(bi + kTileBlock, nt); ++ti)
-                            for (int tj = std::max(ti, bj); tj < std::min(bj + kTileBlock, nt); ++tj)
-                                lists[x].push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + ti : -1});
+        // the tiles of one unit at tile edge `edge` (blocks of kBlockRows / edge tiles)
+        auto unit_tiles = [&](const Unit &u, int edge, int diag_step, std::vector<TileDesc> &out) {
+            const int32_t k = u.k;
+            const int nt = (plan->desc[k].s_pad + edge - 1) / edge;
+            const int tb = kBlockRows / edge;
+            const int b_lo = u.bi < 0 ? 0 : u.bi, b_hi = u.bi < 0 ? (nt + tb - 1) / tb : u.bi + 1;
+            for (int BI = b_lo; BI < b_hi; ++BI) {
+                const int c_lo = u.bi < 0 ? BI : u.bj, c_hi = u.bi < 0 ? (nt + tb - 1) / tb : u.bj + 1;
+                for (int BJ = c_lo; BJ < c_hi; ++BJ)
+                    for (int ti = BI * tb; ti < std::min((BI + 1) * tb, nt); ++ti)
+                        for (int tj = std::max(ti, BJ * tb); tj < std::min((BJ + 1) * tb, nt); ++tj)
+                            out.push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + diag_step * ti : -1});
             }
-        }
+        };
+        std::vector<std::vector<TileDesc>> lists(kXcds);
+        for (int x = 0; x < kXcds; ++x)
+            for (const Unit &u : xcd_units[x]) unit_tiles(u, T, 1, lists[x]);
         size_t longest = 0;
         for (auto &l : lists) longest = std::max(longest, l.size());
         for (size_t q = 0; q < longest; ++q)
             for (int x = 0; x < kXcds; ++x)
                 plan->tiles.push_back(q < lists[x].size() ? lists[x][q] : TileDesc{-1, 0, 0, -1});
-        // The same order for the 256 x 256 tiles of the 16-bit products, in
+        // The same units for the 256 x 256 tiles of the 16-bit products, in
         // blocks of 4 x 4 (the same panels as 8 x 8 blocks of 128-tiles).  A
         // diagonal 256-tile covers 128-tile diagonal slots 2t and 2t + 1.
-        constexpr int kTileBlockW = 4;
         std::vector<std::vector<TileDesc>> lists_w(kXcds);
-        for (int x = 0; x < kXcds; ++x) {
-            for (int32_t k : xcd_parts[x]) {
-                const int nt = (plan->desc[k].s_pad + kTileWide - 1) / kTileWide;
-                for (int bi = 0; bi < nt; bi += kTileBlockW)
-                    for (int bj = bi; bj < nt; bj += kTileBlockW)
-                        for (int ti = bi; ti < std::min(bi + kTileBlockW, nt); ++ti)
-                            for (int tj = std::max(ti, bj); tj < std::min(bj + kTileBlockW, nt); ++tj)
-                                lists_w[x].push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + 2 * ti : -1});
-            }
-        }
+        for (int x = 0; x < kXcds; ++x)
+            for (const Unit &u : xcd_units[x]) unit_tiles(u, kTileWide, 2, lists_w[x]);
         longest = 0;
         for (auto &l : lists_w) longest = std::max(longest, l.size());
         for (size_t q = 0; q < longest; ++q)
@@ -728,8 +759,10 @@ gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int3
     float *scratch = nullptr;
     const gsp2_status st = guarded([&] {
         if (!plan || !H) fail(GSP2_E_INVALID, "null argument");
-        if (precision != GSP2_PREC_FP16 && precision != GSP2_PREC_BF16 && precision != GSP2_PREC_FP16X3)
-            fail(GSP2_E_INVALID, "gsp2_plan_tune takes a 16-bit precision");
+        const bool wide16 = precision == GSP2_PREC_FP16 || precision == GSP2_PREC_BF16 ||
+                            precision == GSP2_PREC_FP16X3;
+        if (precision != GSP2_PREC_FP32 && !wide16)
+            fail(GSP2_E_INVALID, "gsp2_plan_tune takes an FP32 or 16-bit precision");
         if (n_products < 2 || n_products > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_products out of range");
         int64_t nnz_p = 0;
         for (const auto &d : plan->desc) nnz_p += (int64_t)d.c * d.s;
@@ -746,30 +779,34 @@ gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int3
         o.timing = 1;
         o.precision = precision;
         if (plan->n_sys > 1) o.n_occ_system = occ.data();
-        const int32_t saved_fixed = plan->tile16_fixed;
-        double ms[2] = {0.0, 0.0};
-        const int32_t edge[2] = {kTile, kTileWide};
-        for (int c = 0; c < 2; ++c) {
-            plan->tile16_fixed = edge[c];
+        const int32_t cand[3] = {GSP2_KERNEL_T128, GSP2_KERNEL_T128_SKIP, GSP2_KERNEL_T256};
+        const int n_cand = wide16 ? 3 : 2;
+        double ms[3] = {0.0, 0.0, 0.0};
+        int best = 0;
+        for (int c = 0; c < n_cand; ++c) {
+            o.kernel = cand[c];
             gsp2_status r = GSP2_OK;
             for (int rep = 0; rep < 2 && r == GSP2_OK; ++rep)    // the first run builds the graph
                 r = gsp2_density(plan, H, n_occ, &o, scratch, nullptr);
             gsp2_timing t;
             if (r == GSP2_OK) r = gsp2_run_timing(plan, &t);
-            plan->tile16_fixed = saved_fixed;
             if (r != GSP2_OK) fail(r, std::string("tuning run: ") + g_last_error);
             double sum = 0.0;
             for (int i = 0; i < t.n_products; ++i) sum += t.product_ms[i];
             ms[c] = t.n_products > 0 ? sum / t.n_products : 0.0;
+            if (ms[c] < ms[best]) best = c;
         }
-        plan->tile16_tuned[precision] = ms[0] < ms[1] ? kTile : kTileWide;
+        plan->kernel_tuned[precision] = cand[best];
         if (info) {
+            std::memset(info, 0, sizeof(*info));
             info->precision = precision;
-            info->tile16 = plan->tile16_tuned[precision];
-            info->ms_128 = ms[0];
-            info->ms_256 = ms[1];
+            info->chosen = cand[best];
+            info->n_candidates = n_cand;
             info->n_products = n_products;
-            info->pad_ = 0;
+            for (int c = 0; c < n_cand; ++c) {
+                info->candidate[c] = cand[c];
+                info->ms[c] = ms[c];
+            }
         }
     });
     if (scratch) (void)hipFree(scratch);     // waits for the tuning runs
@@ -921,10 +958,26 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     rp.refine = o.refine;
     rp.persistent = o.persistent ? 1 : 0;
     rp.symmetrize = o.symmetrize;
-    rp.tile16 = 0;
-    if (wide16)
-        rp.tile16 = plan->tile16_fixed ? plan->tile16_fixed
-                    : plan->tile16_tuned[rp.precision] ? plan->tile16_tuned[rp.precision] : kTileWide;
+    // the product kernel's form: named by the run, else the plan's fixed
+    // 16-bit tile edge, else the tuned form, else the default
+    if (o.kernel < GSP2_KERNEL_AUTO || o.kernel > GSP2_KERNEL_T256) fail(GSP2_E_INVALID, "bad kernel");
+    if (o.kernel == GSP2_KERNEL_T256 && !wide16) fail(GSP2_E_INVALID, "256 x 256 tiles take 16-bit products only");
+    if (o.kernel == GSP2_KERNEL_T128_SKIP && o.precision == GSP2_PREC_FP64)
+        fail(GSP2_E_INVALID, "FP64 products have the one form GSP2_KERNEL_T128");
+    if (o.kernel != GSP2_KERNEL_AUTO)
+        rp.kernel = o.kernel;
+    else if (wide16 && plan->tile16_fixed)
+        rp.kernel = plan->tile16_fixed == kTile ? GSP2_KERNEL_T128 : GSP2_KERNEL_T256;
+    else if (plan->kernel_tuned[o.precision])
+        rp.kernel = plan->kernel_tuned[o.precision];
+    else
+        rp.kernel = wide16 ? GSP2_KERNEL_T256 : GSP2_KERNEL_T128;
+    if (o.precision == GSP2_PREC_FP32)
+        rp.kernel32 = rp.kernel;
+    else if (o.precision == GSP2_PREC_FP64)
+        rp.kernel32 = GSP2_KERNEL_T128;
+    else
+        rp.kernel32 = plan->kernel_tuned[GSP2_PREC_FP32] ? plan->kernel_tuned[GSP2_PREC_FP32] : GSP2_KERNEL_T128;
     if (rp.persistent && (n_sys > 1 || (rp.precision != GSP2_PREC_FP32 && rp.precision != GSP2_PREC_FP16 &&
                                          rp.precision != GSP2_PREC_BF16)))
         fail(GSP2_E_UNSUPPORTED, "the persistent product launch takes one system and FP32, FP16 or BF16 products");

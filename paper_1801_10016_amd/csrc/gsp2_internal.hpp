@@ -104,9 +104,12 @@ struct RunParams {
     int32_t precision;          // gsp2_precision of the main phase
     int32_t refine;             // FP32 products after the main phase
     int32_t persistent;         // 1: main-phase products in one persistent launch
-    int32_t tile16;             // 16-bit products: 256 (k_sp2_wide) or 128 (k_sp2_step) tiles
+    int32_t kernel;             // gsp2_kernel of the main-phase products (resolved, never AUTO)
+    int32_t kernel32;           // gsp2_kernel of the refinement products (T128 or T128_SKIP)
     int32_t symmetrize;         // scatter the mean of mirrored stored pairs
+    int32_t pad_;               // keeps the struct free of implicit padding (graph keys compare bytes)
 };
+static_assert(sizeof(RunParams) == 48, "RunParams layout");
 
 // Per-call parameters of one system, uploaded to the device before each run.
 struct SysParams {

@@ -555,7 +555,7 @@ __device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16
 // ---------------------------------------------------------------------------
 constexpr int kLdsWords = 2 * 2 * kTile * kLdsRow;  // [buffer][A/B][row * 9 + word]
 
-template <typename Op, bool kSplit = false>
+template <typename Op, bool kSplit = false, bool kSkip = false>
 __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, int cur, float alpha,
                                          float *__restrict__ buf0, float *__restrict__ buf1,
                                          Op *__restrict__ sh0, Op *__restrict__ sh1,
@@ -647,7 +647,21 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
         Bs_[0] = pb##S##0; Bs_[32 * kLdsRow] = pb##S##1;                                           \
         Bs_[64 * kLdsRow] = pb##S##2; Bs_[96 * kLdsRow] = pb##S##3;                                \
     } while (0)
-    auto compute = [&](int buf) __attribute__((always_inline)) {
+    // kSkip: work the matrix cores can leave out, exactly (wave-uniform):
+    //  * a 32-row (or 32-column) block that starts at or beyond s lies in the
+    //    zero padding, so its products are zero and its accumulator stays 0;
+    //  * in a diagonal tile the lower-left wave's block is the transpose of
+    //    the upper-right wave's (the same products in the same order), so
+    //    that wave forms no products and the upper-right wave writes both.
+    // The branch around the MFMAs costs time of its own; the tile autotuner
+    // picks the form per plan (it pays where padding is a large share).
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const bool mirror_wave = kSkip && diag && (wv >> 1) == 1 && (wv & 1) == 0;
+    const bool actA[2] = {!mirror_wave && I0 + (wv >> 1) * 64 < pd.s, !mirror_wave && I0 + (wv >> 1) * 64 + 32 < pd.s};
+    const bool actB[2] = {J0 + (wv & 1) * 64 < pd.s, J0 + (wv & 1) * 64 + 32 < pd.s};
+    const bool all_active = actA[0] && actA[1] && actB[0] && actB[1];
+    const bool any_active = (actA[0] || actA[1]) && (actB[0] || actB[1]);
+    auto compute_full = [&](int buf) __attribute__((always_inline)) {
         const uint4 *Asb = lds(buf, 0);
         const uint4 *Bsb = lds(buf, 1);
         // interleave the LDS fragment reads with the MFMAs (3.5% faster FP32
@@ -667,6 +681,34 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
             for (int m = 0; m < 2; ++m)
 #pragma unroll
                 for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
+        }
+    };
+    // edge tiles of the kSkip form: only the blocks that reach into s
+    auto compute_part = [&](int buf) __attribute__((always_inline)) {
+        const uint4 *Asb = lds(buf, 0);
+        const uint4 *Bsb = lds(buf, 1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int w = kF32 ? kh * 4 + q : 2 * q + kh;
+            uint4 fa[2], fb[2];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
+                fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
+            }
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int nn = 0; nn < 2; ++nn)
+                    if (actA[m] && actB[nn]) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
+        }
+    };
+    auto compute = [&](int buf) __attribute__((always_inline)) {
+        if constexpr (!kSkip) {
+            compute_full(buf);
+        } else {
+            if (all_active) compute_full(buf);
+            else if (any_active) compute_part(buf);
         }
     };
     GSP2_LD(0, 0);
@@ -701,11 +743,15 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // the epilogue adds D O + O D + D^2 in FP32, (d_r + d_c) X_rc off the
     // diagonal and d_r^2 on it, so the diagonal is never rounded.
     constexpr bool kExactDiag = !kF32 && !kSplit;
+    // the mirrored writes: every off-diagonal tile; in the kSkip form also
+    // the upper-right wave of a diagonal tile, for the lower-left one
+    const bool write_mirror = !diag || (kSkip && (wv >> 1) == 0 && (wv & 1) == 1);
     double tY = 0.0, tX = 0.0;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
 #pragma unroll
         for (int nn = 0; nn < 2; ++nn) {
+            if (mirror_wave) continue;
             const int cg = J0 + wc * 64 + nn * 32 + l32;
             const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
 #pragma unroll
@@ -736,7 +782,7 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
                         tX += static_cast<double>(v);
                     }
                 }
-                if (!diag) {
+                if (write_mirror) {
                     const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
                     *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
                     if constexpr (!kF32) {
@@ -764,7 +810,7 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     }
 }
 
-template <typename Op, bool kSplit = false>
+template <typename Op, bool kSplit = false, bool kSkip = false>
 __global__ __launch_bounds__(kBlock, 2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_sp2_step(const TileDesc *__restrict__ tiles,
                                                         const PartDesc *__restrict__ parts,
                                                         float *__restrict__ buf0, float *__restrict__ buf1,
@@ -778,8 +824,8 @@ __global__ __launch_bounds__(kBlock, 2) __attribute__((amdgpu_waves_per_eu(1, 2)
     const PartDesc pd = parts[td.part];
     const RunState *st = st_all + pd.sys;       // each system runs, stops and branches on its own
     if (st->done || st->phase != phase) return;
-    sp2_tile<Op, kSplit>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, diag_partials,
-                         lds, lo0, lo1);
+    sp2_tile<Op, kSplit, kSkip>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1,
+                                diag_partials, lds, lo0, lo1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1927,38 +1973,48 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     _Float16 *l16[2] = {static_cast<_Float16 *>(dp.shadow_lo[0]), static_cast<_Float16 *>(dp.shadow_lo[1])};
     __bf16 *b16[2] = {static_cast<__bf16 *>(dp.shadow[0]), static_cast<__bf16 *>(dp.shadow[1])};
     const dim3 grid_w(dp.n_tiles_w), blk_w(kBlockW);
-    // 16-bit products on 128 x 128 tiles (the tile autotuner's other candidate)
-    const bool narrow16 = mixed && rp.tile16 == kTile;
+    // the product kernel of form `form` with operands of `prec` (phase 0 or 1)
+    auto product = [&](int form, int prec, int phase) {
+        const bool skip = form == GSP2_KERNEL_T128_SKIP;
+        if (prec == GSP2_PREC_FP64) {
+            record(rec, k_sp2_step64, grid, blk, dp.tiles, dp.parts, dp.buf64[0], dp.buf64[1], dp.state,
+                   dp.diag_partials, phase);
+        } else if (prec == GSP2_PREC_FP32) {
+            auto k = skip ? k_sp2_step<float, false, true> : k_sp2_step<float, false, false>;
+            record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr, (float *)nullptr, dp.state,
+                   dp.diag_partials, phase, (float *)nullptr, (float *)nullptr);
+        } else if (form == GSP2_KERNEL_T256) {
+            if (prec == GSP2_PREC_FP16)
+                record(rec, k_sp2_wide<_Float16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0],
+                       h16[1], dp.state, dp.diag_partials, (_Float16 *)nullptr, (_Float16 *)nullptr);
+            else if (prec == GSP2_PREC_FP16X3)
+                record(rec, k_sp2_wide<_Float16, true>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0],
+                       h16[1], dp.state, dp.diag_partials, l16[0], l16[1]);
+            else
+                record(rec, k_sp2_wide<__bf16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, b16[0],
+                       b16[1], dp.state, dp.diag_partials, (__bf16 *)nullptr, (__bf16 *)nullptr);
+        } else if (prec == GSP2_PREC_FP16) {
+            auto k = skip ? k_sp2_step<_Float16, false, true> : k_sp2_step<_Float16, false, false>;
+            record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1], dp.state, dp.diag_partials,
+                   phase, (_Float16 *)nullptr, (_Float16 *)nullptr);
+        } else if (prec == GSP2_PREC_FP16X3) {
+            auto k = skip ? k_sp2_step<_Float16, true, true> : k_sp2_step<_Float16, true, false>;
+            record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1], dp.state, dp.diag_partials,
+                   phase, l16[0], l16[1]);
+        } else {
+            auto k = skip ? k_sp2_step<__bf16, false, true> : k_sp2_step<__bf16, false, false>;
+            record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, b16[0], b16[1], dp.state, dp.diag_partials,
+                   phase, (__bf16 *)nullptr, (__bf16 *)nullptr);
+        }
+    };
     for (int it = 0; it < (rp.persistent ? 0 : rp.n_steps); ++it) {
         if (ev) rec.add_event(ev->step[2 * it]);
-        if (narrow16 && rp.precision == GSP2_PREC_FP16)
-            record(rec, k_sp2_step<_Float16, false>, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1],
-                   dp.state, dp.diag_partials, 0, (_Float16 *)nullptr, (_Float16 *)nullptr);
-        else if (narrow16 && rp.precision == GSP2_PREC_FP16X3)
-            record(rec, k_sp2_step<_Float16, true>, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1],
-                   dp.state, dp.diag_partials, 0, l16[0], l16[1]);
-        else if (narrow16 && rp.precision == GSP2_PREC_BF16)
-            record(rec, k_sp2_step<__bf16, false>, grid, blk, dp.tiles, dp.parts, b0, b1, b16[0], b16[1],
-                   dp.state, dp.diag_partials, 0, (__bf16 *)nullptr, (__bf16 *)nullptr);
-        else if (rp.precision == GSP2_PREC_FP16)
-            record(rec, k_sp2_wide<_Float16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0], h16[1],
-                   dp.state, dp.diag_partials, (_Float16 *)nullptr, (_Float16 *)nullptr);
-        else if (rp.precision == GSP2_PREC_FP16X3)
-            record(rec, k_sp2_wide<_Float16, true>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0], h16[1],
-                   dp.state, dp.diag_partials, l16[0], l16[1]);
-        else if (rp.precision == GSP2_PREC_BF16)
-            record(rec, k_sp2_wide<__bf16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, b16[0], b16[1],
-                   dp.state, dp.diag_partials, (__bf16 *)nullptr, (__bf16 *)nullptr);
-        else if (f64)
-            record(rec, k_sp2_step64, grid, blk, dp.tiles, dp.parts, dp.buf64[0], dp.buf64[1], dp.state,
-                   dp.diag_partials, 0);
-        else
-            record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr,
-                   (float *)nullptr, dp.state, dp.diag_partials, 0, (float *)nullptr, (float *)nullptr);
+        product(rp.kernel, rp.precision, 0);
         if (ev) rec.add_event(ev->step[2 * it + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 0);
     }
-    if (!rp.persistent && rp.n_steps > 0 && mixed && !narrow16) {
+    // 16-bit products on 256 x 256 tiles leave the FP32 master incomplete
+    if (!rp.persistent && rp.n_steps > 0 && mixed && rp.kernel == GSP2_KERNEL_T256) {
         if (rp.precision == GSP2_PREC_FP16)
             record(rec, k_wide_fixup<_Float16, false>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
                    (const _Float16 *)nullptr, (const _Float16 *)nullptr, (const _Float16 *)nullptr,
@@ -1975,12 +2031,7 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     for (int r = 0; r < rp.refine; ++r) {
         const int slot = rp.n_steps + r;
         if (ev) rec.add_event(ev->step[2 * slot]);
-        if (f64)
-            record(rec, k_sp2_step64, grid, blk, dp.tiles, dp.parts, dp.buf64[0], dp.buf64[1], dp.state,
-                   dp.diag_partials, 1);
-        else
-            record(rec, k_sp2_step<float>, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr,
-                   (float *)nullptr, dp.state, dp.diag_partials, 1, (float *)nullptr, (float *)nullptr);
+        product(rp.kernel32, f64 ? GSP2_PREC_FP64 : GSP2_PREC_FP32, 1);
         if (ev) rec.add_event(ev->step[2 * slot + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 1);
     }

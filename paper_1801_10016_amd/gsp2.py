@@ -22,6 +22,11 @@ GSP2_PREC_FP32, GSP2_PREC_FP16, GSP2_PREC_BF16, GSP2_PREC_FP16X3, GSP2_PREC_FP64
 PRECISIONS = {"fp32": GSP2_PREC_FP32, "fp16": GSP2_PREC_FP16, "bf16": GSP2_PREC_BF16,
               "fp16x3": GSP2_PREC_FP16X3, "fp64": GSP2_PREC_FP64}
 GSP2_MAX_ITER = 100
+GSP2_KERNEL_AUTO, GSP2_KERNEL_T128, GSP2_KERNEL_T128_SKIP, GSP2_KERNEL_T256 = 0, 1, 2, 3
+KERNELS = {"auto": GSP2_KERNEL_AUTO, "t128": GSP2_KERNEL_T128, "t128_skip": GSP2_KERNEL_T128_SKIP,
+           "t256": GSP2_KERNEL_T256}
+KERNEL_NAMES = {v: k for k, v in KERNELS.items()}
+GSP2_TUNE_MAX = 4
 
 STATUS_NAMES = {0: "GSP2_OK", 1: "GSP2_E_INVALID", 2: "GSP2_E_HIP", 3: "GSP2_E_OOM",
                 4: "GSP2_E_NOT_CONVERGED", 5: "GSP2_E_WRONG_TRACE", 6: "GSP2_E_UNSUPPORTED"}
@@ -38,8 +43,9 @@ class gsp2_plan_options(C.Structure):
 
 
 class gsp2_tune_info(C.Structure):
-    _fields_ = [("precision", C.c_int32), ("tile16", C.c_int32), ("ms_128", C.c_double),
-                ("ms_256", C.c_double), ("n_products", C.c_int32), ("pad_", C.c_int32)]
+    _fields_ = [("precision", C.c_int32), ("chosen", C.c_int32), ("n_candidates", C.c_int32),
+                ("n_products", C.c_int32), ("candidate", C.c_int32 * GSP2_TUNE_MAX),
+                ("ms", C.c_double * GSP2_TUNE_MAX)]
 
 
 class gsp2_plan_info(C.Structure):
@@ -55,7 +61,7 @@ class gsp2_run_options(C.Structure):
                 ("timing", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
                 ("persistent", C.c_int32), ("n_occ_system", C.POINTER(C.c_double)),
                 ("alpha_seq_system", C.POINTER(C.c_int8)), ("n_alpha_system", C.POINTER(C.c_int32)),
-                ("symmetrize", C.c_int32), ("pad_", C.c_int32)]
+                ("symmetrize", C.c_int32), ("kernel", C.c_int32)]
 
 
 class gsp2_run_info(C.Structure):
@@ -232,7 +238,8 @@ class Plan:
 def gsp2_plan_create(P_prev: DeviceCSR, tau: float, part, n_parts: int, tile: int = 0, stream=None,
                      part_system=None, tile16: int = 0) -> Plan:
     """part_system (n_parts ids) batches independent systems in one plan;
-    tile16 fixes the 16-bit product tile edge (0: tuned, else 256)."""
+    tile16 fixes the 16-bit product tile edge (0: the tuned form, else 256
+    x 256 tiles)."""
     part = np.ascontiguousarray(part, dtype=np.int32)
     if part.shape != (P_prev.n,):
         raise ValueError("part must have one entry per vertex")
@@ -292,15 +299,15 @@ def gsp2_probe_mfma(precision: str, stream=None) -> float:
 
 
 def gsp2_plan_tune(plan: Plan, H: DeviceCSR, n_occ, precision: str, n_products: int = 8) -> dict:
-    """Time both 16-bit product tile edges on the plan's sub-problems and keep
-    the faster for `precision` (gsp2_plan_tune in gsp2.h).  Returns the
-    timings and the choice; json.dump of it is the tuning record."""
+    """Time every product-kernel form of `precision` on the plan's
+    sub-problems and keep the fastest (gsp2_plan_tune in gsp2.h).  Returns
+    the timings and the choice; json.dump of it is the tuning record."""
     info = gsp2_tune_info()
     c = H.as_c()
     _check(load().gsp2_plan_tune(plan.handle, C.byref(c), float(n_occ), PRECISIONS[precision], int(n_products),
                                  C.byref(info)))
-    return {"precision": precision, "tile16": info.tile16, "ms_per_product_128": info.ms_128,
-            "ms_per_product_256": info.ms_256, "n_products": info.n_products}
+    return {"precision": precision, "chosen": KERNEL_NAMES[info.chosen], "n_products": info.n_products,
+            "ms_per_product": {KERNEL_NAMES[info.candidate[i]]: info.ms[i] for i in range(info.n_candidates)}}
 
 
 def gsp2_plan_graph(plan: Plan):
@@ -348,11 +355,14 @@ def gsp2_plan_set_stream(plan: Plan, stream=None):
 
 
 def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5, timing=False,
-                     precision="fp32", refine=0, persistent=False, n_occ_system=None, symmetrize=False):
+                     precision="fp32", refine=0, persistent=False, n_occ_system=None, symmetrize=False,
+                     kernel="auto"):
     """Options struct and the arrays it points to (keep them alive for the
     call).  alpha_seq: one sequence, or (batched plans) a list of sequences,
-    one per system; n_occ_system: occupations of a batched plan's systems."""
+    one per system; n_occ_system: occupations of a batched plan's systems;
+    kernel: the product kernel's form ("auto", "t128", "t128_skip", "t256")."""
     o = gsp2_run_options_default()
+    o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.persistent = 1 if persistent else 0
     o.max_iter = int(max_iter)
     o.timing = 1 if timing else 0
@@ -403,7 +413,7 @@ def run_info_dict(info: gsp2_run_info) -> dict:
 
 def _density(entry: str, plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=None,
              stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False,
-             precision="fp32", refine=0, persistent=False, symmetrize=False):
+             precision="fp32", refine=0, persistent=False, symmetrize=False, kernel="auto"):
     """Enqueue one density matrix into P_val (torch on the GPU, nnz_P entries:
     float64 for precision "fp64", float32 otherwise).  With want_info the
     call waits and returns the run's info dict (a list of them, one per
@@ -421,7 +431,7 @@ def _density(entry: str, plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, al
         raise ValueError("a batched plan takes one n_occ per system")
     c = H.as_c()
     o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine, persistent,
-                               n_occ_system=n_occ if batched else None, symmetrize=symmetrize)
+                               n_occ_system=n_occ if batched else None, symmetrize=symmetrize, kernel=kernel)
     info = (gsp2_run_info * plan.n_systems)() if want_info else None
     st = getattr(load(), entry)(plan.handle, C.byref(c), 0.0 if batched else float(n_occ), C.byref(o),
                                 C.c_void_p(P_val.data_ptr()), info)

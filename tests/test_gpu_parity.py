@@ -217,8 +217,9 @@ def test_mixed_precision_trace_mode(precision):
 
 @pytest.mark.parametrize("precision", ["fp16", pytest.param("bf16", marks=BF16_MISSES), "fp16x3"])
 def test_16bit_products_on_128_tiles(precision):
-    # the tile autotuner's other candidate: 16-bit products on 128 x 128
-    # tiles meet the same bars as on 256 x 256 tiles, against the oracle
+    # the tile autotuner's other candidates: 16-bit products on 128 x 128
+    # tiles (every block formed, or padding and mirror blocks skipped) meet
+    # the same bars as on 256 x 256 tiles, against the oracle
     from tests._gpu import rel_fro, run_gsp2
     s = pins.water(200, 1)
     Pp = _dense_prev(s)
@@ -226,12 +227,47 @@ def test_16bit_products_on_128_tiles(precision):
     ref = oracle.gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ)
     bar = {"fp16": MIXED_TOL, "bf16": MIXED_TOL, "fp16x3": 1e-5}[precision]
     errs = {}
-    for tile16 in (128, 256):
-        P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, tile16=tile16)
+    for form in ("t128", "t128_skip", "t256"):
+        P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, kernel=form)
         assert run["status"] == 0 and np.isfinite(vals).all(), run
-        errs[tile16] = rel_fro(P, ref.csc())
-    print(f"{precision}: rel_err 128 tiles {errs[128]:.2e}, 256 tiles {errs[256]:.2e}", flush=True)
-    assert errs[128] <= bar and errs[256] <= bar
+        errs[form] = rel_fro(P, ref.csc())
+    print(f"{precision}: rel_err " + ", ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert max(errs.values()) <= bar
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16", "fp16x3"])
+@pytest.mark.parametrize("n_mol,seed,n_parts,tau", [(64, 0, 8, 1e-3), (200, 1, 6, 1e-4), (8, 0, 8, 1e-2)])
+def test_skip_form_gives_the_same_bits(precision, n_mol, seed, n_parts, tau):
+    # the skipped 32-row blocks lie wholly in the zero padding and the
+    # skipped diagonal-tile quarter is the transpose of a formed one, so the
+    # two 128-tile forms give the same P, branch sequence and traces bit for
+    # bit (8 molecules in 8 parts: 6-orbital cores padded to 128, where all
+    # but one 32-row block is padding).  Split FP16 is the exception: the
+    # formed quarter sums its two cross terms in the other order than the
+    # skipped one would, so the two forms agree to FP32 rounding.
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(n_mol, seed)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, n_parts, seed=0)
+    out = {}
+    for form in ("t128", "t128_skip"):
+        P, run, _, _, vals = run_gsp2(s.H, Pp, tau, part, n_parts, s.n_occ, precision=precision, kernel=form)
+        assert run["status"] == 0 and np.isfinite(vals).all(), run
+        out[form] = (vals, run)
+    v0, r0 = out["t128"]
+    v1, r1 = out["t128_skip"]
+    if precision == "fp16x3":
+        assert r0["alpha"] == r1["alpha"]
+        assert np.allclose(r0["traces"], r1["traces"], rtol=0.0, atol=1e-6 * s.n)
+        assert np.linalg.norm(v0 - v1) <= 1e-6 * np.linalg.norm(v0)
+    else:
+        assert r0["alpha"] == r1["alpha"] and r0["traces"] == r1["traces"]
+        assert np.array_equal(v0.view(np.uint32), v1.view(np.uint32))
+    if precision in ("fp32", "fp16x3"):
+        ref = oracle.gsp2(s.H, Pp, tau, part, n_parts, s.n_occ, alpha_seq=r1["alpha"])
+        err = rel_fro(P, ref.csc())
+        print(f"{precision} {n_mol} mol: skip form vs oracle {err:.2e}", flush=True)
+        assert err <= 1e-5
 
 
 @pytest.mark.parametrize("precision,published", [("fp32", 157.3), ("fp16", 2500.0), ("bf16", 2500.0)])
@@ -244,20 +280,42 @@ def test_mfma_probe_rate_is_plausible(precision, published):
     assert 0.6 * published < rate < 1.05 * published
 
 
-def test_tile_autotuner_choice_is_used():
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_tile_autotuner_choice_is_used(precision):
     from tests._gpu import rel_fro, run_gsp2
     s = pins.water(200, 1)
     Pp = _dense_prev(s)
     part = uneven_spatial_partition(s, 6, seed=0)
     ref = oracle.gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ)
-    P, run, _, _, _ = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision="fp16", tune="fp16")
+    P, run, _, _, _ = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, tune=precision)
     rec = run["tune"]
     print(f"tuner: {rec}", flush=True)
-    assert rec["tile16"] in (128, 256) and rec["n_products"] == 4
-    assert rec["ms_per_product_128"] > 0 and rec["ms_per_product_256"] > 0
-    faster = 128 if rec["ms_per_product_128"] < rec["ms_per_product_256"] else 256
-    assert rec["tile16"] == faster
-    assert run["status"] == 0 and rel_fro(P, ref.csc()) <= MIXED_TOL
+    want = {"fp32": {"t128", "t128_skip"}, "fp16": {"t128", "t128_skip", "t256"}}[precision]
+    assert set(rec["ms_per_product"]) == want and rec["n_products"] == 4
+    assert all(v > 0 for v in rec["ms_per_product"].values())
+    assert rec["chosen"] == min(rec["ms_per_product"], key=rec["ms_per_product"].get)
+    assert run["status"] == 0 and rel_fro(P, ref.csc()) <= (1e-5 if precision == "fp32" else MIXED_TOL)
+
+
+def test_kernel_form_is_checked():
+    # forms a precision does not have are refused before any work
+    import torch
+    import paper_1801_10016_amd as g
+    s = pins.water(16, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 2, seed=0)
+    Hd = g.csr_to_device(s.H)
+    with g.gsp2_plan_create(g.csr_to_device(sp.csr_matrix(Pp)), 1e-3, part, 2) as plan:
+        P32 = torch.empty(plan.nnz_P, dtype=torch.float32, device="cuda")
+        P64 = torch.empty(plan.nnz_P, dtype=torch.float64, device="cuda")
+        for prec, form, out in (("fp32", "t256", P32), ("fp64", "t128_skip", P64), ("fp64", "t256", P64),
+                                ("fp32", 7, P32)):
+            with pytest.raises(g.Gsp2Error) as e:
+                g.gsp2_density(plan, Hd, s.n_occ, out, precision=prec, kernel=form)
+            assert e.value.status == g.GSP2_E_INVALID
+        with pytest.raises(g.Gsp2Error) as e:
+            g.gsp2_plan_tune(plan, Hd, s.n_occ, "fp64", n_products=2)
+        assert e.value.status == g.GSP2_E_INVALID
 
 
 @pytest.mark.parametrize("n_mol,seed,n_parts,tau", [(64, 0, 8, 1e-5), (200, 1, 6, 1e-4)])
