@@ -642,10 +642,19 @@ def bench_water(args, g, torch):
         if stored is not None:
             with torch.cuda.stream(stream):
                 for refine in ((0, 2) if prec in ("fp16", "bf16") else (0,)):
+                    # the oracle's branch sequence replayed (every product of the oracle's run formed
+                    # with this precision's operands) ...
                     g.gsp2_density(plan, Hd, n_occ, P_mp, alpha_seq=stored[0]["alphas"], trace_tol=1e9,
                                    precision=prec, refine=refine)
                     rec[f"error_vs_oracle_refine{refine}"] = oracle_sketch_errors(
                         stored, P_mp.cpu().numpy(), col_ptr, part)["max"]
+                    # ... and the run's own branches and stop (at this precision's floor), against the
+                    # oracle's P
+                    r_t = g.gsp2_density(plan, Hd, n_occ, P_mp, precision=prec, refine=refine, check=False)
+                    rec[f"trace_mode_refine{refine}"] = {
+                        "error_vs_oracle": oracle_sketch_errors(stored, P_mp.cpu().numpy(), col_ptr, part)["max"],
+                        "n_products": r_t["n_products"], "status": r_t["status_name"],
+                        "trace_minus_nocc": r_t["trace"] - n_occ}
         compare[prec] = rec
         log(f"{prec}: {rec['ms_per_P']:.1f} ms/P, {n_mp} products, status {r0['status_name']}, "
             f"Tr P - N_occ = {rec['trace_minus_nocc']:.3e}" +

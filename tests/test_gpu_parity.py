@@ -301,6 +301,7 @@ def test_kernel_form_is_checked():
     # forms a precision does not have are refused before any work
     import torch
     import paper_1801_10016_amd as g
+    from paper_1801_10016_amd.gsp2 import GSP2_E_INVALID
     s = pins.water(16, 0)
     Pp = _dense_prev(s)
     part = uneven_spatial_partition(s, 2, seed=0)
@@ -312,10 +313,10 @@ def test_kernel_form_is_checked():
                                 ("fp32", 7, P32)):
             with pytest.raises(g.Gsp2Error) as e:
                 g.gsp2_density(plan, Hd, s.n_occ, out, precision=prec, kernel=form)
-            assert e.value.status == g.GSP2_E_INVALID
+            assert e.value.status == GSP2_E_INVALID
         with pytest.raises(g.Gsp2Error) as e:
             g.gsp2_plan_tune(plan, Hd, s.n_occ, "fp64", n_products=2)
-        assert e.value.status == g.GSP2_E_INVALID
+        assert e.value.status == GSP2_E_INVALID
 
 
 @pytest.mark.parametrize("n_mol,seed,n_parts,tau", [(64, 0, 8, 1e-5), (200, 1, 6, 1e-4)])
