@@ -968,7 +968,7 @@ __device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd,
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_sp2_step64(const TileDesc *__restrict__ tiles,
+__global__ __launch_bounds__(kBlock, 2) void k_sp2_step64(const TileDesc *__restrict__ tiles,
                                                        const PartDesc *__restrict__ parts,
                                                        double *__restrict__ buf0, double *__restrict__ buf1,
                                                        const RunState *__restrict__ st_all,

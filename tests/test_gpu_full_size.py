@@ -186,14 +186,32 @@ def test_fp16_trace_mode_full_size(case):
 
 
 @pytest.mark.xfail(strict=True, raises=AssertionError,
-                   reason="BF16 products miss the 1e-3 bar at full size (6.4e-3 to 7.1e-3 measured with the "
-                          "diagonal rounded; the subspace rotation of 2^-8 rounding accumulates over the run)")
+                   reason="BF16 products miss the 1e-3 bar at full size (2.4e-3 measured with the oracle's "
+                          "sequence replayed; the subspace rotation left by 2^-8 rounding is not undone)")
 def test_bf16_error_vs_oracle(case):
     gold = case["gold"]
     run, vals = _run(case, precision="bf16", alpha_seq=gold["alphas"], trace_tol=1e9)
     errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
     print(f"bf16: parts sketch rel_err max {errs.max():.2e} median {np.median(errs):.2e}", flush=True)
     assert np.isfinite(vals).all() and errs.max() <= MIXED_TOL
+
+
+@pytest.mark.parametrize("refine", [0, 2])
+@pytest.mark.xfail(strict=True, raises=AssertionError,
+                   reason="BF16 in trace mode misses the 1e-3 bar at full size (1.8e-3, and 1.3e-3 with two FP32 "
+                          "refinement products, measured)")
+def test_bf16_trace_mode_full_size(case, refine):
+    """BF16 products in trace mode: the run stops at its own floor (before the
+    late products, where BF16 rounding costs most), passes the occupation
+    check, and is compared with the oracle's P on every part."""
+    gold = case["gold"]
+    run, vals = _run(case, precision="bf16", refine=refine, check=False)
+    errs = _full.part_errors(gold, case["arrays"], vals, case["col_ptr"], case["part"])
+    print(f"bf16 trace mode refine={refine}: status {run['status_name']}, {run['n_products']} products, "
+          f"Tr P - N_occ = {run['trace'] - case['s'].n_occ:.3e}, parts sketch rel_err max {errs.max():.2e}",
+          flush=True)
+    assert run["status"] == 0 and abs(run["trace"] - case["s"].n_occ) <= 0.5
+    assert errs.max() <= MIXED_TOL
 
 
 def test_split_fp16_full_size(case):
