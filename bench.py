@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the kernel autotuner (gsp2_plan_tune) and use the default forms: 128 x 128 "
                          "tiles for FP32 products, 256 x 256 for 16-bit ones")
+    ap.add_argument("--kernel", choices=["auto", "t128", "t128_skip", "t256"], default="auto",
+                    help="product-kernel form of the headline precision when the autotuner is skipped "
+                         "(--no-tune); auto = the library's default form")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device copy of this many GiB (HBM counter calibration)")
     ap.add_argument("--workload", choices=["water3500", "batch16", "backward1000"], default="water3500",
@@ -581,7 +584,7 @@ def bench_water(args, g, torch):
         with torch.cuda.stream(stream):
             head_tune = g.gsp2_plan_tune(plan, Hd, n_occ, args.precision, n_products=6)
         log(f"kernel autotuner: {head_tune}")
-    head_form = head_tune["chosen"] if head_tune else "auto"
+    head_form = head_tune["chosen"] if head_tune else args.kernel
     timed = not args.no_kernel_timing
     kw = dict(max_iter=n_prod, precision=args.precision, timing=timed, kernel=head_form)
     wall, timings, last = timed_runs(g, torch, plan, Hd, n_occ, P_val, args.steps, args.warmup, stream, **kw)
