@@ -558,7 +558,8 @@ def bench_water(args, g, torch):
         f"graph {nnz_sym} entries sha256 {digest[:16]}")
     stored = stored_oracle(args, digest) if saved is None else None
     log("stored oracle sketches: " + ("used (the benched graph is the oracle's)" if stored else "not applicable"))
-    P_val = torch.empty(info["nnz_P"], dtype=torch.float32, device="cuda")
+    P_val = torch.empty(info["nnz_P"], dtype=torch.float64 if args.precision == "fp64" else torch.float32,
+                        device="cuda")
     col_ptr, _ = g.gsp2_plan_pattern(plan)
 
     # the first run finds where the stop rule fires; later runs form exactly
@@ -600,12 +601,13 @@ def bench_water(args, g, torch):
     else:
         product_ms, setup, scatter, totals = [float("nan")], [float("nan")], [float("nan")], [float("nan")]
         sp2 = wall
-    fp32_err = None
-    if stored is not None:
+    head_err = None
+    if stored is not None and args.precision != "fp64":
         with torch.cuda.stream(stream):
-            g.gsp2_density(plan, Hd, n_occ, P_val, alpha_seq=stored[0]["alphas"], trace_tol=1e9, kernel=head_form)
-        fp32_err = oracle_sketch_errors(stored, P_val.cpu().numpy(), col_ptr, part)
-        log(f"fp32 vs oracle: max {fp32_err['max']:.2e}")
+            g.gsp2_density(plan, Hd, n_occ, P_val, alpha_seq=stored[0]["alphas"], trace_tol=1e9, kernel=head_form,
+                           precision=args.precision)
+        head_err = oracle_sketch_errors(stored, P_val.cpu().numpy(), col_ptr, part)
+        log(f"{args.precision} vs oracle: max {head_err['max']:.2e}")
 
     s = np.asarray(sub_sizes, dtype=np.float64)
     sym_flops = float(np.sum(s * s * (s + 1.0)))          # distinct entries s(s+1)/2, 2s flops each
@@ -711,7 +713,7 @@ def bench_water(args, g, torch):
             "sum_s3": info["sum_s3"], "n_products": n_prod, "tiles_per_product": info["n_tiles"],
             "precision": f"{args.precision.upper()} MFMA operands, FP32 accumulation and iterate, FP64 traces",
         },
-        "error_vs_oracle": fp32_err,
+        "error_vs_oracle": head_err,
         "gemm_convention_rate": {
             "value": round(n_prod * float(np.sum(2.0 * s ** 3)) / (sp2_med * 1e-3) / 1e12, 2),
             "convention": ("n_products * sum_k 2 s_k^3 / SP2-phase time, in 1e12 per second: the flop count of "
