@@ -86,7 +86,9 @@ def parse():
                     "500-8,000 molecules, each one MD step on, in one batched plan; backward1000: forward "
                     "and reverse mode on 1,000 molecules, 32 parts, tau = 1e-3")
     ap.add_argument("--refine", type=int, default=None,
-                    help="FP32 refinement products after the stop (default: 0, or 2 for batch16)")
+                    help="refinement products after the stop (default: 0, or 2 for batch16)")
+    ap.add_argument("--refine-precision", choices=["fp32", "fp16x3"], default="fp32",
+                    help="operands of the refinement products (fp16x3: split FP16, after 16-bit products only)")
     ap.add_argument("--no-alone", action="store_true", help="batch16: skip timing each system in a plan of its own")
     return ap.parse_args()
 
@@ -341,11 +343,13 @@ def bench_batch(args, g, torch):
         log(f"kernel autotuner: {tuning}")
     form = tuning["chosen"] if tuning else "auto"
     with torch.cuda.stream(stream):
-        first = g.gsp2_density(plan, Hd, b.n_occ, P_val, max_iter=args.max_iter, precision=precision, refine=refine)
+        first = g.gsp2_density(plan, Hd, b.n_occ, P_val, max_iter=args.max_iter, precision=precision, refine=refine,
+                               refine_precision=args.refine_precision)
     n_main = [r["n_products"] - r["n_refine"] for r in first]
     max_main = max(n_main)
     log(f"first run: main products per system {n_main}")
-    kw = dict(max_iter=max_main, precision=precision, refine=refine, kernel=form)
+    kw = dict(max_iter=max_main, precision=precision, refine=refine, kernel=form,
+              refine_precision=args.refine_precision)
     with torch.cuda.stream(stream):
         for i in range(args.warmup):
             runs = g.gsp2_density(plan, Hd, b.n_occ, P_val, timing=True, **kw)
@@ -412,10 +416,11 @@ def bench_batch(args, g, torch):
             "workload": (f"{len(b.steps)} independent water systems of {min(s_.system.n_mol for s_ in b.steps)}-"
                          f"{max(s_.system.n_mol for s_ in b.steps)} molecules ({b.H.shape[0]} orbitals, "
                          f"{b.n_parts} parts), 0.05 A displacements, repartitioned, tau={b.tau:g}, "
-                         f"{precision.upper()} products + {refine} FP32 refinement products"),
+                         f"{precision.upper()} products + {refine} "
+                         f"{'split-FP16' if args.refine_precision == 'fp16x3' else 'FP32'} refinement products"),
             "n_systems": len(b.steps), "n_orbitals": b.H.shape[0], "n_parts": b.n_parts, "tau": b.tau,
             "s_min": info["min_s"], "s_max": info["max_s"], "tiles_per_product": info["n_tiles"],
-            "precision": precision, "refine": refine,
+            "precision": precision, "refine": refine, "refine_precision": args.refine_precision,
         },
         "aggregate_tflops": round(total_flops / (float(np.sum(per_launch)) * 1e-3) / 1e12, 2),
         "aggregate_tflops_convention": "symmetric-product flops of every system in every launch it took part in "
@@ -660,6 +665,19 @@ def bench_water(args, g, torch):
                         "error_vs_oracle": oracle_sketch_errors(stored, P_mp.cpu().numpy(), col_ptr, part)["max"],
                         "n_products": r_t["n_products"], "status": r_t["status_name"],
                         "trace_minus_nocc": r_t["trace"] - n_occ}
+        if prec in ("fp16", "bf16"):
+            # the whole P with two refinement products, FP32 or split FP16, timed like the main line
+            rec["with_refinement"] = {}
+            for rp in ("fp32", "fp16x3"):
+                kw_r = dict(max_iter=n_mp, precision=prec, refine=2, refine_precision=rp)
+                w_r, _, last_r = timed_runs(g, torch, plan, Hd, n_occ, P_mp, args.compare_steps, 1, stream, **kw_r)
+                e_r = (oracle_sketch_errors(stored, P_mp.cpu().numpy(), col_ptr, part)["max"]
+                       if stored is not None else None)
+                rec["with_refinement"][rp] = {"ms_per_P": round(statistics.median(w_r), 3),
+                                              "n_products": last_r["n_products"], "status": last_r["status_name"],
+                                              "error_vs_oracle": e_r, "trace_minus_nocc": last_r["trace"] - n_occ}
+                log(f"{prec} + 2 {rp} refinement products: {statistics.median(w_r):.1f} ms/P" +
+                    (f", error vs oracle {e_r:.2e}" if e_r is not None else ""))
         compare[prec] = rec
         log(f"{prec}: {rec['ms_per_P']:.1f} ms/P, {n_mp} products, status {r0['status_name']}, "
             f"Tr P - N_occ = {rec['trace_minus_nocc']:.3e}" +

@@ -150,7 +150,8 @@ typedef struct {
     int32_t timing;            /* 1 = record HIP events around every phase and product
                                   (read with gsp2_run_timing); default 0 */
     int32_t precision;         /* gsp2_precision of the products, default GSP2_PREC_FP32 */
-    int32_t refine;            /* FP32 products (FP64 products in GSP2_PREC_FP64 runs) appended
+    int32_t refine;            /* refinement products (FP32, split FP16 with refine_precision, FP64
+                                  in GSP2_PREC_FP64 runs) appended
                                   after the stop, alternating X^2 and 2X - X^2, 0..8, default 0;
                                   max_iter + refine <= GSP2_MAX_ITER */
     int32_t persistent;        /* must be 0 (one launch per product, all in one HIP graph).
@@ -170,6 +171,12 @@ typedef struct {
     int32_t kernel;            /* gsp2_kernel of the products, default GSP2_KERNEL_AUTO; anything
                                   else overrides the plan's tile16 and the tuned form.  The FP32
                                   refinement products use the FP32 form (tuned or default). */
+    int32_t refine_precision;  /* operands of the refinement products: GSP2_PREC_FP32 (default) or,
+                                  after 16-bit products (FP16 or BF16), GSP2_PREC_FP16X3: split FP16
+                                  products on 256 x 256 tiles, about as accurate as FP32 ones at a
+                                  third of their time; the iterate is split into its two FP16
+                                  parts once, when the main phase ends */
+    int32_t pad2_;
 } gsp2_run_options;
 
 #define GSP2_MAX_ITER 100
@@ -180,7 +187,7 @@ typedef struct {
     int32_t n_products;        /* products formed, including a discarded last one */
     int32_t n_alpha;           /* branches applied to reach the returned P */
     int32_t result_iterate;    /* index t of the returned iterate X_t */
-    int32_t n_refine;          /* FP32 refinement products among n_products */
+    int32_t n_refine;          /* refinement products among n_products */
     int32_t precision;         /* gsp2_precision of the run */
     double eps_min, eps_max;   /* Gershgorin bounds of H */
     double trace;              /* summed core trace of the returned P */

@@ -289,6 +289,8 @@ gsp2_status gsp2_run_options_default(gsp2_run_options *opt) {
         opt->n_alpha_system = nullptr;
         opt->symmetrize = 0;
         opt->kernel = GSP2_KERNEL_AUTO;
+        opt->refine_precision = GSP2_PREC_FP32;
+        opt->pad2_ = 0;
     });
 }
 
@@ -972,6 +974,14 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
         rp.kernel = plan->kernel_tuned[o.precision];
     else
         rp.kernel = wide16 ? GSP2_KERNEL_T256 : GSP2_KERNEL_T128;
+    rp.refine_prec = o.precision == GSP2_PREC_FP64 ? GSP2_PREC_FP64 : GSP2_PREC_FP32;
+    if (o.refine_precision == GSP2_PREC_FP16X3) {
+        if (o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16)
+            fail(GSP2_E_INVALID, "split FP16 refinement products follow FP16 or BF16 products only");
+        rp.refine_prec = GSP2_PREC_FP16X3;
+    } else if (o.refine_precision != GSP2_PREC_FP32) {
+        fail(GSP2_E_INVALID, "refine_precision must be GSP2_PREC_FP32 or GSP2_PREC_FP16X3");
+    }
     if (o.precision == GSP2_PREC_FP32)
         rp.kernel32 = rp.kernel;
     else if (o.precision == GSP2_PREC_FP64)
@@ -1055,7 +1065,8 @@ gsp2_status gsp2_density(gsp2_plan plan, const gsp2_csr *H, double n_occ, const 
             plan->dp.shadow[0] = plan->alloc<uint16_t>(plan->arena_floats, "16-bit X copy 0");
             plan->dp.shadow[1] = plan->alloc<uint16_t>(plan->arena_floats, "16-bit X copy 1");
         }
-        if (rp.precision == GSP2_PREC_FP16X3 && !plan->dp.shadow_lo[0]) {
+        const bool split_any = rp.precision == GSP2_PREC_FP16X3 || (rp.refine > 0 && rp.refine_prec == GSP2_PREC_FP16X3);
+        if (split_any && !plan->dp.shadow_lo[0]) {
             plan->dp.shadow_lo[0] = plan->alloc<uint16_t>(plan->arena_floats, "FP16 low parts 0");
             plan->dp.shadow_lo[1] = plan->alloc<uint16_t>(plan->arena_floats, "FP16 low parts 1");
         }
@@ -1122,7 +1133,8 @@ gsp2_status gsp2_density_noalloc(gsp2_plan plan, const gsp2_csr *H, double n_occ
         const size_t o_x[2] = {take(elem * arena), take(elem * arena)};
         size_t o_sh[2] = {0, 0}, o_lo[2] = {0, 0};
         if (wide16) { o_sh[0] = take(2 * arena); o_sh[1] = take(2 * arena); }
-        if (rp.precision == GSP2_PREC_FP16X3) { o_lo[0] = take(2 * arena); o_lo[1] = take(2 * arena); }
+        const bool split_any = rp.precision == GSP2_PREC_FP16X3 || (rp.refine > 0 && rp.refine_prec == GSP2_PREC_FP16X3);
+        if (split_any) { o_lo[0] = take(2 * arena); o_lo[1] = take(2 * arena); }
         if (off > kStaticScratchBytes)
             fail(GSP2_E_UNSUPPORTED, "this run needs " + std::to_string(off) + " bytes of device scratch; the "
                                      "static scratch of gsp2_density_noalloc holds " +
@@ -1144,7 +1156,7 @@ gsp2_status gsp2_density_noalloc(gsp2_plan plan, const gsp2_csr *H, double n_occ
             if (rp.precision == GSP2_PREC_FP64) dp.buf64[i] = reinterpret_cast<double *>(b + o_x[i]);
             else dp.buf[i] = reinterpret_cast<float *>(b + o_x[i]);
             if (wide16) dp.shadow[i] = b + o_sh[i];
-            if (rp.precision == GSP2_PREC_FP16X3) dp.shadow_lo[i] = b + o_lo[i];
+            if (split_any) dp.shadow_lo[i] = b + o_lo[i];
         }
         // per-system parameters into the scratch, in stream order; the next
         // call rewrites the pinned staging buffer only after this copy ends

@@ -107,9 +107,9 @@ struct RunParams {
     int32_t kernel;             // gsp2_kernel of the main-phase products (resolved, never AUTO)
     int32_t kernel32;           // gsp2_kernel of the refinement products (T128 or T128_SKIP)
     int32_t symmetrize;         // scatter the mean of mirrored stored pairs
-    int32_t pad_;               // keeps the struct free of implicit padding (graph keys compare bytes)
+    int32_t refine_prec;        // gsp2_precision of the refinement products (FP32, FP16X3 or FP64)
 };
-static_assert(sizeof(RunParams) == 48, "RunParams layout");
+static_assert(sizeof(RunParams) == 48, "RunParams layout (no implicit padding: graph keys compare bytes)");
 
 // Per-call parameters of one system, uploaded to the device before each run.
 struct SysParams {

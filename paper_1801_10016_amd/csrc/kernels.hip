@@ -1394,13 +1394,13 @@ __global__ __launch_bounds__(kBlockW, 1) void k_sp2_wide(const TileDesc *__restr
                                                          Op *__restrict__ sh0, Op *__restrict__ sh1,
                                                          const RunState *__restrict__ st_all,
                                                          double *__restrict__ diag_partials,
-                                                         Op *__restrict__ lo0, Op *__restrict__ lo1) {
+                                                         Op *__restrict__ lo0, Op *__restrict__ lo1, int phase) {
     __shared__ uint4 lds_w[kLdsWordsW];
     const TileDesc td = tiles[blockIdx.x];
     if (td.part < 0) return;
     const PartDesc pd = parts[td.part];
     const RunState *st = st_all + pd.sys;
-    if (st->done || st->phase != 0) return;
+    if (st->done || st->phase != phase) return;
     sp2_tile_wide<Op, kSplit>(td, pd, st->cur, static_cast<float>(st->alpha), buf0, buf1, sh0, sh1, lo0, lo1,
                               diag_partials, lds_w);
 }
@@ -1418,11 +1418,13 @@ __global__ __launch_bounds__(kBlock) void k_wide_fixup(const PartDesc *__restric
                                                        float *__restrict__ buf0, float *__restrict__ buf1,
                                                        const Op *__restrict__ hi0, const Op *__restrict__ hi1,
                                                        const Op *__restrict__ lo0, const Op *__restrict__ lo1,
-                                                       const RunState *__restrict__ st_all) {
+                                                       const RunState *__restrict__ st_all, int after_refine) {
     const RowChunk ch = chunks[blockIdx.x];
     const PartDesc pd = parts[ch.part];
     const RunState *st = st_all + pd.sys;
     if (st->status == GSP2_E_INVALID || st->status == GSP2_E_HIP) return;
+    // after split refinement products: only the systems that formed them
+    if (after_refine && st->n_refine == 0) return;
     const int b = st->phase == 1 ? st->cur : st->result_buf;
     float *X = (b ? buf1 : buf0) + pd.x_off;
     const int ld = pd.s_pad;
@@ -1456,6 +1458,46 @@ __global__ __launch_bounds__(kBlock) void k_wide_fixup(const PartDesc *__restric
 #pragma unroll
             for (int i = 0; i < kRows; ++i)
                 if (ch.r0 + i < ch.r1 && c > ch.r0 + i) X[(int64_t)(ch.r0 + i) * ld + c] = v[i];
+        }
+    }
+}
+
+// Before split-FP16 refinement products that follow 16-bit main products:
+// split each refining system's iterate (its FP32 master, complete after the
+// main phase's fixup) into the two FP16 operand parts the split product
+// reads, X = hi + 2^-11 lo with hi = fp16(X), lo = fp16(2^11 (X - hi)).  One
+// workgroup per chunk of rows of one part, four entries per thread.
+__global__ __launch_bounds__(kBlock) void k_split_operands(const PartDesc *__restrict__ parts,
+                                                           const RowChunk *__restrict__ chunks,
+                                                           const float *__restrict__ buf0,
+                                                           const float *__restrict__ buf1,
+                                                           _Float16 *__restrict__ hi0, _Float16 *__restrict__ hi1,
+                                                           _Float16 *__restrict__ lo0, _Float16 *__restrict__ lo1,
+                                                           const RunState *__restrict__ st_all) {
+    const RowChunk ch = chunks[blockIdx.x];
+    const PartDesc pd = parts[ch.part];
+    const RunState *st = st_all + pd.sys;
+    if (st->done || st->phase != 1) return;     // no refinement for this system
+    const int b = st->cur;
+    const float *X = (b ? buf1 : buf0) + pd.x_off;
+    _Float16 *H = (b ? hi1 : hi0) + pd.x_off;
+    _Float16 *L = (b ? lo1 : lo0) + pd.x_off;
+    const int ld = pd.s_pad;
+    for (int r = ch.r0; r < ch.r1; ++r) {
+        const float4 *x4 = reinterpret_cast<const float4 *>(X + (int64_t)r * ld);
+        uint2 *h4 = reinterpret_cast<uint2 *>(H + (int64_t)r * ld);
+        uint2 *l4 = reinterpret_cast<uint2 *>(L + (int64_t)r * ld);
+        for (int i = threadIdx.x; i < ld / 4; i += kBlock) {
+            const float4 v = x4[i];
+            const float x[4] = {v.x, v.y, v.z, v.w};
+            union { _Float16 h[4]; uint2 u; } a, c;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                a.h[e] = static_cast<_Float16>(x[e]);
+                c.h[e] = static_cast<_Float16>((x[e] - static_cast<float>(a.h[e])) * 0x1p11f);
+            }
+            h4[i] = a.u;
+            l4[i] = c.u;
         }
     }
 }
@@ -1986,13 +2028,13 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
         } else if (form == GSP2_KERNEL_T256) {
             if (prec == GSP2_PREC_FP16)
                 record(rec, k_sp2_wide<_Float16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0],
-                       h16[1], dp.state, dp.diag_partials, (_Float16 *)nullptr, (_Float16 *)nullptr);
+                       h16[1], dp.state, dp.diag_partials, (_Float16 *)nullptr, (_Float16 *)nullptr, phase);
             else if (prec == GSP2_PREC_FP16X3)
                 record(rec, k_sp2_wide<_Float16, true>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, h16[0],
-                       h16[1], dp.state, dp.diag_partials, l16[0], l16[1]);
+                       h16[1], dp.state, dp.diag_partials, l16[0], l16[1], phase);
             else
                 record(rec, k_sp2_wide<__bf16, false>, grid_w, blk_w, dp.tiles_w, dp.parts, b0, b1, b16[0],
-                       b16[1], dp.state, dp.diag_partials, (__bf16 *)nullptr, (__bf16 *)nullptr);
+                       b16[1], dp.state, dp.diag_partials, (__bf16 *)nullptr, (__bf16 *)nullptr, phase);
         } else if (prec == GSP2_PREC_FP16) {
             auto k = skip ? k_sp2_step<_Float16, false, true> : k_sp2_step<_Float16, false, false>;
             record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1], dp.state, dp.diag_partials,
@@ -2018,23 +2060,36 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
         if (rp.precision == GSP2_PREC_FP16)
             record(rec, k_wide_fixup<_Float16, false>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
                    (const _Float16 *)nullptr, (const _Float16 *)nullptr, (const _Float16 *)nullptr,
-                   (const _Float16 *)nullptr, dp.state);
+                   (const _Float16 *)nullptr, dp.state, 0);
         else if (rp.precision == GSP2_PREC_BF16)
             record(rec, k_wide_fixup<__bf16, false>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
                    (const __bf16 *)nullptr, (const __bf16 *)nullptr, (const __bf16 *)nullptr,
-                   (const __bf16 *)nullptr, dp.state);
+                   (const __bf16 *)nullptr, dp.state, 0);
         else if (rp.precision == GSP2_PREC_FP16X3)
             record(rec, k_wide_fixup<_Float16, true>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
                    (const _Float16 *)h16[0], (const _Float16 *)h16[1], (const _Float16 *)l16[0],
-                   (const _Float16 *)l16[1], dp.state);
+                   (const _Float16 *)l16[1], dp.state, 0);
     }
+    // refinement products: FP32 (FP64 in FP64 runs), or split FP16 on the
+    // iterate split once into its FP16 parts
+    const bool split_refine = rp.refine > 0 && rp.refine_prec == GSP2_PREC_FP16X3;
+    if (split_refine)
+        record(rec, k_split_operands, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, (const float *)b0,
+               (const float *)b1, h16[0], h16[1], l16[0], l16[1], dp.state);
     for (int r = 0; r < rp.refine; ++r) {
         const int slot = rp.n_steps + r;
         if (ev) rec.add_event(ev->step[2 * slot]);
-        product(rp.kernel32, f64 ? GSP2_PREC_FP64 : GSP2_PREC_FP32, 1);
+        if (split_refine)
+            product(GSP2_KERNEL_T256, GSP2_PREC_FP16X3, 1);
+        else
+            product(rp.kernel32, f64 ? GSP2_PREC_FP64 : GSP2_PREC_FP32, 1);
         if (ev) rec.add_event(ev->step[2 * slot + 1]);
         record(rec, k_sp2_decide, sys, blk, dp.diag_partials, dp.sys_diag_ptr, dp.state, 1);
     }
+    if (split_refine)
+        record(rec, k_wide_fixup<_Float16, true>, dim3(dp.n_chunks), blk, dp.parts, dp.chunks, b0, b1,
+               (const _Float16 *)h16[0], (const _Float16 *)h16[1], (const _Float16 *)l16[0],
+               (const _Float16 *)l16[1], dp.state, 1);
     if (ev) rec.add_event(ev->sp2_end);
     const int wpb = kBlock / kWave;
     if (f64)

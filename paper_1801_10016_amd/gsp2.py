@@ -61,7 +61,8 @@ class gsp2_run_options(C.Structure):
                 ("timing", C.c_int32), ("precision", C.c_int32), ("refine", C.c_int32),
                 ("persistent", C.c_int32), ("n_occ_system", C.POINTER(C.c_double)),
                 ("alpha_seq_system", C.POINTER(C.c_int8)), ("n_alpha_system", C.POINTER(C.c_int32)),
-                ("symmetrize", C.c_int32), ("kernel", C.c_int32)]
+                ("symmetrize", C.c_int32), ("kernel", C.c_int32), ("refine_precision", C.c_int32),
+                ("pad2_", C.c_int32)]
 
 
 class gsp2_run_info(C.Structure):
@@ -356,12 +357,15 @@ def gsp2_plan_set_stream(plan: Plan, stream=None):
 
 def make_run_options(max_iter=60, alpha_seq=None, stop_rule=True, trace_tol=0.5, timing=False,
                      precision="fp32", refine=0, persistent=False, n_occ_system=None, symmetrize=False,
-                     kernel="auto"):
+                     kernel="auto", refine_precision="fp32"):
     """Options struct and the arrays it points to (keep them alive for the
     call).  alpha_seq: one sequence, or (batched plans) a list of sequences,
     one per system; n_occ_system: occupations of a batched plan's systems;
-    kernel: the product kernel's form ("auto", "t128", "t128_skip", "t256")."""
+    kernel: the product kernel's form ("auto", "t128", "t128_skip", "t256");
+    refine_precision: operands of the refinement products ("fp32" or "fp16x3")."""
     o = gsp2_run_options_default()
+    o.refine_precision = (PRECISIONS[refine_precision] if isinstance(refine_precision, str)
+                          else int(refine_precision))
     o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     o.persistent = 1 if persistent else 0
     o.max_iter = int(max_iter)
@@ -413,7 +417,8 @@ def run_info_dict(info: gsp2_run_info) -> dict:
 
 def _density(entry: str, plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, alpha_seq=None,
              stop_rule=True, trace_tol=0.5, want_info=True, check=True, timing=False,
-             precision="fp32", refine=0, persistent=False, symmetrize=False, kernel="auto"):
+             precision="fp32", refine=0, persistent=False, symmetrize=False, kernel="auto",
+             refine_precision="fp32"):
     """Enqueue one density matrix into P_val (torch on the GPU, nnz_P entries:
     float64 for precision "fp64", float32 otherwise).  With want_info the
     call waits and returns the run's info dict (a list of them, one per
@@ -431,7 +436,8 @@ def _density(entry: str, plan: Plan, H: DeviceCSR, n_occ, P_val, max_iter=60, al
         raise ValueError("a batched plan takes one n_occ per system")
     c = H.as_c()
     o, keep = make_run_options(max_iter, alpha_seq, stop_rule, trace_tol, timing, precision, refine, persistent,
-                               n_occ_system=n_occ if batched else None, symmetrize=symmetrize, kernel=kernel)
+                               n_occ_system=n_occ if batched else None, symmetrize=symmetrize, kernel=kernel,
+                               refine_precision=refine_precision)
     info = (gsp2_run_info * plan.n_systems)() if want_info else None
     st = getattr(load(), entry)(plan.handle, C.byref(c), 0.0 if batched else float(n_occ), C.byref(o),
                                 C.c_void_p(P_val.data_ptr()), info)

@@ -129,14 +129,15 @@ def test_batch_matches_oracle_per_system():
         assert err <= TOL, (i, err)
 
 
-@pytest.mark.parametrize("precision,refine", [("fp32", 0), ("fp16", 2)])
-def test_batch_equals_one_system_plans(precision, refine):
+@pytest.mark.parametrize("precision,refine,refine_precision", [("fp32", 0, "fp32"), ("fp16", 2, "fp32"),
+                                                                ("fp16", 2, "fp16x3")])
+def test_batch_equals_one_system_plans(precision, refine, refine_precision):
     from tests._gpu import run_gsp2
     b = _small_batch()
-    P, runs, vals, col_ptr, _ = b.run(precision=precision, refine=refine)
+    P, runs, vals, col_ptr, _ = b.run(precision=precision, refine=refine, refine_precision=refine_precision)
     for i, s in enumerate(b.systems):
         _, run1, _, _, vals1 = run_gsp2(b.H_s[i], b.Pp_s[i], b.tau, b.part_s[i], b.n_parts[i], s.n_occ,
-                                        precision=precision, refine=refine)
+                                        precision=precision, refine=refine, refine_precision=refine_precision)
         assert runs[i]["alpha"] == run1["alpha"] and runs[i]["n_products"] == run1["n_products"], i
         assert runs[i]["traces"] == run1["traces"], i
         assert np.array_equal(b.system_vals(vals, col_ptr, i), vals1), i

@@ -368,6 +368,51 @@ def test_refinement_products_do_not_drift():
     assert err[8] <= 1.05 * err[2] and err[2] <= MIXED_TOL
 
 
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_split_fp16_refinement_products(precision):
+    # refinement products with split-FP16 operands after 16-bit products:
+    # FP32-grade products, so the result agrees with FP32 refinement products
+    # to FP32 rounding and meets the same bar against the oracle; in trace
+    # mode and with the oracle's sequence replayed, on 128 and 256 tiles
+    from tests._gpu import rel_fro, run_gsp2
+    s = pins.water(200, 1)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 6, seed=0)
+    ref = oracle.gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ)
+    for kw in ({}, {"alpha_seq": ref.sp2.alphas, "trace_tol": 1e9}, {"kernel": "t128"}):
+        out = {}
+        for rp in ("fp32", "fp16x3"):
+            P, run, _, _, vals = run_gsp2(s.H, Pp, 1e-4, part, 6, s.n_occ, precision=precision, refine=2,
+                                          refine_precision=rp, check=False, **kw)
+            assert run["status"] == 0 and run["n_refine"] == 2 and np.isfinite(vals).all(), run
+            out[rp] = (P, run)
+        gap = rel_fro(out["fp16x3"][0], out["fp32"][0])
+        errs = {rp: rel_fro(P, ref.csc()) for rp, (P, _) in out.items()}
+        print(f"{precision} {kw.get('kernel', 'auto')} {'replay' if kw.get('alpha_seq') else 'trace'}: split vs FP32 "
+              f"refinement {gap:.2e}; vs oracle {errs['fp32']:.2e} / {errs['fp16x3']:.2e}", flush=True)
+        assert out["fp16x3"][1]["alpha"] == out["fp32"][1]["alpha"]
+        assert gap <= 1e-5
+        assert abs(errs["fp16x3"] - errs["fp32"]) <= 1e-5
+        if precision == "fp16":
+            assert errs["fp16x3"] <= MIXED_TOL
+
+
+def test_split_refinement_needs_16bit_products():
+    import torch
+    import paper_1801_10016_amd as g
+    from paper_1801_10016_amd.gsp2 import GSP2_E_INVALID
+    s = pins.water(16, 0)
+    Pp = _dense_prev(s)
+    part = uneven_spatial_partition(s, 2, seed=0)
+    Hd = g.csr_to_device(s.H)
+    with g.gsp2_plan_create(g.csr_to_device(sp.csr_matrix(Pp)), 1e-3, part, 2) as plan:
+        P32 = torch.empty(plan.nnz_P, dtype=torch.float32, device="cuda")
+        for prec, rp in (("fp32", "fp16x3"), ("fp16x3", "fp16x3"), ("fp16", "bf16")):
+            with pytest.raises(g.Gsp2Error) as e:
+                g.gsp2_density(plan, Hd, s.n_occ, P32, precision=prec, refine=2, refine_precision=rp)
+            assert e.value.status == GSP2_E_INVALID
+
+
 def test_fp32_refinement_products():
     # refine FP32 products after the FP32 stop: the iterate stays at the oracle's result
     from tests._gpu import rel_fro, run_gsp2

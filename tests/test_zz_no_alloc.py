@@ -66,6 +66,7 @@ def test_noalloc_equals_density_two_calls():
 
 
 @pytest.mark.parametrize("kw", [{"precision": "fp64"}, {"precision": "fp16", "refine": 2},
+                                {"precision": "bf16", "refine": 2, "refine_precision": "fp16x3"},
                                 {"alpha_seq": [1, -1, 1, -1, -1], "trace_tol": 1e9, "symmetrize": True}])
 def test_noalloc_other_options(kw):
     _, _, _, _, v1, v2, r1, r2 = _both(32, 2, 4, 1e-3, **kw)
