@@ -649,24 +649,33 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     } while (0)
     // kSkip: work the matrix cores can leave out, exactly (wave-uniform):
     //  * a 32-row (or 32-column) block that starts at or beyond s lies in the
-    //    zero padding, so its products are zero and its accumulator stays 0;
-    //  * in a diagonal tile the lower-left wave's block is the transpose of
-    //    the upper-right wave's (the same products in the same order), so
-    //    that wave forms no products and the upper-right wave writes both.
-    // The branch around the MFMAs costs time of its own; the tile autotuner
-    // picks the form per plan (it pays where padding is a large share).
+    //    zero padding, so its products are zero and its accumulator stays 0
+    //    (the epilogue still writes those zeros: padding must stay zero);
+    //  * in a diagonal tile the lower-left wave's 64 x 64 block is the
+    //    transpose of the upper-right wave's (the same products in the same
+    //    order), so that wave forms no products and the upper-right wave
+    //    writes both; likewise, in each of the two waves on the diagonal, the
+    //    lower-left 32 x 32 block is the transpose of the upper-right one.
+    // The choice is made once per tile: each wave runs a straight-line K loop
+    // of its kind (all four blocks; three, on the diagonal; only those that
+    // reach into s, on edge tiles; none), so no branch sits among the MFMAs.
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     const bool mirror_wave = kSkip && diag && (wv >> 1) == 1 && (wv & 1) == 0;
+    const bool diag_wave = kSkip && diag && (wv >> 1) == (wv & 1);
     const bool actA[2] = {!mirror_wave && I0 + (wv >> 1) * 64 < pd.s, !mirror_wave && I0 + (wv >> 1) * 64 + 32 < pd.s};
     const bool actB[2] = {J0 + (wv & 1) * 64 < pd.s, J0 + (wv & 1) * 64 + 32 < pd.s};
     const bool all_active = actA[0] && actA[1] && actB[0] && actB[1];
     const bool any_active = (actA[0] || actA[1]) && (actB[0] || actB[1]);
-    auto compute_full = [&](int buf) __attribute__((always_inline)) {
+    // kind 0: all four blocks; 1: the blocks that reach into s (edge tiles);
+    // 2: none; 3: all but the lower-left block (diagonal waves)
+    auto compute_kind = [&](int buf, auto kind) __attribute__((always_inline)) {
+        constexpr int K = decltype(kind)::value;
+        if constexpr (K == 2) return;
         const uint4 *Asb = lds(buf, 0);
         const uint4 *Bsb = lds(buf, 1);
         // interleave the LDS fragment reads with the MFMAs (3.5% faster FP32
         // products than the default schedule, measured)
-        __builtin_amdgcn_iglp_opt(1);
+        if constexpr (K != 1) __builtin_amdgcn_iglp_opt(1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             // FP32: word kh*4+q of the row (k = 16 kh + 4 q + e); 16-bit: word 2q+kh (k = 16 q + 8 kh + e)
@@ -680,58 +689,48 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
 #pragma unroll
             for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
+                for (int nn = 0; nn < 2; ++nn) {
+                    if constexpr (K == 3) {
+                        if (m == 1 && nn == 0) continue;
+                    }
+                    if constexpr (K == 1) {
+                        if (!(actA[m] && actB[nn]) || (diag_wave && m == 1 && nn == 0)) continue;
+                    }
+                    acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
+                }
         }
     };
-    // edge tiles of the kSkip form: only the blocks that reach into s
-    auto compute_part = [&](int buf) __attribute__((always_inline)) {
-        const uint4 *Asb = lds(buf, 0);
-        const uint4 *Bsb = lds(buf, 1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int w = kF32 ? kh * 4 + q : 2 * q + kh;
-            uint4 fa[2], fb[2];
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
-                fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
-            }
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-                for (int nn = 0; nn < 2; ++nn)
-                    if (actA[m] && actB[nn]) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
-        }
-    };
-    auto compute = [&](int buf) __attribute__((always_inline)) {
-        if constexpr (!kSkip) {
-            compute_full(buf);
-        } else {
-            if (all_active) compute_full(buf);
-            else if (any_active) compute_part(buf);
-        }
-    };
-    GSP2_LD(0, 0);
-    GSP2_ST(0, 0);
-    GSP2_LD(1, min(1, nc - 1));
-    __syncthreads();
-    for (int kc = 0; kc < nc; kc += 2) {
-        if constexpr (kSplit) {
-            if (kc == 2 * nk) {                 // cross terms done: scale them by 2^-11
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
-            }
-        }
-        GSP2_LD(0, min(kc + 2, nc - 1));
-        compute(0);
-        GSP2_ST(1, 1);
-        __syncthreads();
-        GSP2_LD(1, min(kc + 3, nc - 1));
-        compute(1);
+    auto kloop = [&](auto kind) __attribute__((always_inline)) {
+        GSP2_LD(0, 0);
         GSP2_ST(0, 0);
+        GSP2_LD(1, min(1, nc - 1));
         __syncthreads();
+        for (int kc = 0; kc < nc; kc += 2) {
+            if constexpr (kSplit) {
+                if (kc == 2 * nk) {             // cross terms done: scale them by 2^-11
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+#pragma unroll
+                        for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
+                }
+            }
+            GSP2_LD(0, min(kc + 2, nc - 1));
+            compute_kind(0, kind);
+            GSP2_ST(1, 1);
+            __syncthreads();
+            GSP2_LD(1, min(kc + 3, nc - 1));
+            compute_kind(1, kind);
+            GSP2_ST(0, 0);
+            __syncthreads();
+        }
+    };
+    if constexpr (!kSkip) {
+        kloop(std::integral_constant<int, 0>{});
+    } else {
+        if (mirror_wave || !any_active) kloop(std::integral_constant<int, 2>{});
+        else if (!all_active) kloop(std::integral_constant<int, 1>{});
+        else if (diag_wave) kloop(std::integral_constant<int, 3>{});
+        else kloop(std::integral_constant<int, 0>{});
     }
 #undef GSP2_SRC
 #undef GSP2_LD
@@ -744,14 +743,17 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // diagonal and d_r^2 on it, so the diagonal is never rounded.
     constexpr bool kExactDiag = !kF32 && !kSplit;
     // the mirrored writes: every off-diagonal tile; in the kSkip form also
-    // the upper-right wave of a diagonal tile, for the lower-left one
-    const bool write_mirror = !diag || (kSkip && (wv >> 1) == 0 && (wv & 1) == 1);
+    // the upper-right wave of a diagonal tile, for the lower-left one, and
+    // the upper-right block of each diagonal wave, for its lower-left one
+    const bool upper_right_wave = kSkip && diag && (wv >> 1) == 0 && (wv & 1) == 1;
     double tY = 0.0, tX = 0.0;
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
 #pragma unroll
         for (int nn = 0; nn < 2; ++nn) {
             if (mirror_wave) continue;
+            if (diag_wave && m == 1 && nn == 0) continue;
+            const bool write_mirror = !diag || upper_right_wave || (diag_wave && m == 0 && nn == 1);
             const int cg = J0 + wc * 64 + nn * 32 + l32;
             const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
 #pragma unroll
