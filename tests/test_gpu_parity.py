@@ -509,6 +509,19 @@ def test_largest_checked_single_block():
     P, run, ref = _check_parity(s, 1e-5, 1, part=part)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16x3"])
+def test_one_large_part_beside_small_ones(precision):
+    # a part holding most of the work is dealt to the XCDs block by block
+    # while the small parts go whole: tile lists of both kinds in one plan,
+    # for 128- and 256-wide tiles
+    s = pins.water(200, 1)
+    part = uneven_spatial_partition(s, 6, seed=0)
+    part = np.where(part < 4, 0, part - 3).astype(np.int32)    # parts 0-3 joined: 3 parts, one large
+    sizes = np.bincount(part)
+    assert sizes[0] > 2 * sizes[1:].sum(), sizes
+    P, run, ref = _check_parity(s, 1e-4, 3, part=part, precision=precision)
+
+
 def test_dense_block_beyond_the_lds_index_list():
     # a single part of 9,000 orbitals: the gather's vertex list no longer fits
     # LDS (8,192 entries) and is read from global memory.  No oracle runs at
