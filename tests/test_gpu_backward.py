@@ -154,11 +154,19 @@ def test_backward_water1000_two_losses():
         got, info = _gpu_grad(s, Pp, tau, part, n_parts, fw.sp2.alphas, Wl)
         explicit = np.where(Hd != 0, ref.P, 0.0) if band else 0.0   # dTr(PH)/dH at fixed P
         total_ref = ref.dH + explicit
-        err = np.linalg.norm(got - ref.dH) / np.linalg.norm(total_ref)
-        print(f"water1000 {name}: {len(fw.sp2.alphas)} products, rel_err={err:.2e} "
-              f"(through P alone {np.linalg.norm(got - ref.dH) / np.linalg.norm(ref.dH):.2e}; "
-              f"oracle {t_or:.1f} s, GPU pass workspace {info['workspace_bytes'] / 2**30:.2f} GiB)", flush=True)
-        assert err <= TOL
+        err_total = np.linalg.norm(got - ref.dH) / np.linalg.norm(total_ref)
+        err_through_p = np.linalg.norm(got - ref.dH) / np.linalg.norm(ref.dH)
+        print(f"water1000 {name}: {len(fw.sp2.alphas)} products, gap on the whole gradient {err_total:.2e}, "
+              f"on the part through P alone {err_through_p:.2e} "
+              f"(oracle {t_or:.1f} s, GPU pass workspace {info['workspace_bytes'] / 2**30:.2f} GiB)", flush=True)
+        if band:
+            # the part through P nearly cancels (Hellmann-Feynman: it vanishes for
+            # an exact projector), so FP32 rounding is large relative to it: it is
+            # held to the bar on the scale of the whole gradient, and on its own
+            # scale to 5e-4 (2.0e-4 measured)
+            assert err_total <= TOL and err_through_p <= 5e-4
+        else:
+            assert err_through_p <= TOL
 
         def L_of(hop_a):
             Hh = make_water(1000, 0, hop_a=hop_a).H
