@@ -511,15 +511,20 @@ def test_largest_checked_single_block():
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16x3"])
 def test_one_large_part_beside_small_ones(precision):
-    # a part holding most of the work is dealt to the XCDs block by block
-    # while the small parts go whole: tile lists of both kinds in one plan,
-    # for 128- and 256-wide tiles
+    # a part holding more than half an XCD's share of the product work (a
+    # sixteenth of it) is dealt to the XCDs block by block while the other
+    # parts go whole: tile lists of both kinds in one plan, for 128- and
+    # 256-wide tiles.  200 molecules in 48 uneven parts, the first 16 joined:
+    # 33 parts, of which only the joined one (s = 1,043) is split.
+    from oracle.graph import core_halo, threshold_graph
     s = pins.water(200, 1)
-    part = uneven_spatial_partition(s, 6, seed=0)
-    part = np.where(part < 4, 0, part - 3).astype(np.int32)    # parts 0-3 joined: 3 parts, one large
-    sizes = np.bincount(part)
-    assert sizes[0] > 2 * sizes[1:].sum(), sizes
-    P, run, ref = _check_parity(s, 1e-4, 3, part=part, precision=precision)
+    part = uneven_spatial_partition(s, 48, seed=0)
+    part = np.where(part < 16, 0, part - 15).astype(np.int32)
+    cores, halos = core_halo(threshold_graph(_dense_prev(s), 1e-3), part, 33)
+    nt = -(-np.array([len(c) + len(h) for c, h in zip(cores, halos)]) // 128)
+    work = nt * (nt + 1) / 2 * nt
+    assert np.flatnonzero(work > work.sum() / 16).tolist() == [0], work
+    _check_parity(s, 1e-3, 33, part=part, precision=precision)
 
 
 def test_dense_block_beyond_the_lds_index_list():
