@@ -513,6 +513,46 @@ gsp2_status gsp2_core_halo_host(int32_t n, const int64_t *adj_ptr, const int32_t
                                 const int32_t *part, int32_t n_parts, int64_t *sub_ptr,
                                 int32_t *sub_idx, int32_t *core_count);
 
+/* Outcome of gsp2_sparse_sp2_host. */
+typedef struct {
+    int32_t status;            /* GSP2_OK, GSP2_E_NOT_CONVERGED or GSP2_E_WRONG_TRACE */
+    int32_t n_products;        /* products formed, including a discarded last one */
+    int32_t n_alpha;           /* branches applied */
+    int32_t pad_;
+    double eps_min, eps_max;   /* Gershgorin bounds of H */
+    double trace;              /* Tr P */
+    double idempotency;        /* e_t = Tr[X_t] - Tr[X_t^2] of the returned iterate */
+    int64_t nnz;               /* stored entries of P */
+    int8_t alpha[GSP2_MAX_ITER];
+} gsp2_sparse_sp2_info;
+
+/* Host-only (no GPU needed): the very first density matrix, by SP2 of the
+ * whole H in numerically thresholded sparse algebra, the standard scheme
+ * that provides P before any graph or partition exists (Fig. 1 description
+ * in the Introduction; the threshold is the same kind of parameter as the
+ * graph's tau, Methods, "Graph Theory").  The steps are those of a dense
+ * run: Gershgorin bounds, eq. (1), then per product the stop rule (stop at
+ * the first product t >= 2 whose idempotency measure |e_t| has stopped
+ * falling below |e_{t-2}| < 1; the product just formed is discarded), the
+ * trace rule for the branch and eq. (2); every iterate keeps only its
+ * entries with |x| > eps (eps = 0 keeps every nonzero).  Sparse products on
+ * the host threads; the result does not depend on their number.
+ *
+ *  n, H_row_ptr, H_col, H_val  host CSR of H (symmetric, FP64), both triangles stored.
+ *  n_occ       occupied states, 0 <= n_occ <= n.
+ *  eps         threshold, >= 0.
+ *  max_iter    product budget, 1..GSP2_MAX_ITER.
+ *  P_row_ptr   host, n+1: filled with P's row pointer.
+ *  P_col, P_val host, P_row_ptr[n] entries each, or both NULL: only
+ *              P_row_ptr and info are filled (size query; a second call with
+ *              the arrays recomputes the same P).
+ *  info        nullable.
+ * Returns GSP2_E_INVALID for bad arguments or a flat spectrum bound; else the
+ * run's status (P is filled in every case). */
+gsp2_status gsp2_sparse_sp2_host(int32_t n, const int64_t *H_row_ptr, const int32_t *H_col, const double *H_val,
+                                 double n_occ, double eps, int32_t max_iter, int64_t *P_row_ptr, int32_t *P_col,
+                                 double *P_val, gsp2_sparse_sp2_info *info);
+
 #ifdef __cplusplus
 }
 #endif

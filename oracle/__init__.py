@@ -8,7 +8,7 @@ arXiv:1801.10016 named in its docstring, written as the plain definition
 (or the algorithm's steps in the paper's order), in float64 numpy, with no
 blocking, fusion or reordering of its own.
 """
-from .sp2 import (gershgorin_bounds, initial_guess, sp2_blocks, dense_sp2,
+from .sp2 import (gershgorin_bounds, initial_guess, sp2_blocks, dense_sp2, thresholded_sp2, drop_small,
                   SP2Result, NotConverged, WrongTrace)
 from .graph import threshold_graph, core_halo, ch_cost, subproblem_index
 from .gsp2 import gsp2, GSP2Result
@@ -16,7 +16,7 @@ from .spectral import eig_projector, spectral_gap
 from .adjoint import gsp2_grad, gershgorin_rows, GSP2Grad
 
 __all__ = [
-    "gershgorin_bounds", "initial_guess", "sp2_blocks", "dense_sp2", "SP2Result",
+    "gershgorin_bounds", "initial_guess", "sp2_blocks", "dense_sp2", "thresholded_sp2", "drop_small", "SP2Result",
     "NotConverged", "WrongTrace", "threshold_graph", "core_halo", "ch_cost",
     "subproblem_index", "gsp2", "GSP2Result", "eig_projector", "spectral_gap",
     "gsp2_grad", "gershgorin_rows", "GSP2Grad",

@@ -90,15 +90,27 @@ class SP2Result:
     meta: dict = field(default_factory=dict)
 
 
+def drop_small(X: np.ndarray, eps: float) -> np.ndarray:
+    """Numerical thresholding of sparse-matrix SP2 (the standard scheme that
+    gives the initial P, Fig. 1 description; the threshold is the same kind of
+    parameter as the graph's tau, Methods, "Graph Theory"): an entry is kept
+    iff |x| > eps, the strict comparison of the graph's threshold."""
+    return np.where(np.abs(X) > eps, X, 0.0)
+
+
 def sp2_blocks(X0: list, cores: list, n_occ: float, max_iter: int = 60,
                alpha_seq=None, stop_rule: bool = True, trace_tol: float = 0.5,
-               raise_on_failure: bool = False, unit_roundoff: float = 2.0 ** -53) -> SP2Result:
+               raise_on_failure: bool = False, unit_roundoff: float = 2.0 ** -53,
+               eps: float | None = None) -> SP2Result:
     """Run the SP2 recursion eq. (2) on every block at once, all blocks sharing
     one branch sequence chosen from the summed core trace.
 
     X0: list of square FP64 arrays, part k's core rows first (its first
-    cores[k] rows/columns)."""
+    cores[k] rows/columns).  eps: if given, every iterate (X0 included) is
+    thresholded with drop_small; the products themselves are formed in full."""
     X = [np.array(x, dtype=np.float64, copy=True) for x in X0]
+    if eps is not None:
+        X = [drop_small(x, eps) for x in X]
     tr = _core_trace(X, cores)
     traces, errors, alphas = [tr], [], []
     replay = alpha_seq is not None
@@ -121,6 +133,8 @@ def sp2_blocks(X0: list, cores: list, n_occ: float, max_iter: int = 60,
             alpha = 1 if tr <= n_occ else -1
         # eq. (2): X_i = [I + alpha (I - X)] X = X + alpha (X - X^2)
         X = [x + alpha * (x - y) for x, y in zip(X, Y)]
+        if eps is not None:
+            X = [drop_small(x, eps) for x in X]
         alphas.append(alpha)
         tr = _core_trace(X, cores)
         traces.append(tr)
@@ -142,4 +156,18 @@ def dense_sp2(H, n_occ: float, max_iter: int = 60, **kw) -> tuple[np.ndarray, SP
     emin, emax = gershgorin_bounds(Hd)
     X0 = initial_guess(Hd, emin, emax)
     res = sp2_blocks([X0], [Hd.shape[0]], n_occ, max_iter=max_iter, **kw)
+    return res.blocks[0], res
+
+
+def thresholded_sp2(H, n_occ: float, eps: float, max_iter: int = 60, **kw) -> tuple[np.ndarray, SP2Result]:
+    """SP2 of the whole matrix in numerically thresholded algebra, the scheme
+    that computes the initial density matrix before any graph exists (Fig. 1
+    description): dense SP2 (Gershgorin bounds, eq. (1), eq. (2), the trace
+    rule and the stop rule) with every iterate thresholded by drop_small;
+    each product is formed from the thresholded iterate, and the stop
+    measure e_t from that full product."""
+    Hd = H.toarray() if sp.issparse(H) else np.asarray(H, dtype=np.float64)
+    emin, emax = gershgorin_bounds(Hd)
+    X0 = initial_guess(Hd, emin, emax)
+    res = sp2_blocks([X0], [Hd.shape[0]], n_occ, max_iter=max_iter, eps=eps, **kw)
     return res.blocks[0], res

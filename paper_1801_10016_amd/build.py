@@ -28,7 +28,8 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     inc = os.path.join(ROOT, "include")
-    srcs = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "gsp2_abi.cpp"), os.path.join(CSRC, "partition.cpp")]
+    srcs = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "gsp2_abi.cpp"), os.path.join(CSRC, "partition.cpp"),
+            os.path.join(CSRC, "sparse_sp2.cpp")]
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", inc, "-I", CSRC, "-shared", "-o", tmp, *srcs]
     if verbose:

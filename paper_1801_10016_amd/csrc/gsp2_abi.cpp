@@ -13,6 +13,7 @@
 #include <numeric>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gsp2.h"
@@ -860,6 +861,54 @@ gsp2_status gsp2_locality_graph(int32_t n_orb, const int32_t *orbital_atom, int3
         std::copy(ptr.begin(), ptr.end(), adj_ptr);
         if (adj_col) std::copy(col.begin(), col.end(), adj_col);
     });
+}
+
+gsp2_status gsp2_sparse_sp2_host(int32_t n, const int64_t *H_row_ptr, const int32_t *H_col, const double *H_val,
+                                 double n_occ, double eps, int32_t max_iter, int64_t *P_row_ptr, int32_t *P_col,
+                                 double *P_val, gsp2_sparse_sp2_info *info) {
+    gsp2_status run_status = GSP2_OK;
+    const gsp2_status st = guarded([&] {
+        if (n < 1) fail(GSP2_E_INVALID, "need n >= 1");
+        if (!H_row_ptr || !P_row_ptr) fail(GSP2_E_INVALID, "null pointer");
+        if ((P_col == nullptr) != (P_val == nullptr)) fail(GSP2_E_INVALID, "P_col and P_val go together");
+        if (H_row_ptr[0] != 0) fail(GSP2_E_INVALID, "H_row_ptr[0] must be 0");
+        for (int32_t i = 0; i < n; ++i)
+            if (H_row_ptr[i + 1] < H_row_ptr[i]) fail(GSP2_E_INVALID, "H_row_ptr must not decrease");
+        const int64_t nnz = H_row_ptr[n];
+        if (nnz > 0 && (!H_col || !H_val)) fail(GSP2_E_INVALID, "null H arrays");
+        for (int64_t e = 0; e < nnz; ++e) {
+            if (H_col[e] < 0 || H_col[e] >= n) fail(GSP2_E_INVALID, "column index out of range");
+            if (!std::isfinite(H_val[e])) fail(GSP2_E_INVALID, "non-finite H");
+        }
+        if (!(n_occ >= 0.0) || !(n_occ <= (double)n)) fail(GSP2_E_INVALID, "need 0 <= n_occ <= n");
+        if (!(eps >= 0.0) || !std::isfinite(eps)) fail(GSP2_E_INVALID, "eps must be finite and >= 0");
+        if (max_iter < 1 || max_iter > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "max_iter out of range");
+        const int n_threads = (int)std::min(16u, std::max(1u, std::thread::hardware_concurrency()));
+        SparseSP2Result r = sparse_sp2(n, H_row_ptr, H_col, H_val, n_occ, eps, max_iter, 0.5, n_threads);
+        if (!(r.eps_max > r.eps_min)) fail(GSP2_E_INVALID, "flat spectrum bounds (eps_max <= eps_min)");
+        std::copy(r.ptr.begin(), r.ptr.end(), P_row_ptr);
+        if (P_col) {
+            std::copy(r.col.begin(), r.col.end(), P_col);
+            std::copy(r.val.begin(), r.val.end(), P_val);
+        }
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->status = r.status;
+            info->n_products = r.n_products;
+            info->n_alpha = (int32_t)r.alphas.size();
+            info->eps_min = r.eps_min;
+            info->eps_max = r.eps_max;
+            info->trace = r.trace;
+            info->idempotency = r.idempotency;
+            info->nnz = r.ptr.back();
+            std::copy(r.alphas.begin(), r.alphas.end(), info->alpha);
+        }
+        run_status = (gsp2_status)r.status;
+        if (run_status != GSP2_OK)
+            g_last_error = run_status == GSP2_E_WRONG_TRACE ? "trace of the result misses n_occ by more than 0.5"
+                                                            : "no convergence within max_iter products";
+    });
+    return st != GSP2_OK ? st : run_status;
 }
 
 gsp2_status gsp2_plan_set_stream(gsp2_plan plan, void *stream) {

@@ -247,6 +247,19 @@ struct AnnealResult {
 AnnealResult anneal_partition(int32_t n, const int64_t *adj_ptr, const int32_t *adj_col, int32_t n_parts,
                               int32_t *part, int32_t sweeps, double t0, double cooling, uint64_t seed);
 
+// SP2 of the whole matrix in thresholded sparse algebra, on the host
+// (sparse_sp2.cpp).
+struct SparseSP2Result {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    std::vector<int8_t> alphas;
+    int32_t status = 0, n_products = 0;
+    double eps_min = 0.0, eps_max = 0.0, trace = 0.0, idempotency = 0.0;
+};
+SparseSP2Result sparse_sp2(int32_t n, const int64_t *rp, const int32_t *ci, const double *hv, double n_occ,
+                           double eps, int32_t max_iter, double trace_tol, int n_threads);
+
 // Graph of the locality construction: orbitals adjacent when their atoms are
 // closer than `radius` (partition.cpp).
 void locality_graph(int32_t n_orb, const int32_t *orbital_atom, int32_t n_atoms, const double *xyz, double radius,

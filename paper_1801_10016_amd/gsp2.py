@@ -92,6 +92,12 @@ class gsp2_backward_info(C.Structure):
                 ("workspace_bytes", C.c_int64)]
 
 
+class gsp2_sparse_sp2_info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_products", C.c_int32), ("n_alpha", C.c_int32), ("pad_", C.c_int32),
+                ("eps_min", C.c_double), ("eps_max", C.c_double), ("trace", C.c_double),
+                ("idempotency", C.c_double), ("nnz", C.c_int64), ("alpha", C.c_int8 * GSP2_MAX_ITER)]
+
+
 _PLAN = C.c_void_p
 
 # name -> (restype, argtypes), exactly the functions declared in gsp2.h
@@ -123,6 +129,10 @@ SIGNATURES = {
     "gsp2_partition_anneal": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(gsp2_anneal_options),
                                         C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "gsp2_sparse_sp2_host": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_double), C.c_double, C.c_double, C.c_int32,
+                                       C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                       C.POINTER(gsp2_sparse_sp2_info)]),
     "gsp2_core_halo_host": (C.c_int, [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.c_int32, C.POINTER(C.c_int64),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
@@ -524,3 +534,33 @@ def gsp2_core_halo_host(adj_ptr, adj_col, part, n_parts: int):
     _check(lib.gsp2_core_halo_host(n, _i64(adj_ptr), _i32(adj_col), _i32(part), int(n_parts),
                                    _i64(sub_ptr), _i32(sub_idx), _i32(core)))
     return sub_ptr, sub_idx, core
+
+
+def gsp2_sparse_sp2_host(H, n_occ, eps: float, max_iter: int = 60, check: bool = True):
+    """Host: the first density matrix of H (scipy sparse, FP64) by SP2 in
+    thresholded sparse algebra (gsp2_sparse_sp2_host in gsp2.h).  Returns
+    (P as scipy.sparse.csr_matrix, info dict); with check a failing run
+    status raises Gsp2Error."""
+    import scipy.sparse as sp
+    H = sp.csr_matrix(H, dtype=np.float64)
+    n = H.shape[0]
+    rp = np.ascontiguousarray(H.indptr, dtype=np.int64)
+    ci = np.ascontiguousarray(H.indices, dtype=np.int32)
+    hv = np.ascontiguousarray(H.data, dtype=np.float64)
+    lib = load()
+    ptr = np.empty(n + 1, dtype=np.int64)
+    info = gsp2_sparse_sp2_info()
+    args = (n, _i64(rp), _i32(ci), hv.ctypes.data_as(C.POINTER(C.c_double)), float(n_occ), float(eps), int(max_iter))
+    st = lib.gsp2_sparse_sp2_host(*args, _i64(ptr), None, None, C.byref(info))
+    if st not in (GSP2_OK, GSP2_E_NOT_CONVERGED, GSP2_E_WRONG_TRACE):
+        _check(st)
+    col = np.empty(int(ptr[-1]), dtype=np.int32)
+    val = np.empty(int(ptr[-1]), dtype=np.float64)
+    st = lib.gsp2_sparse_sp2_host(*args, _i64(ptr), _i32(col), val.ctypes.data_as(C.POINTER(C.c_double)),
+                                  C.byref(info))
+    if check:
+        _check(st)
+    d = {f: getattr(info, f) for f, _ in gsp2_sparse_sp2_info._fields_ if f not in ("alpha", "pad_")}
+    d["alpha"] = [int(a) for a in info.alpha[:info.n_alpha]]
+    d["status_name"] = STATUS_NAMES.get(info.status, str(info.status))
+    return sp.csr_matrix((val, col, ptr), shape=(n, n)), d

@@ -339,6 +339,26 @@ def check_core_column_layout(sys_, tau=1e-2, n_parts=8):
         assert np.array_equal(D[np.ix_(g.index[k], g.cores[k])], g.core_columns[k])
 
 
+def check_thresholded_sp2(sys_):
+    """Thresholded-algebra SP2 of the whole matrix: with a threshold below any
+    rounding-level entry it is the eigen projector; every entry it keeps
+    exceeds the threshold in magnitude; and its distance from the projector
+    grows with the threshold but stays within the sum of what can be dropped
+    (at most n^2 entries of size eps per product over the run)."""
+    Pstar = oracle.eig_projector(sys_.H, sys_.n_occ)
+    P0, r0 = oracle.thresholded_sp2(sys_.H, sys_.n_occ, 1e-14)
+    assert r0.status == "ok" and rel(P0, Pstar) <= 1e-12
+    prev = 0.0
+    for eps in (1e-8, 1e-6, 1e-4):
+        P, r = oracle.thresholded_sp2(sys_.H, sys_.n_occ, eps)
+        kept = P[P != 0]
+        assert r.status == "ok" and np.all(np.abs(kept) > eps), eps
+        err = rel(P, Pstar)
+        bound = r.n_products * sys_.n * eps / np.linalg.norm(Pstar)
+        assert prev <= err <= bound, (eps, err, bound)
+        prev = err
+
+
 def battery():
     """Every pin, on small systems; raises on the first failure."""
     check_gershgorin_textbook()
@@ -361,6 +381,7 @@ def battery():
     check_core_column_layout(water(64, 0))
     check_symmetrize(water(32, 0))
     check_occupation_status(water(32, 0))
+    check_thresholded_sp2(water(64, 1))
     check_adjoint_finite_differences()
     check_adjoint_closed_form()
 

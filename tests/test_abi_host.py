@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def declared_functions():
     src = open(os.path.join(ROOT, "include", "gsp2.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(gsp2_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(gsp2_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -126,7 +126,8 @@ def test_binding_structs_match_the_header(tmp_path):
     if cc is None:
         pytest.skip("no host C compiler")
     structs = [binding.gsp2_csr, binding.gsp2_plan_options, binding.gsp2_plan_info, binding.gsp2_run_options,
-               binding.gsp2_run_info, binding.gsp2_timing, binding.gsp2_backward_info, binding.gsp2_tune_info]
+               binding.gsp2_run_info, binding.gsp2_timing, binding.gsp2_backward_info, binding.gsp2_tune_info,
+               binding.gsp2_sparse_sp2_info, binding.gsp2_anneal_options]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gsp2.h"', "int main(void) {"]
     for cls in structs:
         name = cls.__name__

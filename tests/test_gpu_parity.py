@@ -527,6 +527,26 @@ def test_one_large_part_beside_small_ones(precision):
     _check_parity(s, 1e-3, 33, part=part, precision=precision)
 
 
+def test_plan_from_the_sparse_first_p():
+    # the first P by thresholded sparse SP2 on the host, thresholded into the
+    # plan's graph, then G-SP2 on the GPU: against the oracle's G-SP2 on the
+    # oracle's own thresholded first P
+    from tests._gpu import rel_fro, run_gsp2
+    import paper_1801_10016_amd as g
+    s = pins.water(100, 0)
+    P_first, info = g.gsp2_sparse_sp2_host(s.H, s.n_occ, 1e-7)
+    Po_first, _ = oracle.thresholded_sp2(s.H, s.n_occ, 1e-7)
+    part = uneven_spatial_partition(s, 6, seed=0)
+    ref = oracle.gsp2(s.H, Po_first, 1e-4, part, 6, s.n_occ)
+    P, run, _, index, _ = run_gsp2(s.H, P_first.toarray(), 1e-4, part, 6, s.n_occ, alpha_seq=ref.sp2.alphas,
+                                   trace_tol=1e9)
+    for k in range(6):
+        assert np.array_equal(index[k], ref.index[k]), k
+    err = rel_fro(P, ref.csc())
+    print(f"first P: {info['n_products']} host products, nnz {P_first.nnz}; G-SP2 rel_err {err:.2e}", flush=True)
+    assert run["status"] == 0 and err <= TOL
+
+
 def test_dense_block_beyond_the_lds_index_list():
     # a single part of 9,000 orbitals: the gather's vertex list no longer fits
     # LDS (8,192 entries) and is read from global memory.  No oracle runs at

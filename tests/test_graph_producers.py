@@ -173,3 +173,66 @@ def test_locality_graph_open_boundaries_and_errors():
         g.gsp2_locality_graph(oa, xyz, 0.0)
     with pytest.raises(g.Gsp2Error):
         g.gsp2_locality_graph(np.array([0, 3], dtype=np.int32), xyz, 1.0)
+
+
+# -- gsp2_sparse_sp2_host: the first P by thresholded sparse SP2 ------------
+
+def _sparse_vs_oracle(s, eps, **kw):
+    P, info = g.gsp2_sparse_sp2_host(s.H, s.n_occ, eps, **kw)
+    Po, r = oracle.thresholded_sp2(s.H, s.n_occ, eps, **kw)
+    return P, info, Po, r
+
+
+@pytest.mark.parametrize("n_mol,seed,eps", [(64, 0, 1e-10), (64, 0, 1e-6), (64, 0, 1e-4), (100, 2, 1e-6),
+                                            (100, 2, 1e-3)])
+def test_sparse_sp2_matches_the_oracle(n_mol, seed, eps):
+    # the same steps in FP64 on both sides: the branch sequences agree (a
+    # stop may fall one product apart where e_t sits at rounding level), P
+    # agrees to rounding, and both keep exactly the entries above eps
+    s = pins.water(n_mol, seed)
+    P, info, Po, r = _sparse_vs_oracle(s, eps)
+    a, b = info["alpha"], r.alphas
+    m = min(len(a), len(b))
+    assert info["status"] == 0 and r.status == "ok" and a[:m] == b[:m] and abs(len(a) - len(b)) <= 1
+    err = np.linalg.norm(P.toarray() - Po) / np.linalg.norm(Po)
+    print(f"{n_mol} molecules, eps {eps:g}: {info['n_products']} products, nnz {P.nnz}, rel_err {err:.2e}", flush=True)
+    assert err <= (1e-12 if a == b else 1e-9)
+    assert np.all(np.abs(P.data) > eps)
+    if a == b:
+        assert P.nnz == np.count_nonzero(Po)
+    assert abs(info["trace"] - np.trace(P.toarray())) <= 1e-9 * s.n
+    emin, emax = oracle.gershgorin_bounds(s.H)
+    assert (info["eps_min"], info["eps_max"]) == pytest.approx((emin, emax), rel=1e-14, abs=1e-12)
+
+
+def test_sparse_sp2_without_threshold_is_the_projector():
+    s = pins.water(32, 1)
+    P, info = g.gsp2_sparse_sp2_host(s.H, s.n_occ, 0.0)
+    Pstar = oracle.eig_projector(s.H, s.n_occ)
+    assert info["status"] == 0
+    assert np.linalg.norm(P.toarray() - Pstar) <= 1e-12 * np.linalg.norm(Pstar)
+
+
+def test_sparse_sp2_graph_feeds_a_plan_graph():
+    # thresholding the sparse P at tau gives the oracle's graph of its own
+    # thresholded P (an input the plan takes as it is)
+    s = pins.water(100, 0)
+    P, _, Po, _ = _sparse_vs_oracle(s, 1e-7)
+    A = oracle.threshold_graph(P, 1e-4)
+    Ao = oracle.threshold_graph(Po, 1e-4)
+    assert (A != Ao).nnz == 0 and A.nnz > 0
+
+
+def test_sparse_sp2_statuses_and_arguments():
+    s = pins.water(16, 0)
+    P, info = g.gsp2_sparse_sp2_host(s.H, s.n_occ, 1e-6, max_iter=5, check=False)
+    assert info["status"] == binding.GSP2_E_NOT_CONVERGED and np.isfinite(P.data).all()
+    P1, _ = g.gsp2_sparse_sp2_host(s.H, s.n_occ, 1e-6)
+    P2, _ = g.gsp2_sparse_sp2_host(s.H, s.n_occ, 1e-6)
+    assert (P1 != P2).nnz == 0
+    for kw in ({"n_occ": s.n + 1}, {"n_occ": -1}, {"eps": -1.0}, {"max_iter": 0}):
+        args = dict(n_occ=s.n_occ, eps=1e-6, max_iter=60)
+        args.update(kw)
+        with pytest.raises(binding.Gsp2Error) as e:
+            g.gsp2_sparse_sp2_host(s.H, args["n_occ"], args["eps"], max_iter=args["max_iter"])
+        assert e.value.status == binding.GSP2_E_INVALID

@@ -37,6 +37,9 @@ MUTANTS = {
     "gap_off_by_one": ("spectral.py", "return float(w[int(n_occ)] - w[int(n_occ) - 1])",
                        "return float(w[int(n_occ) + 1] - w[int(n_occ)])"),
     "occupation_unchecked": ("sp2.py", "            if abs(tr - n_occ) <= trace_tol:", "            if True:"),
+    "drop_signed": ("sp2.py", "np.where(np.abs(X) > eps, X, 0.0)", "np.where(X > eps, X, 0.0)"),
+    "drop_x0_only": ("sp2.py", "            X = [drop_small(x, eps) for x in X]\n        alphas.append",
+                     "            X = [x for x in X]\n        alphas.append"),
     "adjoint_no_bound_terms": ("adjoint.py", "                dH[row, row] += g", "                dH[row, row] += 0.0"),
 }
 

@@ -126,3 +126,8 @@ def test_adjoint_matches_central_differences():
 
 def test_adjoint_closed_form_and_hellmann_feynman():
     pins.check_adjoint_closed_form()
+
+
+@pytest.mark.parametrize("n_mol,seed", [(64, 1), (100, 0)])
+def test_thresholded_sp2_bounds(n_mol, seed):
+    pins.check_thresholded_sp2(pins.water(n_mol, seed))
