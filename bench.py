@@ -116,21 +116,22 @@ def kernel_name(precision, form):
         return "k_sp2_step64"
     if form == "t256" or (form == "auto" and precision != "fp32"):
         return "k_sp2_wide"
-    return "k_sp2_step_skip" if form == "t128_skip" else "k_sp2_step"
+    # the library's untuned FP32 form is the skip form
+    return "k_sp2_step_skip" if form == "t128_skip" or form == "auto" else "k_sp2_step"
 
 
-def counter_traffic(precision, workload, kernel=None):
-    """HBM bytes per product launch from the committed rocprofv3 counter record,
-    or None when the record was taken on another workload (molecules, parts,
-    tau, sum of s^3) or product kernel, or the kernel or planner sources
-    changed since."""
+def counter_traffic(precision, workload, kernel):
+    """HBM bytes per launch of the product kernel `kernel` at `precision` from
+    the committed rocprofv3 counter record, or None when the record holds no
+    such kernel, was taken on another workload (molecules, parts, tau, sum of
+    s^3), or the kernel or planner sources changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_sp2_step_counters.json")
     try:
-        rec = json.load(open(path))[precision]
+        rec = json.load(open(path))[f"{precision}/{kernel}"]
     except (OSError, KeyError, ValueError):
         return None
-    if rec.get("match") != workload or (kernel is not None and rec.get("kernel") != kernel):
+    if rec.get("match") != workload:
         return None
     h = hashlib.sha256()
     for f in rec["sources"]:
@@ -567,15 +568,23 @@ def bench_water(args, g, torch):
                         device="cuda")
     col_ptr, _ = g.gsp2_plan_pattern(plan)
 
-    # the first run finds where the stop rule fires; later runs form exactly
-    # that many products (the same stop fires at the same product), so no
-    # empty launches follow the stop
+    # the kernel autotuner's form for the headline precision, timed on this plan
+    head_tune = None
+    if not args.no_tune and args.precision != "fp64":
+        with torch.cuda.stream(stream):
+            head_tune = g.gsp2_plan_tune(plan, Hd, n_occ, args.precision, n_products=6)
+        log(f"kernel autotuner: {head_tune}")
+    head_form = head_tune["chosen"] if head_tune else args.kernel
+    # the first run, in the form the timed runs take, finds where the stop
+    # rule fires; later runs form exactly that many products (the same stop
+    # fires at the same product), so no empty launches follow the stop
     if saved is not None:
         n_prod = int(saved["n_products"])
         alphas = None
     else:
         with torch.cuda.stream(stream):
-            first = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=args.max_iter, precision=args.precision)
+            first = g.gsp2_density(plan, Hd, n_occ, P_val, max_iter=args.max_iter, precision=args.precision,
+                                   kernel=head_form)
         n_prod = first["n_products"]
         alphas = first["alpha"]
         log(f"first run: status {first['status_name']}, {n_prod} products, Tr P = {first['trace']:.6f}")
@@ -584,13 +593,6 @@ def bench_water(args, g, torch):
             d = dict(z)
         np.savez(args.save_state, n_products=n_prod, **d)
         log(f"state saved to {args.save_state}")
-    # the kernel autotuner's form for the headline precision, timed on this plan
-    head_tune = None
-    if not args.no_tune and args.precision != "fp64":
-        with torch.cuda.stream(stream):
-            head_tune = g.gsp2_plan_tune(plan, Hd, n_occ, args.precision, n_products=6)
-        log(f"kernel autotuner: {head_tune}")
-    head_form = head_tune["chosen"] if head_tune else args.kernel
     timed = not args.no_kernel_timing
     kw = dict(max_iter=n_prod, precision=args.precision, timing=timed, kernel=head_form)
     wall, timings, last = timed_runs(g, torch, plan, Hd, n_occ, P_val, args.steps, args.warmup, stream, **kw)

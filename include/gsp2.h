@@ -70,19 +70,20 @@ typedef enum {
 /* Forms of the product kernel; gsp2_plan_tune times them on a plan's own
  * sub-problems and keeps the fastest per precision.  All forms of one
  * precision give the same arithmetic.  T128 and T128_SKIP give the same bits
- * for FP32, FP16 and BF16 operands; with split FP16 operands the formed
- * quarter of a diagonal tile sums its two cross terms in the other order
- * than the skipped quarter would, so the two agree to FP32 rounding (and
- * T128_SKIP's iterates are exactly symmetric there, T128's to rounding). */
+ * for FP32, FP16 and BF16 operands; with split FP16 operands a block above
+ * the diagonal of a diagonal tile sums its two cross terms in the other
+ * order than the block below it, so there the two forms agree to FP32
+ * rounding (T128_SKIP mirrors the block above, T128 forms both). */
 typedef enum {
     GSP2_KERNEL_AUTO = 0,      /* the form gsp2_plan_tune kept for the precision, else the default:
-                                  T128 for FP32 and FP64 products, T256 for 16-bit ones */
+                                  T128_SKIP for FP32 products, T128 for FP64, T256 for 16-bit ones */
     GSP2_KERNEL_T128 = 1,      /* 128 x 128 product tiles, two workgroups per CU, every 32 x 32
                                   block of the padded tile formed */
-    GSP2_KERNEL_T128_SKIP = 2, /* 128 x 128 tiles; 32-row (column) blocks lying wholly in the zero
-                                  padding, and the lower-left quarter of a diagonal tile (the
-                                  transpose of the upper-right one), form no products.  Not for
-                                  FP64 products. */
+    GSP2_KERNEL_T128_SKIP = 2, /* 128 x 128 tiles; 32 x 32 blocks lying wholly in the zero padding,
+                                  and the blocks below the diagonal of a diagonal tile (transposes
+                                  of blocks above it), form no products, and the blocks a tile
+                                  forms are dealt evenly to its four waves.  Not for FP64
+                                  products. */
     GSP2_KERNEL_T256 = 3       /* 256 x 256 tiles, one workgroup per CU; 16-bit operands only */
 } gsp2_kernel;
 

@@ -1022,7 +1022,8 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     else if (plan->kernel_tuned[o.precision])
         rp.kernel = plan->kernel_tuned[o.precision];
     else
-        rp.kernel = wide16 ? GSP2_KERNEL_T256 : GSP2_KERNEL_T128;
+        rp.kernel = wide16 ? GSP2_KERNEL_T256
+                           : o.precision == GSP2_PREC_FP64 ? GSP2_KERNEL_T128 : GSP2_KERNEL_T128_SKIP;
     rp.refine_prec = o.precision == GSP2_PREC_FP64 ? GSP2_PREC_FP64 : GSP2_PREC_FP32;
     if (o.refine_precision == GSP2_PREC_FP16X3) {
         if (o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16)
@@ -1036,7 +1037,7 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     else if (o.precision == GSP2_PREC_FP64)
         rp.kernel32 = GSP2_KERNEL_T128;
     else
-        rp.kernel32 = plan->kernel_tuned[GSP2_PREC_FP32] ? plan->kernel_tuned[GSP2_PREC_FP32] : GSP2_KERNEL_T128;
+        rp.kernel32 = plan->kernel_tuned[GSP2_PREC_FP32] ? plan->kernel_tuned[GSP2_PREC_FP32] : GSP2_KERNEL_T128_SKIP;
     if (rp.persistent && (n_sys > 1 || (rp.precision != GSP2_PREC_FP32 && rp.precision != GSP2_PREC_FP16 &&
                                          rp.precision != GSP2_PREC_BF16)))
         fail(GSP2_E_UNSUPPORTED, "the persistent product launch takes one system and FP32, FP16 or BF16 products");

@@ -649,25 +649,63 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     } while (0)
     // kSkip: work the matrix cores can leave out, exactly (wave-uniform):
     //  * a 32-row (or 32-column) block that starts at or beyond s lies in the
-    //    zero padding, so its products are zero and its accumulator stays 0
-    //    (the epilogue still writes those zeros: padding must stay zero);
-    //  * in a diagonal tile the lower-left wave's 64 x 64 block is the
-    //    transpose of the upper-right wave's (the same products in the same
-    //    order), so that wave forms no products and the upper-right wave
-    //    writes both; likewise, in each of the two waves on the diagonal, the
-    //    lower-left 32 x 32 block is the transpose of the upper-right one.
-    // The choice is made once per tile: each wave runs a straight-line K loop
-    // of its kind (all four blocks; three, on the diagonal; only those that
-    // reach into s, on edge tiles; none), so no branch sits among the MFMAs.
+    //    zero padding, so its products are zero (the epilogue still writes
+    //    those zeros: padding must stay zero);
+    //  * in a diagonal tile a 32 x 32 block below the diagonal is the
+    //    transpose of the block above it (the same products in the same
+    //    order), so it is not formed and the block above writes both.
+    // A full off-diagonal tile keeps the 2 x 2 wave grid.  Any other tile
+    // deals the blocks it must form to the four waves, so the waves carry
+    // equal work and the tile takes as long as its largest share (at most 3
+    // of the 4 blocks a wave of the grid forms: a diagonal tile has 10, an
+    // edge tile at most 12): off the diagonal, round robin in row-major
+    // order; in a diagonal tile the 32 x 32 blocks on the diagonal stay with
+    // the waves that hold them in the grid (0 and 3, so the FP64 trace
+    // partials are summed in the grid's order and both forms give the same
+    // bits), and each other block goes to the least loaded wave (the lowest
+    // on ties).  The choice is made once per tile: each wave runs a
+    // straight-line K loop for its block count, so no branch sits among the
+    // MFMAs.
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    const bool mirror_wave = kSkip && diag && (wv >> 1) == 1 && (wv & 1) == 0;
-    const bool diag_wave = kSkip && diag && (wv >> 1) == (wv & 1);
-    const bool actA[2] = {!mirror_wave && I0 + (wv >> 1) * 64 < pd.s, !mirror_wave && I0 + (wv >> 1) * 64 + 32 < pd.s};
-    const bool actB[2] = {J0 + (wv & 1) * 64 < pd.s, J0 + (wv & 1) * 64 + 32 < pd.s};
-    const bool all_active = actA[0] && actA[1] && actB[0] && actB[1];
-    const bool any_active = (actA[0] || actA[1]) && (actB[0] || actB[1]);
-    // kind 0: all four blocks; 1: the blocks that reach into s (edge tiles);
-    // 2: none; 3: all but the lower-left block (diagonal waves)
+    const bool grid_tile = !kSkip || (!diag && I0 + 96 < pd.s && J0 + 96 < pd.s);
+    int g_r[3] = {-1, -1, -1}, g_c[3] = {-1, -1, -1};
+    int n_mine = 0;
+    auto take = [&](int r, int c) __attribute__((always_inline)) {
+        if (n_mine == 0) { g_r[0] = r; g_c[0] = c; }
+        else if (n_mine == 1) { g_r[1] = r; g_c[1] = c; }
+        else { g_r[2] = r; g_c[2] = c; }
+        ++n_mine;
+    };
+    if (!grid_tile) {
+        if (!diag) {
+            int u = 0;
+            for (int r = 0; r < 4; ++r)
+                for (int c = 0; c < 4; ++c)
+                    if (I0 + 32 * r < pd.s && J0 + 32 * c < pd.s) {
+                        if ((u & 3) == wv) take(r, c);
+                        ++u;
+                    }
+        } else {
+            int l0 = 0, l1 = 0, l2 = 0, l3 = 0;     // blocks dealt to each wave
+            for (int d = 0; d < 4; ++d)
+                if (I0 + 32 * d < pd.s) {
+                    if (d < 2) { ++l0; if (wv == 0) take(d, d); }
+                    else { ++l3; if (wv == 3) take(d, d); }
+                }
+            for (int r = 0; r < 4; ++r)
+                for (int c = r + 1; c < 4; ++c)
+                    if (I0 + 32 * c < pd.s) {
+                        int w = 0, lw = l0;
+                        if (l1 < lw) { w = 1; lw = l1; }
+                        if (l2 < lw) { w = 2; lw = l2; }
+                        if (l3 < lw) { w = 3; lw = l3; }
+                        if (w == 0) ++l0; else if (w == 1) ++l1; else if (w == 2) ++l2; else ++l3;
+                        if (w == wv) take(r, c);
+                    }
+        }
+    }
+    // kind 0: the wave's 2 x 2 blocks of the grid; 2: none; 3 + M: the wave's
+    // M dealt blocks (slot j in acc[j / 2][j % 2])
     auto compute_kind = [&](int buf, auto kind) __attribute__((always_inline)) {
         constexpr int K = decltype(kind)::value;
         if constexpr (K == 2) return;
@@ -675,29 +713,34 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
         const uint4 *Bsb = lds(buf, 1);
         // interleave the LDS fragment reads with the MFMAs (3.5% faster FP32
         // products than the default schedule, measured)
-        if constexpr (K != 1) __builtin_amdgcn_iglp_opt(1);
+        __builtin_amdgcn_iglp_opt(1);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             // FP32: word kh*4+q of the row (k = 16 kh + 4 q + e); 16-bit: word 2q+kh (k = 16 q + 8 kh + e)
             const int w = kF32 ? kh * 4 + q : 2 * q + kh;
-            uint4 fa[2], fb[2];
+            if constexpr (K == 0) {
+                uint4 fa[2], fb[2];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
-                fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
-            }
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-                for (int nn = 0; nn < 2; ++nn) {
-                    if constexpr (K == 3) {
-                        if (m == 1 && nn == 0) continue;
-                    }
-                    if constexpr (K == 1) {
-                        if (!(actA[m] && actB[nn]) || (diag_wave && m == 1 && nn == 0)) continue;
-                    }
-                    acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
+                for (int m = 0; m < 2; ++m) {
+                    fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
+                    fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
                 }
+#pragma unroll
+                for (int m = 0; m < 2; ++m)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], Op{});
+            } else if constexpr (K >= 4) {
+                constexpr int M = K - 3;
+                uint4 fa[M], fb[M];
+#pragma unroll
+                for (int j = 0; j < M; ++j) {
+                    fa[j] = Asb[(g_r[j] * 32 + l32) * kLdsRow + w];
+                    fb[j] = Bsb[(g_c[j] * 32 + l32) * kLdsRow + w];
+                }
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    acc[j >> 1][j & 1] = mfma_chunk_q(fa[j], fb[j], acc[j >> 1][j & 1], Op{});
+            }
         }
     };
     auto kloop = [&](auto kind) __attribute__((always_inline)) {
@@ -727,10 +770,11 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     if constexpr (!kSkip) {
         kloop(std::integral_constant<int, 0>{});
     } else {
-        if (mirror_wave || !any_active) kloop(std::integral_constant<int, 2>{});
-        else if (!all_active) kloop(std::integral_constant<int, 1>{});
-        else if (diag_wave) kloop(std::integral_constant<int, 3>{});
-        else kloop(std::integral_constant<int, 0>{});
+        if (grid_tile) kloop(std::integral_constant<int, 0>{});
+        else if (n_mine == 0) kloop(std::integral_constant<int, 2>{});
+        else if (n_mine == 1) kloop(std::integral_constant<int, 4>{});
+        else if (n_mine == 2) kloop(std::integral_constant<int, 5>{});
+        else kloop(std::integral_constant<int, 6>{});
     }
 #undef GSP2_SRC
 #undef GSP2_LD
@@ -742,66 +786,81 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // the epilogue adds D O + O D + D^2 in FP32, (d_r + d_c) X_rc off the
     // diagonal and d_r^2 on it, so the diagonal is never rounded.
     constexpr bool kExactDiag = !kF32 && !kSplit;
-    // the mirrored writes: every off-diagonal tile; in the kSkip form also
-    // the upper-right wave of a diagonal tile, for the lower-left one, and
-    // the upper-right block of each diagonal wave, for its lower-left one
-    const bool upper_right_wave = kSkip && diag && (wv >> 1) == 0 && (wv & 1) == 1;
     double tY = 0.0, tX = 0.0;
+    // one 32 x 32 block of the tile (its first row and column within the
+    // tile: ro, co) from its accumulator, written at its place and, with
+    // write_mirror, transposed at the mirrored place
+    auto emit_block = [&](const v16f &a, int ro, int co, bool write_mirror) __attribute__((always_inline)) {
+        const int cg = J0 + co + l32;
+        const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
 #pragma unroll
-    for (int m = 0; m < 2; ++m) {
+        for (int g = 0; g < 4; ++g) {
+            const int rg0 = I0 + ro + g * 8 + kh * 4;
+            float xn[4];
 #pragma unroll
-        for (int nn = 0; nn < 2; ++nn) {
-            if (mirror_wave) continue;
-            if (diag_wave && m == 1 && nn == 0) continue;
-            const bool write_mirror = !diag || upper_right_wave || (diag_wave && m == 0 && nn == 1);
-            const int cg = J0 + wc * 64 + nn * 32 + l32;
-            const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int rg0 = I0 + wr * 64 + m * 32 + g * 8 + kh * 4;
-                float xn[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int rg = rg0 + e;
-                    const float yacc = acc[m][nn][4 * g + e];
-                    const float xo = X[(int64_t)rg * ld + cg];
-                    float y = yacc;
-                    if constexpr (kExactDiag) {
-                        const float dr = X[(int64_t)rg * (ld + 1)];
-                        y = rg == cg ? yacc + dr * dr : yacc + (dr + dc) * xo;
-                    }
-                    const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
-                    xn[e] = v;
-                    Xn[(int64_t)rg * ld + cg] = v;
-                    if constexpr (!kF32) {
-                        const Op h = (kExactDiag && rg == cg) ? static_cast<Op>(0.0f) : static_cast<Op>(v);
-                        Xnop[(int64_t)rg * ld + cg] = h;
-                        if constexpr (kSplit)
-                            Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
-                    }
-                    if (diag && rg == cg && rg < pd.c) {
-                        tY += static_cast<double>(y);
-                        tX += static_cast<double>(v);
-                    }
+            for (int e = 0; e < 4; ++e) {
+                const int rg = rg0 + e;
+                const float yacc = a[4 * g + e];
+                const float xo = X[(int64_t)rg * ld + cg];
+                float y = yacc;
+                if constexpr (kExactDiag) {
+                    const float dr = X[(int64_t)rg * (ld + 1)];
+                    // explicit FMAs: every inlined copy of this epilogue rounds alike
+                    y = rg == cg ? __builtin_fmaf(dr, dr, yacc) : __builtin_fmaf(dr + dc, xo, yacc);
                 }
-                if (write_mirror) {
-                    const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
-                    *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
-                    if constexpr (!kF32) {
-                        union { Op h[4]; uint2 u; } pk, pl;
+                const float v = alpha > 0.0f ? (2.0f * xo - y) : y;
+                xn[e] = v;
+                Xn[(int64_t)rg * ld + cg] = v;
+                if constexpr (!kF32) {
+                    const Op h = (kExactDiag && rg == cg) ? static_cast<Op>(0.0f) : static_cast<Op>(v);
+                    Xnop[(int64_t)rg * ld + cg] = h;
+                    if constexpr (kSplit)
+                        Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
+                }
+                if (diag && rg == cg && rg < pd.c) {
+                    tY += static_cast<double>(y);
+                    tX += static_cast<double>(v);
+                }
+            }
+            if (write_mirror) {
+                const float4 v4 = make_float4(xn[0], xn[1], xn[2], xn[3]);
+                *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = v4;
+                if constexpr (!kF32) {
+                    union { Op h[4]; uint2 u; } pk, pl;
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
-                        *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
-                        if constexpr (kSplit) {
+                    for (int e = 0; e < 4; ++e) pk.h[e] = static_cast<Op>(xn[e]);
+                    *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = pk.u;
+                    if constexpr (kSplit) {
 #pragma unroll
-                            for (int e = 0; e < 4; ++e)
-                                pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
-                            *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
-                        }
+                        for (int e = 0; e < 4; ++e)
+                            pl.h[e] = static_cast<Op>((xn[e] - static_cast<float>(pk.h[e])) * 0x1p11f);
+                        *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = pl.u;
                     }
                 }
             }
         }
+    };
+    if (grid_tile) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int nn = 0; nn < 2; ++nn) emit_block(acc[m][nn], wr * 64 + m * 32, wc * 64 + nn * 32, !diag);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j < n_mine) emit_block(acc[j >> 1][j & 1], 32 * g_r[j], 32 * g_c[j], !diag || g_r[j] < g_c[j]);
+        // the padding blocks of the tile (both triangles of a diagonal tile),
+        // dealt round robin: zero products, so the zeros the grid writes
+        v16f zero;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) zero[i] = 0.0f;
+        int k = 0;
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                if (I0 + 32 * r < pd.s && J0 + 32 * c < pd.s) continue;
+                if ((k & 3) == wv) emit_block(zero, 32 * r, 32 * c, !diag);
+                ++k;
+            }
     }
     if (diag) {
         block_sum2(tY, tX);
@@ -1279,7 +1338,8 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
                         if constexpr (!kSplit) {
                             const int rl = wr * 128 + m * 32 + g * 8 + kh * 4 + e, cl = wc * 128 + nn * 32 + l32;
                             const float dr = d_row[rl];
-                            y = (diag && rl == cl) ? y + dr * dr : y + (dr + d_col[cl]) * xov[e];
+                            y = (diag && rl == cl) ? __builtin_fmaf(dr, dr, y)
+                                                   : __builtin_fmaf(dr + d_col[cl], xov[e], y);
                         }
                         const float v = upd ? (2.0f * xov[e] - y) : y;
                         xn[e] = v;

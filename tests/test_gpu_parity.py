@@ -244,13 +244,14 @@ def test_16bit_products_on_128_tiles(precision):
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16", "fp16x3"])
 @pytest.mark.parametrize("n_mol,seed,n_parts,tau", [(64, 0, 8, 1e-3), (200, 1, 6, 1e-4), (8, 0, 8, 1e-2)])
 def test_skip_form_gives_the_same_bits(precision, n_mol, seed, n_parts, tau):
-    # the skipped 32-row blocks lie wholly in the zero padding and the
-    # skipped diagonal-tile quarter is the transpose of a formed one, so the
-    # two 128-tile forms give the same P, branch sequence and traces bit for
-    # bit (8 molecules in 8 parts: 6-orbital cores padded to 128, where all
-    # but one 32-row block is padding).  Split FP16 is the exception: the
-    # formed quarter sums its two cross terms in the other order than the
-    # skipped one would, so the two forms agree to FP32 rounding.
+    # the skipped 32 x 32 blocks lie wholly in the zero padding or below the
+    # diagonal of a diagonal tile (transposes of formed ones), and a block
+    # formed by another wave is formed alike, so the two 128-tile forms give
+    # the same P, branch sequence and traces bit for bit (8 molecules in 8
+    # parts: 6-orbital cores padded to 128, where all but one 32-row block is
+    # padding).  Split FP16 is the exception: a block above the diagonal sums
+    # its two cross terms in the other order than the block below it, so the
+    # two forms agree to FP32 rounding.
     from tests._gpu import rel_fro, run_gsp2
     s = pins.water(n_mol, seed)
     Pp = _dense_prev(s)
