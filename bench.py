@@ -116,8 +116,7 @@ def kernel_name(precision, form):
         return "k_sp2_step64"
     if form == "t256" or (form == "auto" and precision != "fp32"):
         return "k_sp2_wide"
-    # the library's untuned FP32 form is the skip form
-    return "k_sp2_step_skip" if form == "t128_skip" or form == "auto" else "k_sp2_step"
+    return "k_sp2_step_skip" if form == "t128_skip" else "k_sp2_step"
 
 
 def counter_traffic(precision, workload, kernel):

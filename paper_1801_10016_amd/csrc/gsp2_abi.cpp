@@ -799,6 +799,11 @@ gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int3
             ms[c] = t.n_products > 0 ? sum / t.n_products : 0.0;
             if (ms[c] < ms[best]) best = c;
         }
+        // another form replaces the default only when it is more than 2% faster
+        // (beyond the run-to-run spread): forms of equal speed can differ in
+        // their HBM traffic, and the default is the one with the least
+        const int dflt = wide16 ? 2 : 0;
+        if (ms[best] > 0.98 * ms[dflt]) best = dflt;
         plan->kernel_tuned[precision] = cand[best];
         if (info) {
             std::memset(info, 0, sizeof(*info));
@@ -1022,8 +1027,7 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     else if (plan->kernel_tuned[o.precision])
         rp.kernel = plan->kernel_tuned[o.precision];
     else
-        rp.kernel = wide16 ? GSP2_KERNEL_T256
-                           : o.precision == GSP2_PREC_FP64 ? GSP2_KERNEL_T128 : GSP2_KERNEL_T128_SKIP;
+        rp.kernel = wide16 ? GSP2_KERNEL_T256 : GSP2_KERNEL_T128;
     rp.refine_prec = o.precision == GSP2_PREC_FP64 ? GSP2_PREC_FP64 : GSP2_PREC_FP32;
     if (o.refine_precision == GSP2_PREC_FP16X3) {
         if (o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16)
@@ -1037,7 +1041,7 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     else if (o.precision == GSP2_PREC_FP64)
         rp.kernel32 = GSP2_KERNEL_T128;
     else
-        rp.kernel32 = plan->kernel_tuned[GSP2_PREC_FP32] ? plan->kernel_tuned[GSP2_PREC_FP32] : GSP2_KERNEL_T128_SKIP;
+        rp.kernel32 = plan->kernel_tuned[GSP2_PREC_FP32] ? plan->kernel_tuned[GSP2_PREC_FP32] : GSP2_KERNEL_T128;
     if (rp.persistent && (n_sys > 1 || (rp.precision != GSP2_PREC_FP32 && rp.precision != GSP2_PREC_FP16 &&
                                          rp.precision != GSP2_PREC_BF16)))
         fail(GSP2_E_UNSUPPORTED, "the persistent product launch takes one system and FP32, FP16 or BF16 products");
