@@ -429,7 +429,7 @@ typedef struct {
  * GSP2_KERNEL_T128 and T128_SKIP; 16-bit products T128, T128_SKIP and T256.
  * Keeps the form with the lowest mean product time for `precision`, except
  * that another form replaces the default (GSP2_KERNEL_AUTO's) only when it is
- * more than 2% faster, since forms of equal speed can differ in HBM traffic
+ * more than 1% faster, since forms of equal speed can differ in HBM traffic
  * and the default moves the least; gsp2_density then uses it for that precision unless the run names a form
  * or (16-bit products) the plan was created with a fixed tile16.  The
  * products replay alternating branches (X^2, 2X - X^2, ...), so every

@@ -187,7 +187,7 @@ struct gsp2_plan_s {
     std::vector<int64_t> sub_ptr;
     std::vector<int32_t> sub_idx, core_count;
     std::vector<PartDesc> desc;
-    std::vector<TileDesc> tiles, tiles_w;
+    std::vector<TileDesc> tiles, tiles_s, tiles_w;
     std::vector<RowChunk> chunks;
     std::vector<int32_t> perm;
     std::vector<int64_t> col_ptr;
@@ -499,34 +499,50 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             }
             sys_diag_ptr[y + 1] = slot;
         }
-        // the tiles of one unit at tile edge `edge` (blocks of kBlockRows / edge tiles)
-        auto unit_tiles = [&](const Unit &u, int edge, int diag_step, std::vector<TileDesc> &out) {
+        // the tiles of one unit at tile edge `edge` (blocks of kBlockRows / edge
+        // tiles).  With short_last (the skip form's list), the unit's full
+        // off-diagonal tiles come first and its diagonal tiles and tiles
+        // reaching past s - 32 (those the skip form forms in part) after them:
+        // a short tile ends early, and amid full ones it would put the
+        // workgroups that share an XCD's L2 out of step with the panel chunks
+        // they read together.
+        auto unit_tiles = [&](const Unit &u, int edge, int diag_step, bool short_last, std::vector<TileDesc> &out) {
             const int32_t k = u.k;
+            const int s_k = plan->desc[k].s;
             const int nt = (plan->desc[k].s_pad + edge - 1) / edge;
             const int tb = kBlockRows / edge;
             const int b_lo = u.bi < 0 ? 0 : u.bi, b_hi = u.bi < 0 ? (nt + tb - 1) / tb : u.bi + 1;
-            for (int BI = b_lo; BI < b_hi; ++BI) {
-                const int c_lo = u.bi < 0 ? BI : u.bj, c_hi = u.bi < 0 ? (nt + tb - 1) / tb : u.bj + 1;
-                for (int BJ = c_lo; BJ < c_hi; ++BJ)
-                    for (int ti = BI * tb; ti < std::min((BI + 1) * tb, nt); ++ti)
-                        for (int tj = std::max(ti, BJ * tb); tj < std::min((BJ + 1) * tb, nt); ++tj)
-                            out.push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + diag_step * ti : -1});
-            }
+            for (int pass = 0; pass < (short_last ? 2 : 1); ++pass)
+                for (int BI = b_lo; BI < b_hi; ++BI) {
+                    const int c_lo = u.bi < 0 ? BI : u.bj, c_hi = u.bi < 0 ? (nt + tb - 1) / tb : u.bj + 1;
+                    for (int BJ = c_lo; BJ < c_hi; ++BJ)
+                        for (int ti = BI * tb; ti < std::min((BI + 1) * tb, nt); ++ti)
+                            for (int tj = std::max(ti, BJ * tb); tj < std::min((BJ + 1) * tb, nt); ++tj) {
+                                const bool full = ti != tj && (tj + 1) * edge - 32 < s_k;
+                                if (short_last && full != (pass == 0)) continue;
+                                out.push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + diag_step * ti : -1});
+                            }
+                }
         };
-        std::vector<std::vector<TileDesc>> lists(kXcds);
+        std::vector<std::vector<TileDesc>> lists(kXcds), lists_s(kXcds);
         for (int x = 0; x < kXcds; ++x)
-            for (const Unit &u : xcd_units[x]) unit_tiles(u, T, 1, lists[x]);
+            for (const Unit &u : xcd_units[x]) {
+                unit_tiles(u, T, 1, false, lists[x]);
+                unit_tiles(u, T, 1, true, lists_s[x]);
+            }
         size_t longest = 0;
         for (auto &l : lists) longest = std::max(longest, l.size());
         for (size_t q = 0; q < longest; ++q)
-            for (int x = 0; x < kXcds; ++x)
+            for (int x = 0; x < kXcds; ++x) {
                 plan->tiles.push_back(q < lists[x].size() ? lists[x][q] : TileDesc{-1, 0, 0, -1});
+                plan->tiles_s.push_back(q < lists_s[x].size() ? lists_s[x][q] : TileDesc{-1, 0, 0, -1});
+            }
         // The same units for the 256 x 256 tiles of the 16-bit products, in
         // blocks of 4 x 4 (the same panels as 8 x 8 blocks of 128-tiles).  A
         // diagonal 256-tile covers 128-tile diagonal slots 2t and 2t + 1.
         std::vector<std::vector<TileDesc>> lists_w(kXcds);
         for (int x = 0; x < kXcds; ++x)
-            for (const Unit &u : xcd_units[x]) unit_tiles(u, kTileWide, 2, lists_w[x]);
+            for (const Unit &u : xcd_units[x]) unit_tiles(u, kTileWide, 2, false, lists_w[x]);
         longest = 0;
         for (auto &l : lists_w) longest = std::max(longest, l.size());
         for (size_t q = 0; q < longest; ++q)
@@ -587,6 +603,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         dp.buf[1] = plan->alloc<float>(plan->arena_floats, "X buffer 1");
         auto *d_parts = plan->alloc<PartDesc>(n_parts, "part descriptors");
         auto *d_tiles = plan->alloc<TileDesc>(plan->tiles.size(), "tiles");
+        auto *d_tiles_s = plan->alloc<TileDesc>(plan->tiles_s.size(), "tiles, short ones last");
         auto *d_tiles_w = plan->alloc<TileDesc>(plan->tiles_w.size(), "wide tiles");
         auto *d_chunks = plan->alloc<RowChunk>(plan->chunks.size(), "row chunks");
         auto *d_idx = plan->alloc<int32_t>(plan->sub_idx.size(), "index arena");
@@ -631,6 +648,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         dp.sys_diag_ptr = d_sys_diag_ptr;
         upload(d_parts, plan->desc, s, "upload parts");
         upload(d_tiles, plan->tiles, s, "upload tiles");
+        upload(d_tiles_s, plan->tiles_s, s, "upload tiles, short ones last");
         upload(d_tiles_w, plan->tiles_w, s, "upload wide tiles");
         upload(d_chunks, plan->chunks, s, "upload chunks");
         upload(d_idx, plan->sub_idx, s, "upload index");
@@ -641,6 +659,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         check_hip(hipMemsetAsync(dp.state, 0, sizeof(RunState) * (size_t)n_sys, s), "clear state");
         dp.parts = d_parts;
         dp.tiles = d_tiles;
+        dp.tiles_s = d_tiles_s;
         dp.tiles_w = d_tiles_w;
         dp.n_tiles_w = (int32_t)plan->tiles_w.size();
         dp.chunks = d_chunks;
@@ -799,11 +818,11 @@ gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int3
             ms[c] = t.n_products > 0 ? sum / t.n_products : 0.0;
             if (ms[c] < ms[best]) best = c;
         }
-        // another form replaces the default only when it is more than 2% faster
+        // another form replaces the default only when it is more than 1% faster
         // (beyond the run-to-run spread): forms of equal speed can differ in
         // their HBM traffic, and the default is the one with the least
         const int dflt = wide16 ? 2 : 0;
-        if (ms[best] > 0.98 * ms[dflt]) best = dflt;
+        if (ms[best] > 0.99 * ms[dflt]) best = dflt;
         plan->kernel_tuned[precision] = cand[best];
         if (info) {
             std::memset(info, 0, sizeof(*info));

@@ -2080,12 +2080,13 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
     // the product kernel of form `form` with operands of `prec` (phase 0 or 1)
     auto product = [&](int form, int prec, int phase) {
         const bool skip = form == GSP2_KERNEL_T128_SKIP;
+        const TileDesc *tl = skip ? dp.tiles_s : dp.tiles;     // the skip form's order: short tiles last
         if (prec == GSP2_PREC_FP64) {
             record(rec, k_sp2_step64, grid, blk, dp.tiles, dp.parts, dp.buf64[0], dp.buf64[1], dp.state,
                    dp.diag_partials, phase);
         } else if (prec == GSP2_PREC_FP32) {
             auto k = skip ? k_sp2_step<float, false, true> : k_sp2_step<float, false, false>;
-            record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, (float *)nullptr, (float *)nullptr, dp.state,
+            record(rec, k, grid, blk, tl, dp.parts, b0, b1, (float *)nullptr, (float *)nullptr, dp.state,
                    dp.diag_partials, phase, (float *)nullptr, (float *)nullptr);
         } else if (form == GSP2_KERNEL_T256) {
             if (prec == GSP2_PREC_FP16)
@@ -2099,15 +2100,15 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
                        b16[1], dp.state, dp.diag_partials, (__bf16 *)nullptr, (__bf16 *)nullptr, phase);
         } else if (prec == GSP2_PREC_FP16) {
             auto k = skip ? k_sp2_step<_Float16, false, true> : k_sp2_step<_Float16, false, false>;
-            record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1], dp.state, dp.diag_partials,
+            record(rec, k, grid, blk, tl, dp.parts, b0, b1, h16[0], h16[1], dp.state, dp.diag_partials,
                    phase, (_Float16 *)nullptr, (_Float16 *)nullptr);
         } else if (prec == GSP2_PREC_FP16X3) {
             auto k = skip ? k_sp2_step<_Float16, true, true> : k_sp2_step<_Float16, true, false>;
-            record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, h16[0], h16[1], dp.state, dp.diag_partials,
+            record(rec, k, grid, blk, tl, dp.parts, b0, b1, h16[0], h16[1], dp.state, dp.diag_partials,
                    phase, l16[0], l16[1]);
         } else {
             auto k = skip ? k_sp2_step<__bf16, false, true> : k_sp2_step<__bf16, false, false>;
-            record(rec, k, grid, blk, dp.tiles, dp.parts, b0, b1, b16[0], b16[1], dp.state, dp.diag_partials,
+            record(rec, k, grid, blk, tl, dp.parts, b0, b1, b16[0], b16[1], dp.state, dp.diag_partials,
                    phase, (__bf16 *)nullptr, (__bf16 *)nullptr);
         }
     };
