@@ -116,7 +116,8 @@ def kernel_name(precision, form):
         return "k_sp2_step64"
     if form == "t256" or (form == "auto" and precision != "fp32"):
         return "k_sp2_wide"
-    return "k_sp2_step_skip" if form == "t128_skip" else "k_sp2_step"
+    # the library's untuned FP32 form is the skip form
+    return "k_sp2_step_skip" if form in ("t128_skip", "auto") else "k_sp2_step"
 
 
 def counter_traffic(precision, workload, kernel):

@@ -76,7 +76,7 @@ typedef enum {
  * rounding (T128_SKIP mirrors the block above, T128 forms both). */
 typedef enum {
     GSP2_KERNEL_AUTO = 0,      /* the form gsp2_plan_tune kept for the precision, else the default:
-                                  T128 for FP32 and FP64 products, T256 for 16-bit ones */
+                                  T128_SKIP for FP32 products, T128 for FP64, T256 for 16-bit ones */
     GSP2_KERNEL_T128 = 1,      /* 128 x 128 product tiles, two workgroups per CU, every 32 x 32
                                   block of the padded tile formed */
     GSP2_KERNEL_T128_SKIP = 2, /* 128 x 128 tiles; 32 x 32 blocks lying wholly in the zero padding,
@@ -429,8 +429,7 @@ typedef struct {
  * GSP2_KERNEL_T128 and T128_SKIP; 16-bit products T128, T128_SKIP and T256.
  * Keeps the form with the lowest mean product time for `precision`, except
  * that another form replaces the default (GSP2_KERNEL_AUTO's) only when it is
- * more than 1% faster, since forms of equal speed can differ in HBM traffic
- * and the default moves the least; gsp2_density then uses it for that precision unless the run names a form
+ * more than 1% faster, so that near ties keep the default; gsp2_density then uses it for that precision unless the run names a form
  * or (16-bit products) the plan was created with a fixed tile16.  The
  * products replay alternating branches (X^2, 2X - X^2, ...), so every
  * product carries the same work as in a run; the trace check of those runs

@@ -500,36 +500,37 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
             sys_diag_ptr[y + 1] = slot;
         }
         // the tiles of one unit at tile edge `edge` (blocks of kBlockRows / edge
-        // tiles).  With short_last (the skip form's list), the unit's full
-        // off-diagonal tiles come first and its diagonal tiles and tiles
-        // reaching past s - 32 (those the skip form forms in part) after them:
-        // a short tile ends early, and amid full ones it would put the
-        // workgroups that share an XCD's L2 out of step with the panel chunks
-        // they read together.
-        auto unit_tiles = [&](const Unit &u, int edge, int diag_step, bool short_last, std::vector<TileDesc> &out) {
+        // tiles): all of them (which = 0), only the full off-diagonal ones
+        // (1), or only the diagonal tiles and those reaching past s - 32, the
+        // tiles the skip form forms in part (2).
+        auto unit_tiles = [&](const Unit &u, int edge, int diag_step, int which, std::vector<TileDesc> &out) {
             const int32_t k = u.k;
             const int s_k = plan->desc[k].s;
             const int nt = (plan->desc[k].s_pad + edge - 1) / edge;
             const int tb = kBlockRows / edge;
             const int b_lo = u.bi < 0 ? 0 : u.bi, b_hi = u.bi < 0 ? (nt + tb - 1) / tb : u.bi + 1;
-            for (int pass = 0; pass < (short_last ? 2 : 1); ++pass)
-                for (int BI = b_lo; BI < b_hi; ++BI) {
-                    const int c_lo = u.bi < 0 ? BI : u.bj, c_hi = u.bi < 0 ? (nt + tb - 1) / tb : u.bj + 1;
-                    for (int BJ = c_lo; BJ < c_hi; ++BJ)
-                        for (int ti = BI * tb; ti < std::min((BI + 1) * tb, nt); ++ti)
-                            for (int tj = std::max(ti, BJ * tb); tj < std::min((BJ + 1) * tb, nt); ++tj) {
-                                const bool full = ti != tj && (tj + 1) * edge - 32 < s_k;
-                                if (short_last && full != (pass == 0)) continue;
-                                out.push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + diag_step * ti : -1});
-                            }
-                }
-        };
-        std::vector<std::vector<TileDesc>> lists(kXcds), lists_s(kXcds);
-        for (int x = 0; x < kXcds; ++x)
-            for (const Unit &u : xcd_units[x]) {
-                unit_tiles(u, T, 1, false, lists[x]);
-                unit_tiles(u, T, 1, true, lists_s[x]);
+            for (int BI = b_lo; BI < b_hi; ++BI) {
+                const int c_lo = u.bi < 0 ? BI : u.bj, c_hi = u.bi < 0 ? (nt + tb - 1) / tb : u.bj + 1;
+                for (int BJ = c_lo; BJ < c_hi; ++BJ)
+                    for (int ti = BI * tb; ti < std::min((BI + 1) * tb, nt); ++ti)
+                        for (int tj = std::max(ti, BJ * tb); tj < std::min((BJ + 1) * tb, nt); ++tj) {
+                            const bool full = ti != tj && (tj + 1) * edge - 32 < s_k;
+                            if ((which == 1 && !full) || (which == 2 && full)) continue;
+                            out.push_back(TileDesc{k, ti, tj, ti == tj ? diag_base[k] + diag_step * ti : -1});
+                        }
             }
+        };
+        // The skip form's list holds the same tiles per XCD, but an XCD's full
+        // tiles first and its short ones (formed in part, so ending early)
+        // after all of them: amid full tiles a short one puts the workgroups
+        // that share the XCD's L2 out of step with the panel chunks they read
+        // together, and the offset lasts while the tiles that follow are equal.
+        std::vector<std::vector<TileDesc>> lists(kXcds), lists_s(kXcds);
+        for (int x = 0; x < kXcds; ++x) {
+            for (const Unit &u : xcd_units[x]) unit_tiles(u, T, 1, 0, lists[x]);
+            for (const Unit &u : xcd_units[x]) unit_tiles(u, T, 1, 1, lists_s[x]);
+            for (const Unit &u : xcd_units[x]) unit_tiles(u, T, 1, 2, lists_s[x]);
+        }
         size_t longest = 0;
         for (auto &l : lists) longest = std::max(longest, l.size());
         for (size_t q = 0; q < longest; ++q)
@@ -542,7 +543,7 @@ gsp2_status gsp2_plan_create(const gsp2_csr *P_prev, double tau, const int32_t *
         // diagonal 256-tile covers 128-tile diagonal slots 2t and 2t + 1.
         std::vector<std::vector<TileDesc>> lists_w(kXcds);
         for (int x = 0; x < kXcds; ++x)
-            for (const Unit &u : xcd_units[x]) unit_tiles(u, kTileWide, 2, false, lists_w[x]);
+            for (const Unit &u : xcd_units[x]) unit_tiles(u, kTileWide, 2, 0, lists_w[x]);
         longest = 0;
         for (auto &l : lists_w) longest = std::max(longest, l.size());
         for (size_t q = 0; q < longest; ++q)
@@ -819,9 +820,8 @@ gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int3
             if (ms[c] < ms[best]) best = c;
         }
         // another form replaces the default only when it is more than 1% faster
-        // (beyond the run-to-run spread): forms of equal speed can differ in
-        // their HBM traffic, and the default is the one with the least
-        const int dflt = wide16 ? 2 : 0;
+        // (beyond the run-to-run spread), so near ties keep the default
+        const int dflt = wide16 ? 2 : 1;
         if (ms[best] > 0.99 * ms[dflt]) best = dflt;
         plan->kernel_tuned[precision] = cand[best];
         if (info) {
@@ -1046,7 +1046,8 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     else if (plan->kernel_tuned[o.precision])
         rp.kernel = plan->kernel_tuned[o.precision];
     else
-        rp.kernel = wide16 ? GSP2_KERNEL_T256 : GSP2_KERNEL_T128;
+        rp.kernel = wide16 ? GSP2_KERNEL_T256
+                           : o.precision == GSP2_PREC_FP64 ? GSP2_KERNEL_T128 : GSP2_KERNEL_T128_SKIP;
     rp.refine_prec = o.precision == GSP2_PREC_FP64 ? GSP2_PREC_FP64 : GSP2_PREC_FP32;
     if (o.refine_precision == GSP2_PREC_FP16X3) {
         if (o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16)
@@ -1060,7 +1061,7 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     else if (o.precision == GSP2_PREC_FP64)
         rp.kernel32 = GSP2_KERNEL_T128;
     else
-        rp.kernel32 = plan->kernel_tuned[GSP2_PREC_FP32] ? plan->kernel_tuned[GSP2_PREC_FP32] : GSP2_KERNEL_T128;
+        rp.kernel32 = plan->kernel_tuned[GSP2_PREC_FP32] ? plan->kernel_tuned[GSP2_PREC_FP32] : GSP2_KERNEL_T128_SKIP;
     if (rp.persistent && (n_sys > 1 || (rp.precision != GSP2_PREC_FP32 && rp.precision != GSP2_PREC_FP16 &&
                                          rp.precision != GSP2_PREC_BF16)))
         fail(GSP2_E_UNSUPPORTED, "the persistent product launch takes one system and FP32, FP16 or BF16 products");

@@ -138,7 +138,7 @@ struct DevicePlan {
     void *shadow_lo[2];         // scaled FP16 low parts of the two X buffers (split FP16 products)
     const PartDesc *parts;
     const TileDesc *tiles;
-    const TileDesc *tiles_s;    // the same tiles, each unit's short ones last (the skip form's order)
+    const TileDesc *tiles_s;    // the same tiles, each XCD's short ones last (the skip form's order)
     const TileDesc *tiles_w;    // 256 x 256 tiles of the 16-bit products (same layout rules)
     int32_t n_tiles_w;
     int32_t pad_w_;
