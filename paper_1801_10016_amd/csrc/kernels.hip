@@ -555,7 +555,12 @@ __device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16
 // ---------------------------------------------------------------------------
 constexpr int kLdsWords = 2 * 2 * kTile * kLdsRow;  // [buffer][A/B][row * 9 + word]
 
-template <typename Op, bool kSplit = false, bool kSkip = false>
+// kAdj (FP32 only): the adjoint step instead of the product.  buf0 holds the
+// cotangent G of X_{t+1} (operand and "old" value of the update), buf1 gets
+// the cotangent of X_t, lo0 holds X_t, and the tile accumulates
+// sum_k G[I,k] X[J,k] + X[I,k] G[J,k] (the split form's two cross-term
+// segments with G and X_t for the two parts); no trace partials.
+template <typename Op, bool kSplit = false, bool kSkip = false, bool kAdj = false>
 __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, int cur, float alpha,
                                          float *__restrict__ buf0, float *__restrict__ buf1,
                                          Op *__restrict__ sh0, Op *__restrict__ sh1,
@@ -563,13 +568,15 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
                                          Op *__restrict__ lo0 = nullptr, Op *__restrict__ lo1 = nullptr) {
     constexpr bool kF32 = sizeof(Op) == 4;
     constexpr int kK = OpFmt<Op>::kK;
+    constexpr bool kTwo = kSplit || kAdj;       // operands from two matrices (H, L)
+    static_assert(!kAdj || (kF32 && !kSplit), "the adjoint step has FP32 operands");
     auto lds = [&](int b, int ab) { return lds_base + (b * 2 + ab) * kTile * kLdsRow; };
     const float *__restrict__ X = (cur ? buf1 : buf0) + pd.x_off;
     float *__restrict__ Xn = (cur ? buf0 : buf1) + pd.x_off;
     const Op *__restrict__ Xop = kF32 ? reinterpret_cast<const Op *>(X) : (cur ? sh1 : sh0) + pd.x_off;
     Op *__restrict__ Xnop = kF32 ? nullptr : (cur ? sh0 : sh1) + pd.x_off;
     // split operands: the scaled low parts of X and of the next iterate
-    const Op *__restrict__ Xlo = kSplit ? (cur ? lo1 : lo0) + pd.x_off : nullptr;
+    const Op *__restrict__ Xlo = kTwo ? (cur ? lo1 : lo0) + pd.x_off : nullptr;
     Op *__restrict__ Xnlo = kSplit ? (cur ? lo0 : lo1) + pd.x_off : nullptr;
     const int ld = pd.s_pad;
     const int I0 = td.ti * kTile, J0 = td.tj * kTile;
@@ -580,8 +587,8 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     const int lr = tid >> 3, lw = tid & 7;
     const char *AgH = reinterpret_cast<const char *>(Xop + (int64_t)(I0 + lr) * ld) + lw * 16;
     const char *BgH = reinterpret_cast<const char *>(Xop + (int64_t)(J0 + lr) * ld) + lw * 16;
-    const char *AgL = kSplit ? reinterpret_cast<const char *>(Xlo + (int64_t)(I0 + lr) * ld) + lw * 16 : nullptr;
-    const char *BgL = kSplit ? reinterpret_cast<const char *>(Xlo + (int64_t)(J0 + lr) * ld) + lw * 16 : nullptr;
+    const char *AgL = kTwo ? reinterpret_cast<const char *>(Xlo + (int64_t)(I0 + lr) * ld) + lw * 16 : nullptr;
+    const char *BgL = kTwo ? reinterpret_cast<const char *>(Xlo + (int64_t)(J0 + lr) * ld) + lw * 16 : nullptr;
     const int64_t pass_bytes = (int64_t)32 * ld * sizeof(Op);
 
     const int lane = tid & 63, wave = tid >> 6;
@@ -610,7 +617,7 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // Columns from s on are zero padding, so the K loop stops at the first
     // even chunk count covering s (exact: the skipped terms are zeros).
     const int nk = 2 * ((pd.s + 2 * kK - 1) / (2 * kK));
-    const int nc = kSplit ? 3 * nk : nk;
+    const int nc = kSplit ? 3 * nk : kAdj ? 2 * nk : nk;
     uint4 pa00, pa01, pa02, pa03, pb00, pb01, pb02, pb03;   // register set 0
     uint4 pa10, pa11, pa12, pa13, pb10, pb11, pb12, pb13;   // register set 1
     const char *Ap_ = AgH, *Bp_ = BgH;
@@ -619,7 +626,7 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     do {                                                                                           \
         const int c_ = (c);                                                                        \
         Ap_ = AgH; Bp_ = BgH; kb_ = (int64_t)c_ * 128;                                             \
-        if constexpr (kSplit) {                                                                    \
+        if constexpr (kTwo) {                                                                      \
             const int seg_ = c_ / nk;                                                              \
             Ap_ = seg_ == 1 ? AgL : AgH;                                                           \
             Bp_ = seg_ == 0 ? BgL : BgH;                                                           \
@@ -817,7 +824,7 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
                     if constexpr (kSplit)
                         Xnlo[(int64_t)rg * ld + cg] = static_cast<Op>((v - static_cast<float>(h)) * 0x1p11f);
                 }
-                if (diag && rg == cg && rg < pd.c) {
+                if (!kAdj && diag && rg == cg && rg < pd.c) {
                     tY += static_cast<double>(y);
                     tX += static_cast<double>(v);
                 }
@@ -862,7 +869,7 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
                 ++k;
             }
     }
-    if (diag) {
+    if (!kAdj && diag) {
         block_sum2(tY, tX);
         if (tid == 0) {
             diag_partials[2 * td.diag_slot + 0] = tY;
@@ -1757,107 +1764,8 @@ __global__ __launch_bounds__(kBlock) void k_scatter(const PartDesc *__restrict__
 // With G and X symmetric, tile (I,J) of GX + XG is
 //     sum_k G[I,k] X[J,k] + X[I,k] G[J,k],
 // two row-panel products accumulated into one tile: the forward kernel's
-// data flow with the K loop run twice over different panel pairs.
+// data flow with the K loop run over two panel pairs (sp2_tile's kAdj).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void adj_tile(const TileDesc td, const PartDesc pd, float alpha,
-                                         const float *__restrict__ Gin, float *__restrict__ Gout,
-                                         const float *__restrict__ X, uint4 *__restrict__ lds_base) {
-    auto lds = [&](int b, int ab) { return lds_base + (b * 2 + ab) * kTile * kLdsRow; };
-    const float *Gi = Gin + pd.x_off;
-    float *Go = Gout + pd.x_off;
-    const float *Xp = X + pd.x_off;
-    const int ld = pd.s_pad;
-    const int I0 = td.ti * kTile, J0 = td.tj * kTile;
-    const bool diag = td.ti == td.tj;
-    const int tid = threadIdx.x;
-    const int lr = tid >> 3, lw = tid & 7;
-    const char *A1 = reinterpret_cast<const char *>(Gi + (int64_t)(I0 + lr) * ld) + lw * 16;
-    const char *B1 = reinterpret_cast<const char *>(Xp + (int64_t)(J0 + lr) * ld) + lw * 16;
-    const char *A2 = reinterpret_cast<const char *>(Xp + (int64_t)(I0 + lr) * ld) + lw * 16;
-    const char *B2 = reinterpret_cast<const char *>(Gi + (int64_t)(J0 + lr) * ld) + lw * 16;
-    const int64_t pass_bytes = (int64_t)32 * ld * sizeof(float);
-    const int lane = tid & 63, wave = tid >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
-    const int l32 = lane & 31, kh = lane >> 5;
-
-    v16f acc[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int i = 0; i < 16; ++i) acc[a][b][i] = 0.0f;
-
-    const int nk = ld / OpFmt<float>::kK;
-    const int nc = 2 * nk;
-    uint4 pa0, pa1, pa2, pa3, pb0, pb1, pb2, pb3;
-    auto load = [&](int c) {
-        const char *Ag = c < nk ? A1 : A2;
-        const char *Bg = c < nk ? B1 : B2;
-        const int64_t kb = (int64_t)(c < nk ? c : c - nk) * 128;
-        pa0 = *reinterpret_cast<const uint4 *>(Ag + kb);
-        pa1 = *reinterpret_cast<const uint4 *>(Ag + pass_bytes + kb);
-        pa2 = *reinterpret_cast<const uint4 *>(Ag + 2 * pass_bytes + kb);
-        pa3 = *reinterpret_cast<const uint4 *>(Ag + 3 * pass_bytes + kb);
-        pb0 = *reinterpret_cast<const uint4 *>(Bg + kb);
-        pb1 = *reinterpret_cast<const uint4 *>(Bg + pass_bytes + kb);
-        pb2 = *reinterpret_cast<const uint4 *>(Bg + 2 * pass_bytes + kb);
-        pb3 = *reinterpret_cast<const uint4 *>(Bg + 3 * pass_bytes + kb);
-    };
-    auto store = [&](int b) {
-        uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;
-        uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;
-        As_[0] = pa0; As_[32 * kLdsRow] = pa1; As_[64 * kLdsRow] = pa2; As_[96 * kLdsRow] = pa3;
-        Bs_[0] = pb0; Bs_[32 * kLdsRow] = pb1; Bs_[64 * kLdsRow] = pb2; Bs_[96 * kLdsRow] = pb3;
-    };
-    load(0);
-    store(0);
-    __syncthreads();
-    for (int kc = 0; kc < nc; ++kc) {
-        const int buf = kc & 1;
-        if (kc + 1 < nc) load(kc + 1);
-        const uint4 *Asb = lds(buf, 0);
-        const uint4 *Bsb = lds(buf, 1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int w = kh * 4 + q;
-            uint4 fa[2], fb[2];
-#pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                fa[m] = Asb[(wr * 64 + m * 32 + l32) * kLdsRow + w];
-                fb[m] = Bsb[(wc * 64 + m * 32 + l32) * kLdsRow + w];
-            }
-#pragma unroll
-            for (int m = 0; m < 2; ++m)
-#pragma unroll
-                for (int nn = 0; nn < 2; ++nn) acc[m][nn] = mfma_chunk_q(fa[m], fb[nn], acc[m][nn], float{});
-        }
-        if (kc + 1 < nc) store(buf ^ 1);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-#pragma unroll
-        for (int nn = 0; nn < 2; ++nn) {
-            const int cg = J0 + wc * 64 + nn * 32 + l32;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int rg0 = I0 + wr * 64 + m * 32 + g * 8 + kh * 4;
-                float gn[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int rg = rg0 + e;
-                    const float sv = acc[m][nn][4 * g + e];
-                    const float go = Gi[(int64_t)rg * ld + cg];
-                    const float v = alpha > 0.0f ? (2.0f * go - sv) : sv;
-                    gn[e] = v;
-                    Go[(int64_t)rg * ld + cg] = v;
-                }
-                if (!diag) *reinterpret_cast<float4 *>(Go + (int64_t)cg * ld + rg0) = make_float4(gn[0], gn[1], gn[2], gn[3]);
-            }
-        }
-    }
-}
 
 // One forward product with the buffers and branch given explicitly (the
 // backward pass replays a known sequence).
@@ -1868,7 +1776,8 @@ __global__ __launch_bounds__(kBlock, 2) __attribute__((amdgpu_waves_per_eu(1, 2)
     __shared__ uint4 lds[kLdsWords];
     const TileDesc td = tiles[blockIdx.x];
     if (td.part < 0) return;
-    sp2_tile<float>(td, parts[td.part], 0, alpha, X_in, X_out, nullptr, nullptr, diag_partials, lds);
+    // the skip form (same bits as the full grid), over its own tile order
+    sp2_tile<float, false, true>(td, parts[td.part], 0, alpha, X_in, X_out, nullptr, nullptr, diag_partials, lds);
 }
 
 __global__ __launch_bounds__(kBlock, 2) void k_adj_step(const TileDesc *__restrict__ tiles,
@@ -1878,7 +1787,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_adj_step(const TileDesc *__restri
     __shared__ uint4 lds[kLdsWords];
     const TileDesc td = tiles[blockIdx.x];
     if (td.part < 0) return;
-    adj_tile(td, parts[td.part], alpha, G_in, G_out, X, lds);
+    // G_in is only read (operand and old value); the skip form, over its own tile order
+    sp2_tile<float, false, true, true>(td, parts[td.part], 0, alpha, const_cast<float *>(G_in), G_out, nullptr,
+                                       nullptr, nullptr, lds, const_cast<float *>(X), nullptr);
 }
 
 // Seed: part k's cotangent is dL/dP on its core columns (rows in local
@@ -2185,7 +2096,7 @@ hipError_t backward_typed(const DevicePlan &dp, const gsp2_csr &H, const RunPara
     float *cur = bb.ckpt[0];
     for (int t = 0; t + 1 <= (nseg - 1) * k; ++t) {
         float *out = ((t + 1) % k == 0) ? bb.ckpt[(t + 1) / k] : (cur == dp.buf[0] ? dp.buf[1] : dp.buf[0]);
-        record(rec, k_sp2_fixed, grid, blk, dp.tiles, dp.parts, cur, out, (float)alphas[t], dp.diag_partials);
+        record(rec, k_sp2_fixed, grid, blk, dp.tiles_s, dp.parts, cur, out, (float)alphas[t], dp.diag_partials);
         cur = out;
     }
     // seed and reverse sweep, segment by segment from the last
@@ -2195,12 +2106,12 @@ hipError_t backward_typed(const DevicePlan &dp, const gsp2_csr &H, const RunPara
         const int t0 = seg * k, t1 = (t0 + k < n) ? t0 + k : n;
         for (int i = 1; i < t1 - t0; ++i) {
             float *in = (i == 1) ? bb.ckpt[seg] : bb.slot[i - 2];
-            record(rec, k_sp2_fixed, grid, blk, dp.tiles, dp.parts, in, bb.slot[i - 1], (float)alphas[t0 + i - 1],
+            record(rec, k_sp2_fixed, grid, blk, dp.tiles_s, dp.parts, in, bb.slot[i - 1], (float)alphas[t0 + i - 1],
                    dp.diag_partials);
         }
         for (int t = t1 - 1; t >= t0; --t) {
             const float *X = (t == t0) ? bb.ckpt[seg] : bb.slot[t - t0 - 1];
-            record(rec, k_adj_step, grid, blk, dp.tiles, dp.parts, (const float *)g_cur, g_oth, X, (float)alphas[t]);
+            record(rec, k_adj_step, grid, blk, dp.tiles_s, dp.parts, (const float *)g_cur, g_oth, X, (float)alphas[t]);
             float *tmp = g_cur; g_cur = g_oth; g_oth = tmp;
         }
     }
