@@ -610,13 +610,13 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     //
     // Operands arrive two chunks ahead in two register sets: chunk c + 1 is
     // stored into LDS after the MFMAs of chunk c, from the set loaded before
-    // the MFMAs of chunk c - 1.  Chunk counts are even (below), so the loop
-    // takes chunks in pairs with the sets fixed; past the end
-    // the last chunk is loaded again, so every load is unconditional, and the
-    // last pair stores it a second time into a buffer no wave reads again.
+    // the MFMAs of chunk c - 1.  The loop takes chunks in pairs with the sets
+    // fixed, and an odd count ends with one more chunk from buffer 0; past the
+    // end the last chunk is loaded again, so every load is unconditional, and
+    // the last steps store it again into a buffer no wave reads again.
     // Columns from s on are zero padding, so the K loop stops at the first
-    // even chunk count covering s (exact: the skipped terms are zeros).
-    const int nk = 2 * ((pd.s + 2 * kK - 1) / (2 * kK));
+    // chunk count covering s (exact: the skipped terms are zeros).
+    const int nk = (pd.s + kK - 1) / kK;
     const int nc = kSplit ? 3 * nk : kAdj ? 2 * nk : nk;
     uint4 pa00, pa01, pa02, pa03, pb00, pb01, pb02, pb03;   // register set 0
     uint4 pa10, pa11, pa12, pa13, pb10, pb11, pb12, pb13;   // register set 1
@@ -755,7 +755,8 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
         GSP2_ST(0, 0);
         GSP2_LD(1, min(1, nc - 1));
         __syncthreads();
-        for (int kc = 0; kc < nc; kc += 2) {
+        int kc = 0;
+        for (; kc + 1 < nc; kc += 2) {
             if constexpr (kSplit) {
                 if (kc == 2 * nk) {             // cross terms done: scale them by 2^-11
 #pragma unroll
@@ -772,6 +773,18 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
             compute_kind(1, kind);
             GSP2_ST(0, 0);
             __syncthreads();
+        }
+        if (kc < nc) {                          // an odd count's last chunk, stored in buffer 0
+            if constexpr (kSplit) {
+                if (kc == 2 * nk) {             // (nk = 1: the H H chunk is this one)
+#pragma unroll
+                    for (int m = 0; m < 2; ++m)
+#pragma unroll
+                        for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
+                }
+            }
+            compute_kind(0, kind);
+            __syncthreads();                    // as after a pair: LDS is free again when the loop ends
         }
     };
     if constexpr (!kSkip) {
@@ -794,21 +807,38 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // diagonal and d_r^2 on it, so the diagonal is never rounded.
     constexpr bool kExactDiag = !kF32 && !kSplit;
     double tY = 0.0, tX = 0.0;
+    // X_old (for X' = 2X - Y and, with plain 16-bit operands, the diagonal
+    // terms) is read at the mirrored position, X[r][c] = X[c][r] (X is
+    // symmetric), as one float4 per lane and row group, for all of the wave's
+    // blocks before any store: a wave's loads complete in order behind its
+    // earlier stores, so reads between stores would wait for them.
+    const bool need_xo = kExactDiag || alpha > 0.0f;
+    float4 xo4[4][4];                           // [block slot][row group]
+    auto load_xo = [&](int slot, int ro, int co) __attribute__((always_inline)) {
+        const int cg = J0 + co + l32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int rg0 = I0 + ro + g * 8 + kh * 4;
+            xo4[slot][g] = need_xo ? *reinterpret_cast<const float4 *>(X + (int64_t)cg * ld + rg0)
+                                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+    };
     // one 32 x 32 block of the tile (its first row and column within the
     // tile: ro, co) from its accumulator, written at its place and, with
     // write_mirror, transposed at the mirrored place
-    auto emit_block = [&](const v16f &a, int ro, int co, bool write_mirror) __attribute__((always_inline)) {
+    auto emit_block = [&](const v16f &a, int slot, int ro, int co, bool write_mirror) __attribute__((always_inline)) {
         const int cg = J0 + co + l32;
         const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int rg0 = I0 + ro + g * 8 + kh * 4;
+            const float xov[4] = {xo4[slot][g].x, xo4[slot][g].y, xo4[slot][g].z, xo4[slot][g].w};
             float xn[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int rg = rg0 + e;
                 const float yacc = a[4 * g + e];
-                const float xo = X[(int64_t)rg * ld + cg];
+                const float xo = xov[e];
                 float y = yacc;
                 if constexpr (kExactDiag) {
                     const float dr = X[(int64_t)rg * (ld + 1)];
@@ -847,25 +877,54 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
             }
         }
     };
+    // a block wholly in the zero padding: its products and X_old are zero,
+    // so X' is +0 there (as the grid forms it), written without reading
+    auto emit_zero = [&](int ro, int co, bool write_mirror) __attribute__((always_inline)) {
+        const int cg = J0 + co + l32;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int rg0 = I0 + ro + g * 8 + kh * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                Xn[(int64_t)(rg0 + e) * ld + cg] = 0.0f;
+                if constexpr (!kF32) {
+                    Xnop[(int64_t)(rg0 + e) * ld + cg] = static_cast<Op>(0.0f);
+                    if constexpr (kSplit) Xnlo[(int64_t)(rg0 + e) * ld + cg] = static_cast<Op>(0.0f);
+                }
+            }
+            if (write_mirror) {
+                *reinterpret_cast<float4 *>(Xn + (int64_t)cg * ld + rg0) = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                if constexpr (!kF32) {
+                    *reinterpret_cast<uint2 *>(Xnop + (int64_t)cg * ld + rg0) = make_uint2(0u, 0u);
+                    if constexpr (kSplit) *reinterpret_cast<uint2 *>(Xnlo + (int64_t)cg * ld + rg0) = make_uint2(0u, 0u);
+                }
+            }
+        }
+    };
     if (grid_tile) {
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int nn = 0; nn < 2; ++nn) emit_block(acc[m][nn], wr * 64 + m * 32, wc * 64 + nn * 32, !diag);
+            for (int nn = 0; nn < 2; ++nn) load_xo(2 * m + nn, wr * 64 + m * 32, wc * 64 + nn * 32);
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int nn = 0; nn < 2; ++nn)
+                emit_block(acc[m][nn], 2 * m + nn, wr * 64 + m * 32, wc * 64 + nn * 32, !diag);
     } else {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-            if (j < n_mine) emit_block(acc[j >> 1][j & 1], 32 * g_r[j], 32 * g_c[j], !diag || g_r[j] < g_c[j]);
-        // the padding blocks of the tile (both triangles of a diagonal tile),
-        // dealt round robin: zero products, so the zeros the grid writes
-        v16f zero;
+            if (j < n_mine) load_xo(j, 32 * g_r[j], 32 * g_c[j]);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) zero[i] = 0.0f;
+        for (int j = 0; j < 3; ++j)
+            if (j < n_mine) emit_block(acc[j >> 1][j & 1], j, 32 * g_r[j], 32 * g_c[j], !diag || g_r[j] < g_c[j]);
+        // the padding blocks of the tile (both triangles of a diagonal tile),
+        // dealt round robin
         int k = 0;
         for (int r = 0; r < 4; ++r)
             for (int c = 0; c < 4; ++c) {
                 if (I0 + 32 * r < pd.s && J0 + 32 * c < pd.s) continue;
-                if ((k & 3) == wv) emit_block(zero, 32 * r, 32 * c, !diag);
+                if ((k & 3) == wv) emit_zero(32 * r, 32 * c, !diag);
                 ++k;
             }
     }
