@@ -636,7 +636,7 @@ def bench_water(args, g, torch):
         P_mp = torch.empty(info["nnz_P"], dtype=dt, device="cuda")
         tune_rec = None
         with torch.cuda.stream(stream):
-            if not args.no_tune and prec in ("fp32", "fp16", "bf16", "fp16x3"):
+            if not args.no_tune and prec in ("fp32", "fp16", "bf16", "fp16x3", "fp64"):
                 tune_rec = g.gsp2_plan_tune(plan, Hd, n_occ, prec, n_products=6)
             r0 = g.gsp2_density(plan, Hd, n_occ, P_mp, max_iter=args.max_iter, precision=prec, check=False)
         n_mp = r0["n_products"]

@@ -76,14 +76,13 @@ typedef enum {
  * rounding (T128_SKIP mirrors the block above, T128 forms both). */
 typedef enum {
     GSP2_KERNEL_AUTO = 0,      /* the form gsp2_plan_tune kept for the precision, else the default:
-                                  T128_SKIP for FP32 products, T128 for FP64, T256 for 16-bit ones */
+                                  T128_SKIP for FP32 and FP64 products, T256 for 16-bit ones */
     GSP2_KERNEL_T128 = 1,      /* 128 x 128 product tiles, two workgroups per CU, every 32 x 32
                                   block of the padded tile formed */
     GSP2_KERNEL_T128_SKIP = 2, /* 128 x 128 tiles; 32 x 32 blocks lying wholly in the zero padding,
                                   and the blocks below the diagonal of a diagonal tile (transposes
                                   of blocks above it), form no products, and the blocks a tile
-                                  forms are dealt evenly to its four waves.  Not for FP64
-                                  products. */
+                                  forms are dealt evenly to its four waves. */
     GSP2_KERNEL_T256 = 3       /* 256 x 256 tiles, one workgroup per CU; 16-bit operands only */
 } gsp2_kernel;
 
@@ -425,8 +424,9 @@ typedef struct {
 /* Autotuner of the product kernel (the paper's products are dense
  * matrix-matrix sub-problems, Methods, eq. (4); their tiling is this
  * library's choice).  Times n_products products of the plan's own
- * sub-problems, built from H, with each candidate form: FP32 products
- * GSP2_KERNEL_T128 and T128_SKIP; 16-bit products T128, T128_SKIP and T256.
+ * sub-problems, built from H, with each candidate form: FP32 and FP64
+ * products GSP2_KERNEL_T128 and T128_SKIP; 16-bit products T128, T128_SKIP
+ * and T256.
  * Keeps the form with the lowest mean product time for `precision`, except
  * that another form replaces the default (GSP2_KERNEL_AUTO's) only when it is
  * more than 1% faster, so that near ties keep the default; gsp2_density then uses it for that precision unless the run names a form

@@ -784,12 +784,13 @@ gsp2_status gsp2_plan_tune(gsp2_plan plan, const gsp2_csr *H, double n_occ, int3
         if (!plan || !H) fail(GSP2_E_INVALID, "null argument");
         const bool wide16 = precision == GSP2_PREC_FP16 || precision == GSP2_PREC_BF16 ||
                             precision == GSP2_PREC_FP16X3;
-        if (precision != GSP2_PREC_FP32 && !wide16)
-            fail(GSP2_E_INVALID, "gsp2_plan_tune takes an FP32 or 16-bit precision");
+        if (precision != GSP2_PREC_FP32 && precision != GSP2_PREC_FP64 && !wide16)
+            fail(GSP2_E_INVALID, "gsp2_plan_tune takes a product precision");
         if (n_products < 2 || n_products > GSP2_MAX_ITER) fail(GSP2_E_INVALID, "n_products out of range");
         int64_t nnz_p = 0;
         for (const auto &d : plan->desc) nnz_p += (int64_t)d.c * d.s;
-        check_hip(hipMalloc(&scratch, sizeof(float) * (size_t)std::max<int64_t>(nnz_p, 1)), "tuner scratch output");
+        const size_t p_elem = precision == GSP2_PREC_FP64 ? sizeof(double) : sizeof(float);   // P's type
+        check_hip(hipMalloc(&scratch, p_elem * (size_t)std::max<int64_t>(nnz_p, 1)), "tuner scratch output");
         std::vector<int8_t> seq(n_products);
         for (int i = 0; i < n_products; ++i) seq[i] = (i % 2) ? 1 : -1;
         std::vector<double> occ(plan->n_sys, n_occ);
@@ -1037,8 +1038,6 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     // 16-bit tile edge, else the tuned form, else the default
     if (o.kernel < GSP2_KERNEL_AUTO || o.kernel > GSP2_KERNEL_T256) fail(GSP2_E_INVALID, "bad kernel");
     if (o.kernel == GSP2_KERNEL_T256 && !wide16) fail(GSP2_E_INVALID, "256 x 256 tiles take 16-bit products only");
-    if (o.kernel == GSP2_KERNEL_T128_SKIP && o.precision == GSP2_PREC_FP64)
-        fail(GSP2_E_INVALID, "FP64 products have the one form GSP2_KERNEL_T128");
     if (o.kernel != GSP2_KERNEL_AUTO)
         rp.kernel = o.kernel;
     else if (wide16 && plan->tile16_fixed)
@@ -1046,8 +1045,7 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     else if (plan->kernel_tuned[o.precision])
         rp.kernel = plan->kernel_tuned[o.precision];
     else
-        rp.kernel = wide16 ? GSP2_KERNEL_T256
-                           : o.precision == GSP2_PREC_FP64 ? GSP2_KERNEL_T128 : GSP2_KERNEL_T128_SKIP;
+        rp.kernel = wide16 ? GSP2_KERNEL_T256 : GSP2_KERNEL_T128_SKIP;
     rp.refine_prec = o.precision == GSP2_PREC_FP64 ? GSP2_PREC_FP64 : GSP2_PREC_FP32;
     if (o.refine_precision == GSP2_PREC_FP16X3) {
         if (o.precision != GSP2_PREC_FP16 && o.precision != GSP2_PREC_BF16)
@@ -1056,10 +1054,8 @@ static RunParams prepare_run(gsp2_plan_s *plan, const gsp2_csr *H, double n_occ,
     } else if (o.refine_precision != GSP2_PREC_FP32) {
         fail(GSP2_E_INVALID, "refine_precision must be GSP2_PREC_FP32 or GSP2_PREC_FP16X3");
     }
-    if (o.precision == GSP2_PREC_FP32)
-        rp.kernel32 = rp.kernel;
-    else if (o.precision == GSP2_PREC_FP64)
-        rp.kernel32 = GSP2_KERNEL_T128;
+    if (o.precision == GSP2_PREC_FP32 || o.precision == GSP2_PREC_FP64)
+        rp.kernel32 = rp.kernel;                // the refinement products take the main products' form
     else
         rp.kernel32 = plan->kernel_tuned[GSP2_PREC_FP32] ? plan->kernel_tuned[GSP2_PREC_FP32] : GSP2_KERNEL_T128_SKIP;
     if (rp.persistent && (n_sys > 1 || (rp.precision != GSP2_PREC_FP32 && rp.precision != GSP2_PREC_FP16 &&

@@ -553,6 +553,52 @@ __device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16
 // every 16-byte group, for A and B alike, so each lane reads whole 16-byte
 // LDS words.
 // ---------------------------------------------------------------------------
+// The 32 x 32 blocks a 128 x 128 tile forms in the skip form, dealt to its
+// four waves (wave-uniform; see sp2_tile): blocks wholly in the zero padding
+// and, in a diagonal tile, blocks below the diagonal are not formed.  Off the
+// diagonal the formed blocks go round robin in row-major order; in a diagonal
+// tile the blocks on the diagonal stay with the waves that hold them in the
+// 2 x 2 grid (0 and 3) and every other block goes to the least loaded wave
+// (the lowest on ties).  A wave gets at most 3 (a diagonal tile forms 10, a
+// tile that is not full at most 12).  deal_slot gives slot j of wave wv: the
+// block row and column (br, bc), or -1 if the wave has fewer blocks.  Each
+// slot is found by its own pass, so that nothing is indexed at run time.
+__device__ __forceinline__ void deal_slot(int I0, int J0, int s, bool diag, int wv, int j, int &br, int &bc) {
+    br = -1;
+    bc = -1;
+    int mine = 0;
+    auto take = [&](int r, int c) __attribute__((always_inline)) {
+        if (mine == j) { br = r; bc = c; }
+        ++mine;
+    };
+    if (!diag) {
+        int u = 0;
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c)
+                if (I0 + 32 * r < s && J0 + 32 * c < s) {
+                    if ((u & 3) == wv) take(r, c);
+                    ++u;
+                }
+    } else {
+        int l0 = 0, l1 = 0, l2 = 0, l3 = 0;         // blocks dealt to each wave
+        for (int b = 0; b < 4; ++b)
+            if (I0 + 32 * b < s) {
+                if (b < 2) { ++l0; if (wv == 0) take(b, b); }
+                else { ++l3; if (wv == 3) take(b, b); }
+            }
+        for (int r = 0; r < 4; ++r)
+            for (int c = r + 1; c < 4; ++c)
+                if (I0 + 32 * c < s) {
+                    int w = 0, lw = l0;
+                    if (l1 < lw) { w = 1; lw = l1; }
+                    if (l2 < lw) { w = 2; lw = l2; }
+                    if (l3 < lw) { w = 3; lw = l3; }
+                    if (w == 0) ++l0; else if (w == 1) ++l1; else if (w == 2) ++l2; else ++l3;
+                    if (w == wv) take(r, c);
+                }
+    }
+}
+
 constexpr int kLdsWords = 2 * 2 * kTile * kLdsRow;  // [buffer][A/B][row * 9 + word]
 
 // kAdj (FP32 only): the adjoint step instead of the product.  buf0 holds the
@@ -677,39 +723,10 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     const bool grid_tile = !kSkip || (!diag && I0 + 96 < pd.s && J0 + 96 < pd.s);
     int g_r[3] = {-1, -1, -1}, g_c[3] = {-1, -1, -1};
     int n_mine = 0;
-    auto take = [&](int r, int c) __attribute__((always_inline)) {
-        if (n_mine == 0) { g_r[0] = r; g_c[0] = c; }
-        else if (n_mine == 1) { g_r[1] = r; g_c[1] = c; }
-        else { g_r[2] = r; g_c[2] = c; }
-        ++n_mine;
-    };
-    if (!grid_tile) {
-        if (!diag) {
-            int u = 0;
-            for (int r = 0; r < 4; ++r)
-                for (int c = 0; c < 4; ++c)
-                    if (I0 + 32 * r < pd.s && J0 + 32 * c < pd.s) {
-                        if ((u & 3) == wv) take(r, c);
-                        ++u;
-                    }
-        } else {
-            int l0 = 0, l1 = 0, l2 = 0, l3 = 0;     // blocks dealt to each wave
-            for (int d = 0; d < 4; ++d)
-                if (I0 + 32 * d < pd.s) {
-                    if (d < 2) { ++l0; if (wv == 0) take(d, d); }
-                    else { ++l3; if (wv == 3) take(d, d); }
-                }
-            for (int r = 0; r < 4; ++r)
-                for (int c = r + 1; c < 4; ++c)
-                    if (I0 + 32 * c < pd.s) {
-                        int w = 0, lw = l0;
-                        if (l1 < lw) { w = 1; lw = l1; }
-                        if (l2 < lw) { w = 2; lw = l2; }
-                        if (l3 < lw) { w = 3; lw = l3; }
-                        if (w == 0) ++l0; else if (w == 1) ++l1; else if (w == 2) ++l2; else ++l3;
-                        if (w == wv) take(r, c);
-                    }
-        }
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (!grid_tile) deal_slot(I0, J0, pd.s, diag, wv, j, g_r[j], g_c[j]);
+        if (g_r[j] >= 0) n_mine = j + 1;
     }
     // kind 0: the wave's 2 x 2 blocks of the grid; 2: none; 3 + M: the wave's
     // M dealt blocks (slot j in acc[j / 2][j % 2])
@@ -973,6 +990,7 @@ __global__ __launch_bounds__(kBlock, 2) __attribute__((amdgpu_waves_per_eu(1, 2)
 // ---------------------------------------------------------------------------
 typedef double v4d __attribute__((ext_vector_type(4)));
 
+template <bool kSkip = false>
 __device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd, int cur, double alpha,
                                            double *__restrict__ buf0, double *__restrict__ buf1,
                                            double *__restrict__ diag_partials, uint4 *__restrict__ lds_base) {
@@ -998,6 +1016,19 @@ __device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd,
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
+    // The skip form deals the tile's 32 x 32 blocks to the waves as sp2_tile
+    // does (deal_slot); a 32 x 32 block is 2 x 2 MFMA blocks of 16 x 16, and
+    // sub-block (a, b) of slot j accumulates in acc[2 (j / 2) + a][2 (j % 2) + b].
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    const bool grid_tile = !kSkip || (!diag && I0 + 96 < pd.s && J0 + 96 < pd.s);
+    int g_r[3] = {-1, -1, -1}, g_c[3] = {-1, -1, -1};
+    int n_mine = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        if (!grid_tile) deal_slot(I0, J0, pd.s, diag, wv, j, g_r[j], g_c[j]);
+        if (g_r[j] >= 0) n_mine = j + 1;
+    }
+
     // columns from s on are zero padding: the K loop stops at the first
     // chunk that covers s (the skipped terms are exact zeros)
     constexpr int kK64 = 16;
@@ -1022,33 +1053,83 @@ __device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd,
         As_[0] = pa0; As_[32 * kLdsRow] = pa1; As_[64 * kLdsRow] = pa2; As_[96 * kLdsRow] = pa3;   \
         Bs_[0] = pb0; Bs_[32 * kLdsRow] = pb1; Bs_[64 * kLdsRow] = pb2; Bs_[96 * kLdsRow] = pb3;   \
     } while (0)
-    GSP2_LD64(0);
-    GSP2_ST64(0);
-    __syncthreads();
-    for (int kc = 0; kc < nk; ++kc) {
-        const int b = kc & 1;
-        if (kc + 1 < nk) GSP2_LD64(kc + 1);
+    // kind 0: the wave's 4 x 4 MFMA blocks of the grid; 2: none; 3 + M: its M dealt blocks
+    auto compute = [&](int b, auto kind) __attribute__((always_inline)) {
+        constexpr int K = decltype(kind)::value;
+        if constexpr (K == 2) return;
         const uint4 *Asb = lds(b, 0);
         const uint4 *Bsb = lds(b, 1);
-        double fa[4][4], fb[4][4];              // [block][MFMA step]
+        if constexpr (K == 0) {
+            // MFMA steps in two halves (steps 2h, 2h + 1: the h-th 16 bytes of
+            // a lane's row piece)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const uint4 *ra = Asb + (wr * 64 + m * 16 + l16) * kLdsRow + 2 * g;
-            const uint4 *rb = Bsb + (wc * 64 + m * 16 + l16) * kLdsRow + 2 * g;
-            const double2 a0 = __builtin_bit_cast(double2, ra[0]), a1 = __builtin_bit_cast(double2, ra[1]);
-            const double2 b0 = __builtin_bit_cast(double2, rb[0]), b1 = __builtin_bit_cast(double2, rb[1]);
-            fa[m][0] = a0.x; fa[m][1] = a0.y; fa[m][2] = a1.x; fa[m][3] = a1.y;
-            fb[m][0] = b0.x; fb[m][1] = b0.y; fb[m][2] = b1.x; fb[m][3] = b1.y;
+            for (int h = 0; h < 2; ++h) {
+                double fa[4][2], fb[4][2];          // [block][step in half]
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const double2 va = __builtin_bit_cast(double2, Asb[(wr * 64 + m * 16 + l16) * kLdsRow + 2 * g + h]);
+                    const double2 vb = __builtin_bit_cast(double2, Bsb[(wc * 64 + m * 16 + l16) * kLdsRow + 2 * g + h]);
+                    fa[m][0] = va.x; fa[m][1] = va.y;
+                    fb[m][0] = vb.x; fb[m][1] = vb.y;
+                }
+#pragma unroll
+                for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+#pragma unroll
+                        for (int nn = 0; nn < 4; ++nn)
+                            acc[m][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[m][qq], fb[nn][qq], acc[m][nn], 0, 0, 0);
+            }
+        } else if constexpr (K >= 4) {
+            constexpr int M = K - 3;
+            // MFMA steps in two halves (steps 2h, 2h + 1: the h-th 16 bytes of a
+            // lane's row piece), each element in the same k order as the grid
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int j = 0; j < M; ++j) {       // one slot's fragments at a time
+                    double fa[2][2], fb[2][2];      // [sub-block row / column][step in half]
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const double2 va = __builtin_bit_cast(
+                            double2, Asb[(g_r[j] * 32 + a * 16 + l16) * kLdsRow + 2 * g + h]);
+                        const double2 vb = __builtin_bit_cast(
+                            double2, Bsb[(g_c[j] * 32 + a * 16 + l16) * kLdsRow + 2 * g + h]);
+                        fa[a][0] = va.x; fa[a][1] = va.y;
+                        fb[a][0] = vb.x; fb[a][1] = vb.y;
+                    }
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq)
+#pragma unroll
+                        for (int a = 0; a < 2; ++a)
+#pragma unroll
+                            for (int bb = 0; bb < 2; ++bb) {
+                                v4d &c = acc[2 * (j >> 1) + a][2 * (j & 1) + bb];
+                                c = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a][qq], fb[bb][qq], c, 0, 0, 0);
+                            }
+                }
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int nn = 0; nn < 4; ++nn)
-                    acc[m][nn] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[m][q], fb[nn][q], acc[m][nn], 0, 0, 0);
-        if (kc + 1 < nk) GSP2_ST64(b ^ 1);
+    };
+    auto kloop = [&](auto kind) __attribute__((always_inline)) {
+        GSP2_LD64(0);
+        GSP2_ST64(0);
         __syncthreads();
+        for (int kc = 0; kc < nk; ++kc) {
+            const int b = kc & 1;
+            if (kc + 1 < nk) GSP2_LD64(kc + 1);
+            compute(b, kind);
+            if (kc + 1 < nk) GSP2_ST64(b ^ 1);
+            __syncthreads();
+        }
+    };
+    if constexpr (!kSkip) {
+        kloop(std::integral_constant<int, 0>{});
+    } else {
+        if (grid_tile) kloop(std::integral_constant<int, 0>{});
+        else if (n_mine == 0) kloop(std::integral_constant<int, 2>{});
+        else if (n_mine == 1) kloop(std::integral_constant<int, 4>{});
+        else if (n_mine == 2) kloop(std::integral_constant<int, 5>{});
+        else kloop(std::integral_constant<int, 6>{});
     }
 #undef GSP2_LD64
 #undef GSP2_ST64
@@ -1061,30 +1142,65 @@ __device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd,
     // group.
     double tY = 0.0, tX = 0.0;
     const bool upd = alpha > 0.0;
+    // one 16 x 16 block (first row and column within the tile: ro, co)
+    auto emit16 = [&](const v4d &a, int ro, int co, bool write_mirror) __attribute__((always_inline)) {
+        const int cg = J0 + co + l16;
+        const int rb = I0 + ro + g;
+        double xo[4] = {0.0, 0.0, 0.0, 0.0};
+        if (upd) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+            for (int v = 0; v < 4; ++v) xo[v] = X[(int64_t)(rb + 4 * v) * ld + cg];
+        }
 #pragma unroll
-        for (int nn = 0; nn < 4; ++nn) {
-            const int cg = J0 + wc * 64 + nn * 16 + l16;
-            const int rb = I0 + wr * 64 + m * 16 + g;
-            double xo[4] = {0.0, 0.0, 0.0, 0.0};
-            if (upd) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) xo[v] = X[(int64_t)(rb + 4 * v) * ld + cg];
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int rg = rb + 4 * v;
-                const double y = acc[m][nn][v];
-                const double val = upd ? (2.0 * xo[v] - y) : y;
-                Xn[(int64_t)rg * ld + cg] = val;
-                if (!diag) Xn[(int64_t)cg * ld + rg] = val;
-                if (diag && rg == cg && cg < pd.c) {
-                    tY += y;
-                    tX += val;
-                }
+        for (int v = 0; v < 4; ++v) {
+            const int rg = rb + 4 * v;
+            const double y = a[v];
+            const double val = upd ? (2.0 * xo[v] - y) : y;
+            Xn[(int64_t)rg * ld + cg] = val;
+            if (write_mirror) Xn[(int64_t)cg * ld + rg] = val;
+            if (diag && rg == cg && cg < pd.c) {
+                tY += y;
+                tX += val;
             }
         }
+    };
+    if (grid_tile) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int nn = 0; nn < 4; ++nn) emit16(acc[m][nn], wr * 64 + m * 16, wc * 64 + nn * 16, !diag);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            if (j < n_mine) {
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int bb = 0; bb < 2; ++bb)
+                        emit16(acc[2 * (j >> 1) + a][2 * (j & 1) + bb], g_r[j] * 32 + a * 16, g_c[j] * 32 + bb * 16,
+                               !diag || g_r[j] < g_c[j]);
+            }
+        // 32 x 32 blocks wholly in the padding: X' is +0 there, written without reading
+        int k = 0;
+        for (int r = 0; r < 4; ++r)
+            for (int c = 0; c < 4; ++c) {
+                if (I0 + 32 * r < pd.s && J0 + 32 * c < pd.s) continue;
+                if ((k & 3) == wv) {
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int bb = 0; bb < 2; ++bb) {
+                            const int cg = J0 + 32 * c + bb * 16 + l16;
+                            const int rb = I0 + 32 * r + a * 16 + g;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                Xn[(int64_t)(rb + 4 * v) * ld + cg] = 0.0;
+                                if (!diag) Xn[(int64_t)cg * ld + rb + 4 * v] = 0.0;
+                            }
+                        }
+                }
+                ++k;
+            }
     }
     if (diag) {
         block_sum2(tY, tX);
@@ -1095,6 +1211,7 @@ __device__ __forceinline__ void sp2_tile64(const TileDesc td, const PartDesc pd,
     }
 }
 
+template <bool kSkip>
 __global__ __launch_bounds__(kBlock, 2) void k_sp2_step64(const TileDesc *__restrict__ tiles,
                                                        const PartDesc *__restrict__ parts,
                                                        double *__restrict__ buf0, double *__restrict__ buf1,
@@ -1106,7 +1223,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_sp2_step64(const TileDesc *__rest
     const PartDesc pd = parts[td.part];
     const RunState *st = st_all + pd.sys;
     if (st->done || st->phase != phase) return;
-    sp2_tile64(td, pd, st->cur, static_cast<double>(st->alpha), buf0, buf1, diag_partials, lds);
+    sp2_tile64<kSkip>(td, pd, st->cur, static_cast<double>(st->alpha), buf0, buf1, diag_partials, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -2052,8 +2169,8 @@ hipError_t density_typed(const DevicePlan &dp, const gsp2_csr &H, const RunParam
         const bool skip = form == GSP2_KERNEL_T128_SKIP;
         const TileDesc *tl = skip ? dp.tiles_s : dp.tiles;     // the skip form's order: short tiles last
         if (prec == GSP2_PREC_FP64) {
-            record(rec, k_sp2_step64, grid, blk, dp.tiles, dp.parts, dp.buf64[0], dp.buf64[1], dp.state,
-                   dp.diag_partials, phase);
+            record(rec, skip ? k_sp2_step64<true> : k_sp2_step64<false>, grid, blk, tl, dp.parts, dp.buf64[0],
+                   dp.buf64[1], dp.state, dp.diag_partials, phase);
         } else if (prec == GSP2_PREC_FP32) {
             auto k = skip ? k_sp2_step<float, false, true> : k_sp2_step<float, false, false>;
             record(rec, k, grid, blk, tl, dp.parts, b0, b1, (float *)nullptr, (float *)nullptr, dp.state,
