@@ -829,27 +829,33 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // symmetric), as one float4 per lane and row group, for all of the wave's
     // blocks before any store: a wave's loads complete in order behind its
     // earlier stores, so reads between stores would wait for them.
+    // (Split operands, whose epilogue holds more registers, read them one
+    // block at a time, just before that block's stores.)
     const bool need_xo = kExactDiag || alpha > 0.0f;
-    float4 xo4[4][4];                           // [block slot][row group]
+    constexpr bool kAllAhead = !kSplit;
+    float4 xo4[kAllAhead ? 4 : 1][4];           // [block slot][row group]
     auto load_xo = [&](int slot, int ro, int co) __attribute__((always_inline)) {
         const int cg = J0 + co + l32;
+        const int sl = kAllAhead ? slot : 0;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int rg0 = I0 + ro + g * 8 + kh * 4;
-            xo4[slot][g] = need_xo ? *reinterpret_cast<const float4 *>(X + (int64_t)cg * ld + rg0)
-                                   : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            xo4[sl][g] = need_xo ? *reinterpret_cast<const float4 *>(X + (int64_t)cg * ld + rg0)
+                                 : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         }
     };
     // one 32 x 32 block of the tile (its first row and column within the
     // tile: ro, co) from its accumulator, written at its place and, with
     // write_mirror, transposed at the mirrored place
     auto emit_block = [&](const v16f &a, int slot, int ro, int co, bool write_mirror) __attribute__((always_inline)) {
+        if constexpr (!kAllAhead) load_xo(slot, ro, co);
+        const int sl = kAllAhead ? slot : 0;
         const int cg = J0 + co + l32;
         const float dc = kExactDiag ? X[(int64_t)cg * (ld + 1)] : 0.0f;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int rg0 = I0 + ro + g * 8 + kh * 4;
-            const float xov[4] = {xo4[slot][g].x, xo4[slot][g].y, xo4[slot][g].z, xo4[slot][g].w};
+            const float xov[4] = {xo4[sl][g].x, xo4[sl][g].y, xo4[sl][g].z, xo4[sl][g].w};
             float xn[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -919,19 +925,23 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
         }
     };
     if (grid_tile) {
+        if constexpr (kAllAhead) {
 #pragma unroll
-        for (int m = 0; m < 2; ++m)
+            for (int m = 0; m < 2; ++m)
 #pragma unroll
-            for (int nn = 0; nn < 2; ++nn) load_xo(2 * m + nn, wr * 64 + m * 32, wc * 64 + nn * 32);
+                for (int nn = 0; nn < 2; ++nn) load_xo(2 * m + nn, wr * 64 + m * 32, wc * 64 + nn * 32);
+        }
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
             for (int nn = 0; nn < 2; ++nn)
                 emit_block(acc[m][nn], 2 * m + nn, wr * 64 + m * 32, wc * 64 + nn * 32, !diag);
     } else {
+        if constexpr (kAllAhead) {
 #pragma unroll
-        for (int j = 0; j < 3; ++j)
-            if (j < n_mine) load_xo(j, 32 * g_r[j], 32 * g_c[j]);
+            for (int j = 0; j < 3; ++j)
+                if (j < n_mine) load_xo(j, 32 * g_r[j], 32 * g_c[j]);
+        }
 #pragma unroll
         for (int j = 0; j < 3; ++j)
             if (j < n_mine) emit_block(acc[j >> 1][j & 1], j, 32 * g_r[j], 32 * g_c[j], !diag || g_r[j] < g_c[j]);
