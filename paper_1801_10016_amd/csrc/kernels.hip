@@ -542,12 +542,16 @@ __device__ __forceinline__ v16f mfma_chunk_q(const uint4 &a, const uint4 &b, v16
 // contiguous), for ti <= tj only; the eq. (2) update X' = Y or 2X - Y, in
 // FP32 against the FP32 master X, is fused into the epilogue and written to
 // the other buffer at (I,J) and, mirrored, at (J,I), so every iterate stays
-// exactly symmetric.  With 16-bit operands the epilogue also writes the
-// rounded copy of X' that the next product reads.  Diagonal tiles emit FP64
-// partial sums of Y and X' over the part's core diagonal.
+// symmetric: exactly, except with split FP16 operands, whose two cross terms
+// a diagonal tile sums in opposite orders for Y[i][j] and Y[j][i] where it
+// forms both (the two agree to FP32 rounding, and X_old read at the mirrored
+// position is the other rounding).  With 16-bit operands the epilogue also
+// writes the rounded copy of X' that the next product reads.  Diagonal tiles
+// emit FP64 partial sums of Y and X' over the part's core diagonal.
 //
 // 256 threads = 4 waves in a 2x2 grid, each wave a 64x64 sub-tile as 2x2
-// blocks of 32x32 MFMA output.  Operands are staged through LDS in K chunks,
+// blocks of 32x32 MFMA output (the skip form deals the blocks of diagonal and
+// edge tiles to the waves instead).  Operands are staged through LDS in K chunks,
 // two LDS buffers and two register sets deep.  Within a
 // chunk, lane half h of an MFMA operand takes the k values of its half of
 // every 16-byte group, for A and B alike, so each lane reads whole 16-byte
