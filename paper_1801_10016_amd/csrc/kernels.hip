@@ -1339,22 +1339,26 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
     // earlier chunk; a half-empty panel repeats its first 128 rows in passes
     // 4 to 7 (in bounds; those LDS rows are not read).  Two register sets:
     // chunk c + 2 is loaded while chunk c + 1 waits to be stored.
-#define GSP2W_LOAD(S, ra, rb, kb)                                                                  \
+    // SHR: a diagonal tile with plain operands, whose B panel is its A panel:
+    // the B rows are neither loaded nor stored, and B fragments are read from
+    // the A region (half the panel requests to L2 and the LDS stores)
+#define GSP2W_LOAD(S, ra, rb, kb, SHR)                                                             \
     do {                                                                                           \
         _Pragma("unroll") for (int p_ = 0; p_ < 8; ++p_) {                                         \
             pa[S][p_] = __builtin_bit_cast(                                                        \
                 uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, offA, passA[p_] + (kb), 0));      \
-            pb[S][p_] = __builtin_bit_cast(                                                        \
-                uint4, __builtin_amdgcn_raw_buffer_load_b128(rb, offB, passB[p_] + (kb), 0));      \
+            if constexpr (!(SHR))                                                                  \
+                pb[S][p_] = __builtin_bit_cast(                                                    \
+                    uint4, __builtin_amdgcn_raw_buffer_load_b128(rb, offB, passB[p_] + (kb), 0));  \
         }                                                                                          \
     } while (0)
-#define GSP2W_STORE(b, S)                                                                          \
+#define GSP2W_STORE(b, S, SHR)                                                                     \
     do {                                                                                           \
         uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;                                                \
         uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                                \
         _Pragma("unroll") for (int p_ = 0; p_ < 8; ++p_) {                                         \
             As_[p_ * 32 * kLdsRow] = pa[S][p_];                                                    \
-            Bs_[p_ * 32 * kLdsRow] = pb[S][p_];                                                    \
+            if constexpr (!(SHR)) Bs_[p_ * 32 * kLdsRow] = pb[S][p_];                              \
         }                                                                                          \
     } while (0)
 
@@ -1370,9 +1374,9 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
     // last fragments of this one, so step 3's MFMAs cover the reads of the
     // next chunk's step-0 fragments.
     uint4 fa[2][4], fb[2][4];
-    auto frags = [&](int b, int q, uint4 *fa_, uint4 *fb_) {
+    auto frags = [&](int b, int q, uint4 *fa_, uint4 *fb_, auto shr) __attribute__((always_inline)) {
         const uint4 *Asb = lds(b, 0);
-        const uint4 *Bsb = lds(b, 1);
+        const uint4 *Bsb = lds(b, decltype(shr)::value ? 0 : 1);
         const int w = 2 * q + kh;               // k = 16 q + 8 kh + e
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
@@ -1381,16 +1385,17 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
         }
     };
     auto compute = [&](int buf, uint4 (&sa)[8], uint4 (&sb)[8], __amdgpu_buffer_rsrc_t ra,
-                       __amdgpu_buffer_rsrc_t rb, uint32_t kb) {
+                       __amdgpu_buffer_rsrc_t rb, uint32_t kb, auto shr) __attribute__((always_inline)) {
+        constexpr bool kShr = decltype(shr)::value;
         uint4 *As_ = lds(buf ^ 1, 0) + lr * kLdsRow + lw;
         uint4 *Bs_ = lds(buf ^ 1, 1) + lr * kLdsRow + lw;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             if (q + 1 < 4) {
-                frags(buf, q + 1, fa[(q + 1) & 1], fb[(q + 1) & 1]);
+                frags(buf, q + 1, fa[(q + 1) & 1], fb[(q + 1) & 1], shr);
             } else {
                 __syncthreads();
-                frags(buf ^ 1, 0, fa[0], fb[0]);
+                frags(buf ^ 1, 0, fa[0], fb[0], shr);
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m)
@@ -1403,11 +1408,12 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 #pragma unroll
             for (int p = 0; p < np; ++p) {
                 As_[(p0 + p) * 32 * kLdsRow] = sa[p0 + p];
-                Bs_[(p0 + p) * 32 * kLdsRow] = sb[p0 + p];
+                if constexpr (!kShr) Bs_[(p0 + p) * 32 * kLdsRow] = sb[p0 + p];
                 sa[p0 + p] = __builtin_bit_cast(
                     uint4, __builtin_amdgcn_raw_buffer_load_b128(ra, offA, passA[p0 + p] + kb, 0));
-                sb[p0 + p] = __builtin_bit_cast(
-                    uint4, __builtin_amdgcn_raw_buffer_load_b128(rb, offB, passB[p0 + p] + kb, 0));
+                if constexpr (!kShr)
+                    sb[p0 + p] = __builtin_bit_cast(
+                        uint4, __builtin_amdgcn_raw_buffer_load_b128(rb, offB, passB[p0 + p] + kb, 0));
             }
             // the compiler's MFMA / LDS interleave for one wave per SIMD (3% faster
             // than placing one LDS access after each of the first MFMAs, measured)
@@ -1424,39 +1430,42 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
     // occupies, which no wave reads during that step, and its last step
     // reads fragments that are not used.  The barriers at entry and exit
     // keep LDS reuse (a second pass, the epilogue) clear of these reads.
-    auto run = [&](int c0, int c1) {
+    auto run = [&](int c0, int c1, auto shr) __attribute__((always_inline)) {
+        constexpr bool kShr = decltype(shr)::value;
         __amdgpu_buffer_rsrc_t ra, rb;
         uint32_t kb;
         __syncthreads();
         GSP2W_SRC(c0, ra, rb, kb);
-        GSP2W_LOAD(0, ra, rb, kb);
-        GSP2W_STORE(0, 0);
+        GSP2W_LOAD(0, ra, rb, kb, kShr);
+        GSP2W_STORE(0, 0, kShr);
         GSP2W_SRC(c0 + 1, ra, rb, kb);
-        GSP2W_LOAD(1, ra, rb, kb);
+        GSP2W_LOAD(1, ra, rb, kb, kShr);
         GSP2W_SRC(min(c0 + 2, c1 - 1), ra, rb, kb);
-        GSP2W_LOAD(0, ra, rb, kb);
+        GSP2W_LOAD(0, ra, rb, kb, kShr);
         __syncthreads();
-        frags(0, 0, fa[0], fb[0]);
+        frags(0, 0, fa[0], fb[0], shr);
         for (int kc = c0; kc < c1; kc += 2) {
             // past the end the last chunk is loaded again, so that every
             // load is unconditional and the waits before the stores count
             // exactly the loads issued after them
             GSP2W_SRC(min(kc + 3, c1 - 1), ra, rb, kb);
-            compute(0, pa[1], pb[1], ra, rb, kb);
+            compute(0, pa[1], pb[1], ra, rb, kb, shr);
             GSP2W_SRC(min(kc + 4, c1 - 1), ra, rb, kb);
-            compute(1, pa[0], pb[0], ra, rb, kb);
+            compute(1, pa[0], pb[0], ra, rb, kb, shr);
         }
         __syncthreads();
     };
+    const std::false_type own_b;
     if constexpr (kSplit) {
-        run(0, 2 * nk);                         // cross terms H L and L H
+        run(0, 2 * nk, own_b);                  // cross terms H L and L H
 #pragma unroll
         for (int m = 0; m < 4; ++m)
 #pragma unroll
             for (int nn = 0; nn < 4; ++nn) acc[m][nn] *= 0x1p-11f;
-        run(2 * nk, 3 * nk);                    // H H
+        run(2 * nk, 3 * nk, own_b);             // H H
     } else {
-        run(0, nk);
+        if (diag) run(0, nk, std::true_type{});
+        else run(0, nk, own_b);
     }
 #undef GSP2W_SRC
 #undef GSP2W_LOAD
