@@ -656,7 +656,8 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // K chunks.  Plain: the nk chunks of X[I,:] X[J,:].  Split (X = H + 2^-11 L):
     // nk chunks of H[I,:] L[J,:], nk of L[I,:] H[J,:], the accumulator scaled by
     // 2^-11 (exact), then nk of H[I,:] H[J,:].  Both panels are staged for
-    // every chunk, diagonal tiles included.
+    // every chunk, except in a diagonal tile of the one-operand forms, where
+    // the B panel is the A panel.
     //
     // Operands arrive two chunks ahead in two register sets: chunk c + 1 is
     // stored into LDS after the MFMAs of chunk c, from the set loaded before
@@ -683,26 +684,33 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
             kb_ = (int64_t)(c_ - seg_ * nk) * 128;                                                 \
         }                                                                                          \
     } while (0)
-#define GSP2_LD(S, c)                                                                              \
+    // SHR: a diagonal tile with one operand (not the split or adjoint forms),
+    // whose B panel is its A panel: the B rows are neither loaded nor stored,
+    // and B fragments are read from the A region
+#define GSP2_LD(S, c, SHR)                                                                         \
     do {                                                                                           \
         GSP2_SRC(c);                                                                               \
         pa##S##0 = *reinterpret_cast<const uint4 *>(Ap_ + kb_);                                    \
         pa##S##1 = *reinterpret_cast<const uint4 *>(Ap_ + pass_bytes + kb_);                       \
         pa##S##2 = *reinterpret_cast<const uint4 *>(Ap_ + 2 * pass_bytes + kb_);                   \
         pa##S##3 = *reinterpret_cast<const uint4 *>(Ap_ + 3 * pass_bytes + kb_);                   \
-        pb##S##0 = *reinterpret_cast<const uint4 *>(Bp_ + kb_);                                    \
-        pb##S##1 = *reinterpret_cast<const uint4 *>(Bp_ + pass_bytes + kb_);                       \
-        pb##S##2 = *reinterpret_cast<const uint4 *>(Bp_ + 2 * pass_bytes + kb_);                   \
-        pb##S##3 = *reinterpret_cast<const uint4 *>(Bp_ + 3 * pass_bytes + kb_);                   \
+        if constexpr (!(SHR)) {                                                                    \
+            pb##S##0 = *reinterpret_cast<const uint4 *>(Bp_ + kb_);                                \
+            pb##S##1 = *reinterpret_cast<const uint4 *>(Bp_ + pass_bytes + kb_);                   \
+            pb##S##2 = *reinterpret_cast<const uint4 *>(Bp_ + 2 * pass_bytes + kb_);               \
+            pb##S##3 = *reinterpret_cast<const uint4 *>(Bp_ + 3 * pass_bytes + kb_);               \
+        }                                                                                          \
     } while (0)
-#define GSP2_ST(b, S)                                                                              \
+#define GSP2_ST(b, S, SHR)                                                                         \
     do {                                                                                           \
         uint4 *As_ = lds(b, 0) + lr * kLdsRow + lw;                                                \
-        uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                                \
         As_[0] = pa##S##0; As_[32 * kLdsRow] = pa##S##1;                                           \
         As_[64 * kLdsRow] = pa##S##2; As_[96 * kLdsRow] = pa##S##3;                                \
-        Bs_[0] = pb##S##0; Bs_[32 * kLdsRow] = pb##S##1;                                           \
-        Bs_[64 * kLdsRow] = pb##S##2; Bs_[96 * kLdsRow] = pb##S##3;                                \
+        if constexpr (!(SHR)) {                                                                    \
+            uint4 *Bs_ = lds(b, 1) + lr * kLdsRow + lw;                                            \
+            Bs_[0] = pb##S##0; Bs_[32 * kLdsRow] = pb##S##1;                                       \
+            Bs_[64 * kLdsRow] = pb##S##2; Bs_[96 * kLdsRow] = pb##S##3;                            \
+        }                                                                                          \
     } while (0)
     // kSkip: work the matrix cores can leave out, exactly (wave-uniform):
     //  * a 32-row (or 32-column) block that starts at or beyond s lies in the
@@ -734,11 +742,11 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     }
     // kind 0: the wave's 2 x 2 blocks of the grid; 2: none; 3 + M: the wave's
     // M dealt blocks (slot j in acc[j / 2][j % 2])
-    auto compute_kind = [&](int buf, auto kind) __attribute__((always_inline)) {
+    auto compute_kind = [&](int buf, auto kind, auto shr) __attribute__((always_inline)) {
         constexpr int K = decltype(kind)::value;
         if constexpr (K == 2) return;
         const uint4 *Asb = lds(buf, 0);
-        const uint4 *Bsb = lds(buf, 1);
+        const uint4 *Bsb = lds(buf, decltype(shr)::value ? 0 : 1);
         // interleave the LDS fragment reads with the MFMAs (3.5% faster FP32
         // products than the default schedule, measured)
         __builtin_amdgcn_iglp_opt(1);
@@ -771,10 +779,11 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
             }
         }
     };
-    auto kloop = [&](auto kind) __attribute__((always_inline)) {
-        GSP2_LD(0, 0);
-        GSP2_ST(0, 0);
-        GSP2_LD(1, min(1, nc - 1));
+    auto kloop = [&](auto kind, auto shr) __attribute__((always_inline)) {
+        constexpr bool kShr = decltype(shr)::value;
+        GSP2_LD(0, 0, kShr);
+        GSP2_ST(0, 0, kShr);
+        GSP2_LD(1, min(1, nc - 1), kShr);
         __syncthreads();
         int kc = 0;
         for (; kc + 1 < nc; kc += 2) {
@@ -786,13 +795,13 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
                         for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
                 }
             }
-            GSP2_LD(0, min(kc + 2, nc - 1));
-            compute_kind(0, kind);
-            GSP2_ST(1, 1);
+            GSP2_LD(0, min(kc + 2, nc - 1), kShr);
+            compute_kind(0, kind, shr);
+            GSP2_ST(1, 1, kShr);
             __syncthreads();
-            GSP2_LD(1, min(kc + 3, nc - 1));
-            compute_kind(1, kind);
-            GSP2_ST(0, 0);
+            GSP2_LD(1, min(kc + 3, nc - 1), kShr);
+            compute_kind(1, kind, shr);
+            GSP2_ST(0, 0, kShr);
             __syncthreads();
         }
         if (kc < nc) {                          // an odd count's last chunk, stored in buffer 0
@@ -804,19 +813,30 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
                         for (int nn = 0; nn < 2; ++nn) acc[m][nn] *= 0x1p-11f;
                 }
             }
-            compute_kind(0, kind);
+            compute_kind(0, kind, shr);
             __syncthreads();                    // as after a pair: LDS is free again when the loop ends
         }
     };
-    if constexpr (!kSkip) {
-        kloop(std::integral_constant<int, 0>{});
-    } else {
-        if (grid_tile) kloop(std::integral_constant<int, 0>{});
-        else if (n_mine == 0) kloop(std::integral_constant<int, 2>{});
-        else if (n_mine == 1) kloop(std::integral_constant<int, 4>{});
-        else if (n_mine == 2) kloop(std::integral_constant<int, 5>{});
-        else kloop(std::integral_constant<int, 6>{});
-    }
+    auto kloops = [&](auto shr) __attribute__((always_inline)) {
+        if constexpr (!kSkip) {
+            kloop(std::integral_constant<int, 0>{}, shr);
+        } else {
+            // (a diagonal tile is never a grid tile here)
+            if constexpr (!decltype(shr)::value) {
+                if (grid_tile) {
+                    kloop(std::integral_constant<int, 0>{}, shr);
+                    return;
+                }
+            }
+            if (n_mine == 0) kloop(std::integral_constant<int, 2>{}, shr);
+            else if (n_mine == 1) kloop(std::integral_constant<int, 4>{}, shr);
+            else if (n_mine == 2) kloop(std::integral_constant<int, 5>{}, shr);
+            else kloop(std::integral_constant<int, 6>{}, shr);
+        }
+    };
+    if constexpr (kTwo) kloops(std::false_type{});
+    else if (diag) kloops(std::true_type{});
+    else kloops(std::false_type{});
 #undef GSP2_SRC
 #undef GSP2_LD
 #undef GSP2_ST
@@ -1321,7 +1341,8 @@ __device__ __forceinline__ void sp2_tile_wide(const TileDesc td, const PartDesc 
 
     // chunks as in sp2_tile: plain nk of X X; split nk of H L, nk of L H,
     // the scale by 2^-11, nk of H H.  Both panels are staged for every
-    // chunk, diagonal tiles included.
+    // chunk, except in a diagonal tile with plain operands, where the B panel
+    // is the A panel.
     const int nk = ld / kK;
     uint4 pa[2][8], pb[2][8];
 #define GSP2W_SRC(c, ra, rb, kb)                                                                   \
