@@ -656,8 +656,8 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
     // K chunks.  Plain: the nk chunks of X[I,:] X[J,:].  Split (X = H + 2^-11 L):
     // nk chunks of H[I,:] L[J,:], nk of L[I,:] H[J,:], the accumulator scaled by
     // 2^-11 (exact), then nk of H[I,:] H[J,:].  Both panels are staged for
-    // every chunk, except in a diagonal tile of the one-operand forms, where
-    // the B panel is the A panel.
+    // every chunk, except in a diagonal tile of the one-operand skip form,
+    // where the B panel is the A panel.
     //
     // Operands arrive two chunks ahead in two register sets: chunk c + 1 is
     // stored into LDS after the MFMAs of chunk c, from the set loaded before
@@ -684,8 +684,8 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
             kb_ = (int64_t)(c_ - seg_ * nk) * 128;                                                 \
         }                                                                                          \
     } while (0)
-    // SHR: a diagonal tile with one operand (not the split or adjoint forms),
-    // whose B panel is its A panel: the B rows are neither loaded nor stored,
+    // SHR: a diagonal tile of the skip form with one operand (not the split or
+    // adjoint forms), whose B panel is its A panel: the B rows are neither loaded nor stored,
     // and B fragments are read from the A region
 #define GSP2_LD(S, c, SHR)                                                                         \
     do {                                                                                           \
@@ -834,7 +834,12 @@ __device__ __forceinline__ void sp2_tile(const TileDesc td, const PartDesc pd, i
             else kloop(std::integral_constant<int, 6>{}, shr);
         }
     };
-    if constexpr (kTwo) kloops(std::false_type{});
+    // Only the skip form shares the panel: it runs its diagonal tiles after
+    // the full ones.  In the plain form's list, tiles of one length keep the
+    // workgroups in step; shorter diagonal tiles among them spread the
+    // resident tiles over more panels, and the HBM reads grew by half
+    // (measured), more than the loads saved.
+    if constexpr (kTwo || !kSkip) kloops(std::false_type{});
     else if (diag) kloops(std::true_type{});
     else kloops(std::false_type{});
 #undef GSP2_SRC
