@@ -249,7 +249,9 @@ def test_skip_form_gives_the_same_bits(precision, n_mol, seed, n_parts, tau):
     # formed by another wave is formed alike, so the two 128-tile forms give
     # the same P, branch sequence and traces bit for bit (8 molecules in 8
     # parts: 6-orbital cores padded to 128, where all but one 32-row block is
-    # padding).  Split FP16 is the exception: a block above the diagonal sums
+    # padding).  The skip form's diagonal tiles also stage only their A panel
+    # and read B fragments from it, while the plain form stages both, so the
+    # bit equality covers that path too.  Split FP16 is the exception: a block above the diagonal sums
     # its two cross terms in the other order than the block below it, so the
     # two forms agree to FP32 rounding.
     from tests._gpu import rel_fro, run_gsp2
